@@ -1,0 +1,426 @@
+"""Pins for the FP64 CPU oracle against what the paper and mathematics fix.
+
+None of these compare the oracle with itself: each checks it against an
+independent library routine (mpmath, scipy), a closed form, an invariant, a
+value the paper prints, or brute force on tiny inputs.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.integrate as si
+import scipy.special as ss
+
+import oracle as O
+from paper_2411_03418_amd import synth
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_constants.json")))
+
+
+def _mp_K(x, y):
+    mp = pytest.importorskip("mpmath")
+    mp.mp.dps = 40
+    z = mp.mpc(x, y)
+    return float(mp.re(mp.exp(-z * z) * mp.erfc(-1j * z)))
+
+
+# ---------------------------------------------------------------- K(x, y)
+
+def test_voigt_matches_arbitrary_precision_faddeeva():
+    """K = Re[exp(-z^2) erfc(-iz)], evaluated at 40 digits by mpmath, over every
+    branch of the oracle: |z|>=7 series, y>=0.5 continued fraction, y<0.5 Taylor."""
+    xs = [0.0, 0.1, 0.7, 1.3, 2.2, 3.1, 4.4, 5.5, 6.2, 6.9, 7.0, 7.3, 9.5, 15.0, 40.0, 1e3, 1e6, 1e8]
+    ys = [1e-4, 1e-3, 0.02, 0.1, 0.3, 0.49, 0.5, 0.8, 1.7, 4.0, 6.9, 12.0, 1e2, 1e3, 5e3]
+    worst = 0.0
+    for x in xs:
+        for y in ys:
+            ref = _mp_K(x, y)
+            v = O.voigt_K(x, y)[()]
+            worst = max(worst, abs(v - ref) / ref)
+    assert worst < 1e-9, worst
+
+
+def test_voigt_tiny_y_is_gaussian_plus_lorentz_wing():
+    # y -> 0: K -> exp(-x^2) (Doppler limit, Eq.(5) exactly)
+    for x in [0.0, 0.5, 1.0, 2.0, 3.0]:
+        assert abs(O.voigt_K(x, 0.0)[()] - math.exp(-x * x)) <= 1e-15 * math.exp(-x * x) + 1e-300
+        # first order in y: K = exp(-x^2) + y (2/sqrt(pi)) (2 x D(x) - 1) + O(y^2)
+        y = 1e-7
+        first = math.exp(-x * x) + y * 2 / math.sqrt(math.pi) * (2 * x * ss.dawsn(x) - 1)
+        assert abs(O.voigt_K(x, y)[()] / first - 1.0) < 1e-12
+
+
+def test_voigt_center_is_erfcx():
+    ys = np.geomspace(1e-4, 1e3, 40)
+    v = O.voigt_K(np.zeros_like(ys), ys)
+    ref = ss.erfcx(ys)
+    assert np.max(np.abs(v - ref) / ref) < 1e-10
+
+
+def test_voigt_symmetric_in_x():
+    x = np.linspace(0.01, 30, 97)
+    for y in [1e-3, 0.3, 2.0, 50.0]:
+        assert np.array_equal(O.voigt_K(x, y), O.voigt_K(-x, y))
+
+
+def test_voigt_normalisation_integral():
+    """int K dx = sqrt(pi), i.e. the Voigt profile of Eq.(7) integrates to one."""
+    for y in [1e-3, 0.05, 0.4, 0.6, 3.0, 30.0]:
+        f = lambda x: O.voigt_K(x, y)[()]
+        pts = [0.0, 0.5, 1, 2, 3, 5, 6.9, 7.1, 20, 100]
+        tot = 0.0
+        for a, b in zip(pts[:-1], pts[1:]):
+            tot += si.quad(f, a, b, epsabs=0, epsrel=1e-12, limit=400)[0]
+        # analytic tail beyond 100: K ~ y/(sqrt(pi) x^2) (1 + 3/(2x^2))
+        tail = si.quad(f, 100, 1e6, epsabs=0, epsrel=1e-12, limit=400)[0] + y / (math.sqrt(math.pi) * 1e6)
+        tot = 2 * (tot + tail)
+        assert abs(tot - math.sqrt(math.pi)) < 2e-9 + 1e-6 * y, (y, tot)
+
+
+def test_voigt_lorentz_limit_large_y():
+    """y >> 1: K -> y/(sqrt(pi)(x^2+y^2)), the Lorentz shape of Eq.(4)."""
+    for y in [50.0, 300.0, 3000.0]:
+        x = np.linspace(0, 5 * y, 11)
+        K = O.voigt_K(x, y)
+        L = y / (math.sqrt(math.pi) * (x * x + y * y))
+        assert np.max(np.abs(K / L - 1)) < 1.0 / y ** 2
+
+
+def test_voigt_paper_large_x_asymptotic():
+    """Appendix C: f_V ~ f_L (1 + 3/(2x^2)); the next term is 15/(4x^4)."""
+    y = 1e-3
+    for x in [15.0, 30.0, 100.0]:
+        K = O.voigt_K(x, y)[()]
+        L = y / (math.sqrt(math.pi) * (x * x + y * y))
+        ratio = K / L
+        assert abs(ratio - (1 + 3 / (2 * x * x))) < 1.2 * 15 / (4 * x ** 4), (x, ratio)
+
+
+def test_paper_taylor_moments():
+    g = GOLD["gauss_moments"]
+    m0 = si.quad(lambda t: math.exp(-t * t), -np.inf, np.inf)[0]
+    m1 = si.quad(lambda t: t * math.exp(-t * t), -np.inf, np.inf)[0]
+    m2 = 0.5 * si.quad(lambda t: t * t * math.exp(-t * t), -np.inf, np.inf)[0]
+    assert abs(m0 - g["m0"]) < 1e-12 and abs(m1 - g["m1"]) < 1e-12 and abs(m2 - g["m2_with_half"]) < 1e-12
+
+
+def test_voigt_branch_continuity():
+    """The oracle switches method at |z| = 7 and y = 0.5; both sides agree."""
+    eps = 1e-9
+    for th in np.linspace(0.01, 1.55, 12):
+        x, y = 7 * math.cos(th), 7 * math.sin(th)
+        a = O.voigt_K(x * (1 - eps), y * (1 - eps))[()]
+        b = O.voigt_K(x * (1 + eps), y * (1 + eps))[()]
+        assert abs(a - b) / a < 1e-8
+    for x in [0.0, 1.0, 3.0, 6.0]:
+        a = O.voigt_K(x, 0.5 - 1e-12)[()]
+        b = O.voigt_K(x, 0.5)[()]
+        assert abs(a - b) / a < 1e-10
+
+
+def test_dawson_matches_scipy():
+    x = np.concatenate([np.linspace(-3, 3, 61), np.geomspace(0.01, 50, 60)])
+    v = np.array([O.dawson(t) for t in x])
+    ref = ss.dawsn(x)
+    nz = ref != 0
+    assert np.max(np.abs(v[nz] - ref[nz]) / np.abs(ref[nz])) < 1e-13
+
+
+# ---------------------------------------------------------------- chi, shapes
+
+def test_tonkov_chi_printed_values():
+    pieces = GOLD["tonkov"]["pieces"]
+    a1, b1 = pieces[0][2], pieces[0][3]
+    a2, b2 = pieces[1][2], pieces[1][3]
+    a3, b3 = pieces[2][2], pieces[2][3]
+    assert O.chi(1, 2.999999) == 1.0
+    assert O.chi(1, 0.0) == 1.0
+    assert abs(O.chi(1, 3.0) - a1 * math.exp(-b1 * 3)) < 1e-15
+    assert abs(O.chi(1, 150.0) - a1 * math.exp(-b1 * 150)) < 1e-15
+    assert abs(O.chi(1, 150.0001) - a2 * math.exp(-b2 * 150.0001)) < 1e-15
+    assert abs(O.chi(1, 300.0) - a2 * math.exp(-b2 * 300)) < 1e-15
+    assert abs(O.chi(1, 300.5) - a3 * math.exp(-b3 * 300.5)) < 1e-15
+    assert abs(O.chi(1, 125.0) - 0.0370924) < 5e-8
+    assert O.chi(0, 100.0) == 1.0
+
+
+def test_shapes_normalised_and_symmetric():
+    for kind in (0, 1, 2):
+        gL, aD = 0.07, 0.003
+        f = lambda d: O.shape(kind, d, gL, aD)
+        assert f(0.013) == f(-0.013)
+        if kind == 1:
+            area = 2 * si.quad(f, 0, np.inf, limit=400)[0]
+        else:
+            area = 2 * (si.quad(f, 0, 1, limit=400, epsrel=1e-12)[0] + si.quad(f, 1, np.inf, limit=400)[0])
+        assert abs(area - 1) < 1e-7, (kind, area)
+    # Doppler shape of Eq.(5): half maximum at d = alpha_D
+    aD = 0.002
+    assert abs(O.shape(2, aD, 0.0, aD) / O.shape(2, 0.0, 0.0, aD) - 0.5) < 1e-14
+    # Lorentz shape of Eq.(4): half maximum at d = gamma_L
+    assert abs(O.shape(1, 0.03, 0.03, 0.0) / O.shape(1, 0.0, 0.03, 0.0) - 0.5) < 1e-14
+
+
+def test_voigt_shape_reduces_to_lorentz_without_doppler():
+    # alpha_D -> 0 (nu0 -> 0): the Voigt profile becomes Eq.(4)
+    for d in [0.0, 0.1, 3.0]:
+        v = O.shape(0, d, 0.05, 1e-9)
+        l = O.shape(1, d, 0.05, 0.0)
+        assert abs(v / l - 1) < 1e-9
+
+
+# ---------------------------------------------------------------- line state
+
+def _lines1(**kw):
+    L = synth.make_lines(1, 1000, 1001, 3)
+    for k, v in kw.items():
+        getattr(L, k)[:] = v
+    return L
+
+
+def test_line_state_reference_conditions():
+    L = _lines1(nu0=1234.5, S296=3e-21, gamma_air=0.071, gamma_self=0.09, E_lower=987.0, delta_air=-0.004)
+    st = O.line_state(L, (1.0, 296.0, 0.0, 0.0), 0)
+    assert abs(st["S"] / np.float32(3e-21) - 1) < 1e-15
+    assert abs(st["gamma_L"] - np.float32(0.071)) < 1e-16
+    assert abs(st["nu_t"] - (1234.5 + np.float32(-0.004))) < 1e-12
+    # all-self broadening uses gamma_self
+    st = O.line_state(L, (2.0, 296.0, 2.0, 0.0), 0)
+    assert abs(st["gamma_L"] - 2 * np.float32(0.09)) < 1e-15
+
+
+def test_doppler_width_textbook_constant():
+    # alpha_D = 3.581e-7 nu0 sqrt(T/M) (HWHM, published rule of thumb)
+    L = _lines1(nu0=2000.0)
+    st = O.line_state(L, (1.0, 250.0, 1.0, 0.0), 0)
+    assert abs(st["alpha_D"] / (3.581163e-7 * 2000 * math.sqrt(250 / 44.0)) - 1) < 1e-6
+
+
+def test_intensity_temperature_invariants():
+    # lines differing only in E'' keep the Boltzmann ratio exp(-c2 dE (1/T - 1/296))
+    c2 = 1.4387769
+    L = synth.make_lines(2, 3000, 3000.001, 3)
+    L.nu0[:] = 40000.0
+    L.S296[:] = 1e-20
+    L.E_lower[:] = [0.0, 1500.0]
+    for T in [150.0, 500.0, 740.0]:
+        a = O.line_state(L, (1.0, T, 1.0, 0.0), 0)["S"]
+        b = O.line_state(L, (1.0, T, 1.0, 0.0), 1)["S"]
+        assert abs(b / a / math.exp(-c2 * 1500 * (1 / T - 1 / 296.0)) - 1) < 1e-6
+        # E''=0, nu large: stimulated emission ~1, so S(T)/S296 = Q(296)/Q(T) = 296/T
+        assert abs(a / float(np.float32(1e-20)) * T / 296.0 - 1) < 1e-12
+    # caller-supplied partition ratio
+    a = O.line_state(L, (1.0, 400.0, 1.0, 0.5), 0)["S"]
+    b = O.line_state(L, (1.0, 400.0, 1.0, 0.0), 0)["S"]
+    assert abs(a / b - 0.5 / (296 / 400.0)) < 1e-12
+
+
+def test_number_density_loschmidt():
+    # n(273.15 K, 1 atm) = Loschmidt constant 2.686780111e19 cm^-3 (CODATA 2018)
+    assert abs(O.number_density((1.0, 273.15, 1.0, 0.0)) / 2.686780111e19 - 1) < 1e-9
+
+
+# ---------------------------------------------------------------- sums
+
+def _one_line(nu0, gamma, p=1.0, T=296.0, delta=0.0, S=1e-20):
+    L = synth.make_lines(1, 0, 1, 7)
+    L.nu0[:] = nu0
+    L.gamma_air[:] = gamma
+    L.gamma_self[:] = gamma
+    L.S296[:] = S
+    L.E_lower[:] = 0.0
+    L.delta_air[:] = delta
+    return L, (p, T, p, 0.0)
+
+
+def test_lorentz_line_area_closed_form():
+    """Single Lorentz line: sum_m sigma_m h0 -> S (2/pi) arctan(c/gamma)."""
+    L, lay = _one_line(1000.0, 0.075)
+    S = O.line_state(L, lay, 0)["S"]
+    c = 25.0
+    req = dict(nu_begin=974.0, nu_end=1026.0, cutoff=c, shape=1)
+    nodes = np.arange(int(974 * 2048), int(1026 * 2048) + 1)
+    d = O.direct(L, lay, nodes, **req)
+    g = O.grid(L, lay, **req)
+    exact = S * 2 / math.pi * math.atan(c / 0.075)
+    assert abs(d.sum() / 2048 / exact - 1) < 1e-7
+    assert abs(g.sum() / 2048 / exact - 1) < 2e-6
+    assert abs(exact / S - 0.99809015) < 1e-8
+
+
+def _grid_vs_direct(L, lay, **req):
+    g = O.grid(L, lay, **req)
+    nodes = np.arange(int(round(req["nu_begin"] * 2048)), int(round(req["nu_end"] * 2048)) + 1)
+    d = O.direct(L, lay, nodes, **req)
+    m = d >= 1e-8 * d.max()
+    return np.max(np.abs(g[m] - d[m]) / d[m])
+
+
+@pytest.mark.parametrize("case", [
+    dict(nu0=1005.0, gamma=0.075),                     # centre on a node
+    dict(nu0=1005.00013, gamma=0.075),                 # off node
+    dict(nu0=1005.3, gamma=0.075, chi=1, c=125.0),     # chi breakpoint inside range
+    dict(nu0=1002.1234, gamma=0.3, c=4.0, chi=1),      # cut-off and chi break in range
+    dict(nu0=1007.7, gamma=0.09, p=10.0),              # broad line, start level > 0
+    dict(nu0=1003.0, gamma=0.09, p=30.0, c=125.0, chi=1, nb=900.0, ne=1100.0),
+    dict(nu0=1015.0, gamma=0.06, p=0.01),              # centre outside the range
+    dict(nu0=1010.0, gamma=0.06, p=0.2),               # centre on the range edge
+    dict(nu0=1005.0, gamma=0.06, p=0.2, shape=1),      # Lorentz
+    dict(nu0=1005.0, gamma=0.06, p=0.2, shape=2),      # Doppler
+    dict(nu0=1004.2, gamma=0.06, p=0.4, lt=1),         # all-ratio-2 level table
+])
+def test_grid_matches_definition_one_line(case):
+    c = case.get("c", 25.0)
+    L, lay = _one_line(case["nu0"], case["gamma"], p=case.get("p", 1.0))
+    err = _grid_vs_direct(L, lay, nu_begin=case.get("nb", 1000.0), nu_end=case.get("ne", 1010.0),
+                          cutoff=c, chi=case.get("chi", 0), shape=case.get("shape", 0),
+                          level_table=case.get("lt", 0))
+    assert err < 5e-5, err
+
+
+@pytest.mark.parametrize("n,seed", [(2, 11), (10, 12), (100, 13)])
+def test_grid_matches_definition_few_lines(n, seed):
+    L = synth.make_lines(n, 990.0, 1020.0, seed, shift=True)
+    for lay in [(0.1, 250.0, 0.1, 0.0), (3.0, 500.0, 3.0, 0.0)]:
+        err = _grid_vs_direct(L, lay, nu_begin=1000.0, nu_end=1010.0, cutoff=25.0, chi=1)
+        assert err < 5e-5, (lay, err)
+
+
+def test_grid_matches_definition_single_1k_workload():
+    L, layers, rq = synth.workload("single_1k")
+    err = _grid_vs_direct(L, layers[0], nu_begin=rq["nu_begin"], nu_end=rq["nu_end"],
+                          cutoff=rq["cutoff"], chi=rq["chi"])
+    assert err < 3e-5
+
+
+def test_grid_linear_in_lines():
+    L = synth.make_lines(40, 995.0, 1015.0, 21, shift=True)
+    lay = (0.5, 300.0, 0.5, 0.0)
+    req = dict(nu_begin=1000.0, nu_end=1004.0, cutoff=25.0, chi=1)
+    a = O.grid(L.subset(slice(0, 17)), lay, **req)
+    b = O.grid(L.subset(slice(17, 40)), lay, **req)
+    ab = O.grid(L, lay, **req)
+    assert np.max(np.abs(a + b - ab) / ab) < 1e-12
+
+
+def test_grid_translation_by_one_wavenumber():
+    """Shifting lines and range by 1 cm^-1 is an exact shift of every lattice."""
+    L = synth.make_lines(30, 995.0, 1015.0, 22)
+    lay = (0.5, 296.0, 0.5, 0.0)
+    req = dict(nu_begin=1000.0, nu_end=1004.0, cutoff=25.0, chi=1)
+    a = O.grid(L, lay, **req)
+    L2 = L.subset(slice(None))
+    L2.nu0 = L.nu0 + 1.0
+    L2.gamma_air = L.gamma_air.copy()
+    # alpha_D depends on nu0; compare against the definition instead of bitwise
+    b = O.grid(L2, lay, nu_begin=1001.0, nu_end=1005.0, cutoff=25.0, chi=1)
+    nodes = np.arange(1001 * 2048, 1005 * 2048 + 1)
+    d = O.direct(L2, lay, nodes, nu_begin=1001.0, nu_end=1005.0, cutoff=25.0, chi=1)
+    assert np.max(np.abs(b - d) / d) < 3e-5
+    # Lorentz shape has no nu0 dependence: exact shift up to rounding of d
+    a = O.grid(L, lay, shape=1, **req)
+    b = O.grid(L2, lay, shape=1, nu_begin=1001.0, nu_end=1005.0, cutoff=25.0, chi=1)
+    assert np.max(np.abs(a - b) / a) < 1e-9
+
+
+def test_grid_symmetric_unshifted_line():
+    L, lay = _one_line(1005.0, 0.07, p=0.3)
+    g = O.grid(L, lay, nu_begin=1000.0, nu_end=1010.0, cutoff=25.0, chi=1)
+    c = 5 * 2048
+    nodes = np.arange(1000 * 2048, 1010 * 2048 + 1)
+    d = O.direct(L, lay, nodes, nu_begin=1000.0, nu_end=1010.0, cutoff=25.0, chi=1)
+    # the definition is exactly symmetric about an unshifted centre on a node
+    assert np.max(np.abs(d[c - 3000:c] - d[c + 3000:c:-1]) / d[c - 3000:c]) < 1e-13
+    # the midpoint stencil breaks ties to the lower node, so the eleven-grid
+    # result is symmetric only up to its interpolation error
+    assert np.max(np.abs(g[c - 3000:c] - g[c + 3000:c:-1]) / g[c - 3000:c]) < 5e-5
+
+
+def test_pruning_equals_subset():
+    L = synth.make_lines(60, 990.0, 1020.0, 23)
+    lay = (0.2, 700.0, 0.2, 0.0)
+    req = dict(nu_begin=1000.0, nu_end=1002.0, cutoff=25.0, chi=1)
+    S = np.array([O.line_state(L, lay, j)["S"] for j in range(L.n)])
+    keep = S >= 1e-3 * S.max()
+    assert 0 < keep.sum() < L.n
+    a = O.grid(L, lay, prune=1e-3, **req)
+    b = O.grid(L.subset(np.nonzero(keep)[0]), lay, **req)
+    assert np.array_equal(a, b)
+
+
+def test_absorption_coefficient_scale():
+    L = synth.make_lines(10, 995.0, 1015.0, 24)
+    lay = (0.9, 280.0, 0.3, 0.0)
+    req = dict(nu_begin=1000.0, nu_end=1001.0, cutoff=25.0)
+    s = O.grid(L, lay, **req)
+    k = O.grid(L, lay, out_kind=1, **req)
+    n = 0.3 * 101325 / (1.380649e-23 * 280.0) * 1e-6
+    assert np.allclose(k, s * n * 1e5, rtol=1e-14)
+
+
+def test_invalid_requests_rejected():
+    L = synth.make_lines(3, 995.0, 1015.0, 25)
+    lay = (1.0, 296.0, 1.0, 0.0)
+    with pytest.raises(ValueError):
+        O.grid(L, lay, nu_begin=1001.0, nu_end=1000.0, cutoff=25.0)
+    with pytest.raises(ValueError):
+        O.grid(L, lay, nu_begin=1000.0001, nu_end=1001.0, cutoff=25.0)
+    with pytest.raises(ValueError):
+        O.grid(L, lay, nu_begin=1000.0, nu_end=1001.0, cutoff=0.0)
+    with pytest.raises(ValueError):
+        O.grid(L, (1.0, -3.0, 1.0, 0.0), nu_begin=1000.0, nu_end=1001.0, cutoff=25.0)
+    with pytest.raises(ValueError):
+        O.grid(L, (1.0, 296.0, 2.0, 0.0), nu_begin=1000.0, nu_end=1001.0, cutoff=25.0)
+    with pytest.raises(ValueError):
+        O.grid(L, lay, nu_begin=1000.0, nu_end=1001.0, cutoff=25.0, R=2.0)
+    L.S296[1] = np.nan
+    with pytest.raises(ValueError):
+        O.grid(L, lay, nu_begin=1000.0, nu_end=1001.0, cutoff=25.0)
+
+
+def test_empty_line_list_gives_zeros():
+    L = synth.make_lines(0, 995.0, 1015.0, 26)
+    g = O.grid(L, (1.0, 296.0, 1.0, 0.0), nu_begin=1000.0, nu_end=1001.0, cutoff=25.0)
+    assert g.shape == (2049,) and not g.any()
+
+
+# ---------------------------------------------------------------- records
+
+def test_record_layout_round_trip():
+    L = synth.make_lines(5, 995.0, 1015.0, 27, shift=True)
+    buf = synth.pack_records(L)
+    assert len(buf) == GOLD["line_record_bytes"]["value"] * 5
+    L2 = synth.unpack_records(buf)
+    for f in ("nu0", "S296", "gamma_air", "gamma_self", "E_lower", "n_air", "mol_iso", "delta_air"):
+        assert np.array_equal(getattr(L, f), getattr(L2, f))
+
+
+# ---------------------------------------------------------------- MLP reference
+
+def test_mlp_gradient_matches_finite_differences():
+    rng = np.random.default_rng(5)
+    widths = [3, 8, 8, 1]
+    n = sum(widths[i + 1] * widths[i] + widths[i + 1] for i in range(3))
+    P = rng.normal(0, 0.5, n)
+    X = rng.normal(0, 1, (7, 3))
+    t = rng.normal(0, 1, 7)
+    loss, g = O.mlp_loss_grad(widths, P, X, t)
+    Y = O.mlp_forward(widths, P, X)[:, 0]
+    assert abs(loss - np.mean((Y - t) ** 2)) < 1e-14
+    h = 1e-6
+    for i in range(0, n, 3):
+        Pp = P.copy(); Pp[i] += h
+        Pm = P.copy(); Pm[i] -= h
+        fd = (O.mlp_loss_grad(widths, Pp, X, t)[0] - O.mlp_loss_grad(widths, Pm, X, t)[0]) / (2 * h)
+        assert abs(fd - g[i]) < 1e-7 * max(1.0, abs(fd)), i
+
+
+def test_mlp_forward_hand_network():
+    # 1 -> 1 -> 1: y = w2 * silu(w1 x + b1) + b2
+    widths = [1, 1, 1]
+    P = np.array([2.0, -0.5, 3.0, 0.25])
+    X = np.array([[0.7]])
+    z = 2.0 * 0.7 - 0.5
+    assert abs(O.mlp_forward(widths, P, X)[0, 0] - (3.0 * z / (1 + math.exp(-z)) + 0.25)) < 1e-15
