@@ -1,0 +1,169 @@
+#!/usr/bin/env python3
+"""Benchmark: spectral points per second on one MI355X for an eleven-grid PT table.
+
+A step is one pass of the whole hot path (line preparation, level
+accumulation, cascade) over every layer of the workload, replayed from the
+plan's HIP graph with all inputs resident in HBM.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_VALU_TFLOPS = 157.3   # MI355X published FP32 vector peak
+PEAK_HBM_GBS = 8000.0
+
+# Counted flops per evaluated term (static count of the kernel source; FMA = 2,
+# add/mul/compare-free = 1, rcp/exp = 1).  Double-precision flops of the
+# rational core count twice (the FP64 vector peak is half the FP32 one).
+FLOP_PAIR = 3            # d = (X - k0) - frac, |d| band tests excluded, acc += v
+FLOP_WING = 20           # dcm, d^2, x, y, z^2, Q = 1/(d^2+g^2), e, f, chi, S'*f*chi
+FLOP_WING_TERM = 7       # one more term of the asymptotic series
+FLOP_CORE = 2 * 250      # Weideman N = 32 in FP64 (31 complex Horner steps + setup)
+FLOP_BAND_NODE = 2       # stencil weight times the coarse value
+FLOP_CASCADE_NODE = 5    # 3-point interpolation per node
+
+
+def counted_flops(st):
+    pairs = sum(st["pairs_level"])
+    evals = st["pairs_wing"] + st["pairs_core"]
+    f = (FLOP_PAIR * pairs + FLOP_WING * st["pairs_wing"] + FLOP_WING_TERM * st["wing_terms"]
+         + FLOP_CORE * st["pairs_core"] + FLOP_BAND_NODE * 3 * st["pairs_band"])
+    return float(f), evals
+
+
+def cpu_baseline(lines, layers, req, budget_s):
+    """The FP64 oracle's eleven-grid program on a bounded sample of the workload:
+    one layer, a sub-interval of the spectrum grown until the budget is used."""
+    import oracle as O
+    threads = min(os.cpu_count() or 1, 16)
+    L = layers[len(layers) // 2]
+    o = dict(cutoff=req["cutoff"], chi=req["chi"], prune=req["prune"])
+    width = 0.25
+    lo = 0.5 * (req["nu_begin"] + req["nu_end"])
+    while True:
+        t0 = time.perf_counter()
+        out = O.grid(lines, L, threads=threads, nu_begin=lo, nu_end=lo + width, **o)
+        dt = time.perf_counter() - t0
+        if dt > budget_s / 3 or width >= 64:
+            break
+        width *= 2 if dt > 0.2 * budget_s / 3 else 4
+    pts = out.size
+    return dict(value=pts / dt, unit="points/s", cores=threads, kind="oracle",
+                sample=f"eleven-grid oracle (FP64), layer {len(layers) // 2} (p={L[0]:.3g} atm, T={L[1]:.0f} K), "
+                       f"{width:g} cm^-1 at {lo:g} cm^-1 = {pts} points, {dt:.2f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="pt100_2m")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--check-nodes", type=int, default=256)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (layers shard across GPUs "
+              "without communication; see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import oracle as O
+    from paper_2411_03418_amd import marfa, synth
+
+    t0 = time.perf_counter()
+    lines, layers, rq = synth.workload(args.workload)
+    chi = "tonkov" if rq["chi"] else "none"
+    req = dict(nu_begin=rq["nu_begin"], nu_end=rq["nu_end"], cutoff=rq["cutoff"], chi=chi, prune=rq["prune"])
+    print(f"[bench] {args.workload}: {lines.n} lines, {len(layers)} layers, inputs {time.perf_counter() - t0:.1f} s",
+          file=sys.stderr, flush=True)
+    plan = marfa.Plan(lines, layers, device=0, **req)
+    out = torch.empty((plan.n_layers, plan.points), dtype=torch.float32, device="cuda:0")
+    st = plan.count()
+    flops, evals = counted_flops(st)
+    print(f"[bench] plan ready; pairs {sum(st['pairs_level']):.3e}, core {st['pairs_core']:.3e}, "
+          f"band {st['pairs_band']:.3e}", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        plan.execute(out=out)
+    torch.cuda.synchronize()
+    print("[bench] warmup done", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.execute(out=out)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms = dt / args.steps * 1e3
+    points = plan.points * plan.n_layers
+    # dominant kernel: level accumulation, timed by HIP events recorded in the graph
+    lv, tot, prep, cas = [], [], [], []
+    for _ in range(args.steps):
+        _, t = plan.execute_timed(out=out)
+        lv.append(t["level_ms"]); tot.append(t["total_ms"]); prep.append(t["prep_ms"]); cas.append(t["cascade_ms"])
+    level_ms = float(np.mean(lv))
+    achieved = flops / (level_ms * 1e-3) / 1e12
+    print(f"[bench] {ms:.2f} ms/step; level {level_ms:.2f} ms, prep {np.mean(prep):.2f} ms, "
+          f"cascade {np.mean(cas):.2f} ms", file=sys.stderr, flush=True)
+
+    # sampled parity against the definition (direct sum) on two layers
+    res = {}
+    if args.check_nodes > 0:
+        rng = np.random.default_rng(1)
+        m0 = int(round(req["nu_begin"] * 2048))
+        nodes = np.sort(rng.integers(m0, int(round(req["nu_end"] * 2048)) + 1, args.check_nodes))
+        worst = 0.0
+        o = dict(nu_begin=req["nu_begin"], nu_end=req["nu_end"], cutoff=req["cutoff"], chi=rq["chi"],
+                 prune=req["prune"])
+        for li in sorted({0, plan.n_layers - 1, plan.n_layers // 2}):
+            ref = O.direct(lines, layers[li], nodes, threads=min(os.cpu_count() or 1, 16), **o)
+            got = out[li, torch.as_tensor(nodes - m0, device="cuda:0")].double().cpu().numpy()
+            msk = ref >= 1e-8 * ref.max()
+            worst = max(worst, float(np.max(np.abs(got[msk] - ref[msk]) / ref[msk])))
+        res = dict(max_rel_err_vs_direct=worst, checked_nodes=int(args.check_nodes), checked_layers=3)
+        print(f"[bench] sampled parity {worst:.2e}", file=sys.stderr, flush=True)
+
+    line = {
+        "metric": "spectral points/s/GPU (PT table), plain path at 1e-4 rel err",
+        "value": points / (ms * 1e-3),
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "lines": lines.n, "layers": plan.n_layers,
+                   "points_per_layer": plan.points, "nu_begin": req["nu_begin"], "nu_end": req["nu_end"],
+                   "cutoff": req["cutoff"], "chi": chi, "prune_rel": req["prune"], "R": 48,
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_VALU_TFLOPS, "traffic": None,
+                     "kernel": "k_level", "kernel_ms": level_ms, "counted_tflop_per_launch": flops / 1e12},
+        "stages_ms": {"prep": float(np.mean(prep)), "level": level_ms, "cascade": float(np.mean(cas)),
+                      "graph_total": float(np.mean(tot))},
+        "pairs": {"total": int(sum(st["pairs_level"])), "core": int(st["pairs_core"]),
+                  "wing": int(st["pairs_wing"]), "band": int(st["pairs_band"]),
+                  "per_level": [int(v) for v in st["pairs_level"]]},
+    }
+    line.update(res)
+    plan.close()
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(lines, layers, dict(req, chi=rq["chi"]), args.cpu_seconds)
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,177 @@
+/*
+ * marfa.h -- C ABI of the MI355X (gfx950) eleven-grid line-by-line absorption
+ * library.
+ *
+ * What it computes (MARFA, arXiv 2411.03418):
+ *   sigma(nu; p, T) = sum_j S_j(T) f_j(nu - nu~0_j; gamma_L, alpha_D) chi(|nu - nu~0_j|)
+ *   over every line j with |nu - nu~0_j| <= cutoff                 -- Eq.(3), Section 2.1
+ *   k(nu; p, T)     = n(p_self, T) * sigma                          -- Eq.(2), Section 2.1
+ * on the lattice nu = m * 2^-11 cm^-1 (10/20480, Appendix A), one spectrum per
+ * pressure-temperature layer, evaluated with the eleven-grid interpolation
+ * technique of Section 2.4 (line centres on the finest grid, wings on ten
+ * coarser grids, 3-point interpolation back to the finest grid).  Line shapes:
+ * Voigt (default, Eq.(7)-(8)), Lorentz (Eq.(4)), Doppler (Eq.(5)); wing factor:
+ * none or Tonkov (Eq.(10), Section 2.3).  Line parameters follow the database
+ * record of Appendix B; their temperature/pressure dependences are the HITRAN
+ * forms the paper cites (Section 2.2).
+ *
+ * Conventions
+ *  - Every function returns a marfa_status; nothing throws across the ABI.
+ *    marfa_last_error() gives a thread-local text for the last failure.
+ *  - Host inputs are borrowed for the duration of the call and copied.
+ *  - Device outputs are caller-owned device memory on the plan's device.
+ *  - A plan is not thread-safe; distinct plans are independent.
+ *  - Execution is asynchronous on the caller's HIP stream.
+ */
+#ifndef MARFA_H
+#define MARFA_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MARFA_OK = 0,
+  MARFA_E_INVALID = -1,      /* an argument violates the rules stated below */
+  MARFA_E_NOMEM = -2,        /* host or device allocation failed */
+  MARFA_E_DEVICE = -3,       /* HIP error, or no usable gfx950 device */
+  MARFA_E_UNSUPPORTED = -4,  /* valid but not available (e.g. untrained surrogate) */
+  MARFA_E_STATE = -5         /* call out of order */
+} marfa_status;
+
+typedef enum { MARFA_SHAPE_VOIGT = 0, MARFA_SHAPE_LORENTZ = 1, MARFA_SHAPE_DOPPLER = 2 } marfa_shape;
+typedef enum { MARFA_CHI_NONE = 0, MARFA_CHI_TONKOV = 1 } marfa_chi;
+typedef enum { MARFA_OUT_SIGMA_CM2 = 0, MARFA_OUT_K_PER_KM = 1 } marfa_output;
+typedef enum { MARFA_EVAL_PLAIN = 0, MARFA_EVAL_SURROGATE = 1 } marfa_eval;
+
+/* Line list, structure of arrays in HOST memory, n entries each (fields of the
+ * 36-byte record of Appendix B).  Any order; the plan sorts by nu0.
+ * Rules: n >= 0; every value finite; nu0 >= 0; S296, gamma_* >= 0;
+ * molar_mass_g > 0.  mol_iso may be NULL (it is carried, not used). */
+typedef struct {
+  int64_t n;
+  const double* nu0;          /* transition wavenumber [cm^-1] */
+  const float* S296;          /* intensity at 296 K [cm/molecule] */
+  const float* gamma_air;     /* air-broadened HWHM at 296 K, 1 atm [cm^-1/atm] */
+  const float* gamma_self;    /* self-broadened HWHM at 296 K, 1 atm [cm^-1/atm] */
+  const float* E_lower;       /* lower-state energy E'' [cm^-1] */
+  const float* n_air;         /* temperature exponent of the half-width */
+  const int32_t* mol_iso;     /* joint molecule/isotopologue id */
+  const float* delta_air;     /* pressure shift at 296 K [cm^-1/atm] */
+  double molar_mass_g;        /* [g/mol] */
+} marfa_lines;
+
+/* One pressure-temperature layer.  Rules: T_K > 0, 0 <= p_self_atm <= p_atm.
+ * q_ratio = Q(296)/Q(T); a value <= 0 selects 296/T. */
+typedef struct {
+  double p_atm, T_K, p_self_atm, q_ratio;
+} marfa_layer;
+
+/* Request.  Rules: nu_begin >= 0, nu_end > nu_begin, both multiples of 2^-11;
+ * cutoff > 0 (cm^-1, inclusive, measured from the shifted centre);
+ * R an integer in [4, 4096] (region multiple of the level step, default 48);
+ * level_table 0 (steps 2^-11, 2^-9, ..., 1 cm^-1) or 1 (2^-11, ..., 2^-1);
+ * prune_rel in [0, 1): lines with S(T) < prune_rel * max_j S_j(T) are dropped
+ * per layer (max over the whole list); fp64 = 1 runs the device path in double
+ * precision (output then FP64).  Zero-initialise reserved fields. */
+typedef struct {
+  double nu_begin, nu_end;
+  double cutoff;
+  int32_t shape;              /* marfa_shape */
+  int32_t chi;                /* marfa_chi */
+  int32_t out_kind;           /* marfa_output */
+  int32_t eval;               /* marfa_eval */
+  double prune_rel;
+  double R;
+  int32_t level_table;
+  int32_t fp64;
+  int32_t reserved[4];
+} marfa_request;
+
+typedef struct marfa_plan marfa_plan;
+
+/* Per-plan counters from the last marfa_plan_count() (exact (node, line) pairs
+ * evaluated, split by level and by line-shape branch). */
+typedef struct {
+  int64_t points_per_layer;       /* output nodes per layer */
+  int32_t n_layers;
+  int64_t lines_total;            /* lines in the plan */
+  int64_t lines_kept;             /* sum over layers of lines kept after pruning */
+  int64_t pairs_level[11];        /* pairs with a non-zero contribution, per level */
+  int64_t pairs_core;             /* Voigt pairs in the core branch (|z| < 6) */
+  int64_t pairs_wing;             /* pairs in the wing series branch */
+  int64_t pairs_band;             /* pairs carrying a residual-band correction */
+  int64_t wing_terms;             /* sum over wing pairs of series terms beyond the first */
+  int64_t level_nodes;            /* nodes of levels 1..10 over all layers */
+} marfa_stats;
+
+/* Create a plan: validates and copies the inputs, sorts lines by nu0, uploads
+ * them to `device`, sizes the workspace.  n_layers >= 1.  On success *out
+ * receives the plan (destroy with marfa_plan_destroy).
+ * Errors: MARFA_E_INVALID for any rule above; MARFA_E_DEVICE if the device is
+ * missing or not gfx950; MARFA_E_NOMEM on allocation failure. */
+marfa_status marfa_plan_create(marfa_plan** out, const marfa_lines* lines,
+                               const marfa_layer* layers, int32_t n_layers,
+                               const marfa_request* req, int32_t device);
+
+/* Output nodes per layer: (nu_end - nu_begin) * 2048 + 1. */
+marfa_status marfa_plan_points(const marfa_plan* plan, int64_t* points_per_layer);
+
+/* Compute every layer into out_dev (device memory, FP32, or FP64 if fp64),
+ * layout [n_layers][layer_stride], node m of layer L at out[L*stride + m],
+ * m = 0 .. points-1 <-> nu = nu_begin + m 2^-11.  layer_stride >= points.
+ * hip_stream is a hipStream_t (NULL = legacy default stream).  Asynchronous.
+ * The first call on a plan captures the work into a HIP graph; later calls
+ * with the same (out_dev, layer_stride, stream) replay it. */
+marfa_status marfa_execute(marfa_plan* plan, void* out_dev, int64_t layer_stride, void* hip_stream);
+
+/* As marfa_execute for layers [first, first+count) only; out_dev points at
+ * the slot of layer `first`.  Never graph-captured. */
+marfa_status marfa_execute_layers(marfa_plan* plan, int32_t first, int32_t count,
+                                  void* out_dev, int64_t layer_stride, void* hip_stream);
+
+/* Count pairs exactly (runs the same loops without evaluating shapes) and
+ * fill *stats.  Synchronous. */
+marfa_status marfa_plan_count(marfa_plan* plan, marfa_stats* stats);
+
+/* Tile parameters used by the kernels (read back for reports); autotune=1 in
+ * marfa_plan_tune times candidate shapes on the device and keeps the fastest. */
+typedef struct {
+  int32_t wave_nodes;   /* nodes per wavefront tile */
+  int32_t block_waves;  /* wavefronts per workgroup */
+  int32_t split;        /* line-window split factor for coarse levels */
+  int32_t reserved;
+} marfa_tiles;
+marfa_status marfa_plan_tiles(const marfa_plan* plan, marfa_tiles* tiles);
+marfa_status marfa_plan_tune(marfa_plan* plan, void* scratch_out_dev, int64_t layer_stride,
+                             void* hip_stream);
+
+/* As marfa_execute, but the three stages (line preparation, level
+ * accumulation, cascade) are launched as three graphs on hip_stream with HIP
+ * events recorded on that stream between them; waits for completion and
+ * returns each stage's duration in *t.  Same kernels and arguments as
+ * marfa_execute (used to time the dominant kernel). */
+typedef struct {
+  float prep_ms, level_ms, cascade_ms, total_ms;
+} marfa_timing;
+marfa_status marfa_execute_timed(marfa_plan* plan, void* out_dev, int64_t layer_stride, void* hip_stream,
+                                 marfa_timing* t);
+
+void marfa_plan_destroy(marfa_plan* plan);
+
+const char* marfa_status_string(int32_t status);
+/* Copy the calling thread's last error text into buf (NUL-terminated). */
+marfa_status marfa_last_error(char* buf, size_t n);
+
+/* Device Voigt function for tests: K(x_i, y_i) for n points in HOST arrays,
+ * evaluated by the same device code as the hot path (fp64 selects the double
+ * instantiation).  Synchronous. */
+marfa_status marfa_voigt_eval(int32_t device, int64_t n, const double* x, const double* y,
+                              double* out, int32_t fp64);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,679 @@
+// marfa_plan.hip -- host runtime and C ABI of the eleven-grid library.
+//
+// A plan owns the uploaded line list, the per-layer workspace and one HIP
+// graph holding the whole hot path (line preparation, level accumulation,
+// cascade).  See include/marfa.h for the contract of each entry point.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "marfa.h"
+#include "marfa_internal.h"
+
+
+using namespace marfa;
+
+// ------------------------------------------------------------------
+// errors
+// ------------------------------------------------------------------
+static thread_local std::string g_err;
+
+static marfa_status fail(marfa_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                                        \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess) return fail(MARFA_E_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+// ------------------------------------------------------------------
+// Weideman coefficients: psi(t) = (L^2 + t^2) exp(-t^2) expanded in
+// Z(t)^n = ((L+it)/(L-it))^n; with t = L tan(theta/2) the a_n are the Fourier
+// cosine coefficients of psi(L tan(theta/2)), computed by the trapezoid rule.
+// ------------------------------------------------------------------
+static void weideman_coeffs(int N, double* a, double* Lout) {
+  const double L = std::pow(2.0, -0.25) * std::sqrt((double)N);
+  const int M = 16 * N;
+  const double pi = 3.14159265358979323846;
+  std::vector<double> psi(M), th(M);
+  for (int k = 0; k < M; ++k) {
+    th[k] = -pi + 2.0 * pi * k / M;
+    if (k == 0) { psi[k] = 0.0; continue; }
+    double t = L * std::tan(0.5 * th[k]);
+    psi[k] = (L * L + t * t) * std::exp(-t * t);
+  }
+  for (int n = 0; n <= N; ++n) {
+    double s = 0.0;
+    for (int k = 0; k < M; ++k) s += psi[k] * std::cos(n * th[k]);
+    a[n] = s / M;
+  }
+  *Lout = L;
+}
+
+static std::mutex g_dev_mu;
+static bool g_dev_ready[64];
+
+static marfa_status ensure_device(int device) {
+  int cnt = 0;
+  if (hipGetDeviceCount(&cnt) != hipSuccess || cnt <= 0) return fail(MARFA_E_DEVICE, "no HIP device");
+  if (device < 0 || device >= cnt || device >= 64) return fail(MARFA_E_DEVICE, "device %d out of range", device);
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, device));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(MARFA_E_DEVICE, "device %d is %s, not gfx950", device, prop.gcnArchName);
+  HIP_TRY(hipSetDevice(device));
+  std::lock_guard<std::mutex> lk(g_dev_mu);
+  if (!g_dev_ready[device]) {
+    double a32[kWeidemanN32 + 1], a64[kWeidemanN64 + 1], L2[2];
+    weideman_coeffs(kWeidemanN32, a32, &L2[0]);
+    weideman_coeffs(kWeidemanN64, a64, &L2[1]);
+    HIP_TRY(upload_weideman(a32, a64, L2));
+    g_dev_ready[device] = true;
+  }
+  return MARFA_OK;
+}
+
+// ------------------------------------------------------------------
+// plan
+// ------------------------------------------------------------------
+struct marfa_plan {
+  int device = 0;
+  marfa_request req{};
+  int64_t n_lines = 0;
+  double molar_mass = 44.0;
+  int32_t n_layers = 0;
+  int nblk = 0;
+  Geometry G{};
+  std::vector<IntervalSet> ivs;
+  std::vector<Tile> tiles;
+  std::vector<double> layers_h;
+  std::vector<double> shift_h;
+  DeviceBuffers d;
+  int grid = 0;
+  int cu_count = 0;
+  // graph cache
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr;
+  void* g_out = nullptr;
+  int64_t g_stride = 0;
+  hipStream_t cap = nullptr;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipGraph_t sgraph[3] = {nullptr, nullptr, nullptr};
+  hipGraphExec_t sexec[3] = {nullptr, nullptr, nullptr};
+  void* s_out = nullptr;
+  int64_t s_stride = 0;
+  marfa_tiles tile_cfg{64, 4, 1, 0};
+};
+
+static int64_t fdiv(int64_t a, int64_t b) {
+  int64_t q = a / b;
+  if ((a % b != 0) && ((a < 0) != (b < 0))) --q;
+  return q;
+}
+
+static void make_geometry(const marfa_request& rq, Geometry& G) {
+  for (int l = 0; l < kLevels; ++l) {
+    if (rq.level_table == 1) G.r[l] = 1 << l;
+    else G.r[l] = l == 0 ? 1 : (1 << (l + 1));
+  }
+  G.lo[0] = (int64_t)std::llround(rq.nu_begin * 2048.0);
+  int64_t hi[kLevels];
+  hi[0] = (int64_t)std::llround(rq.nu_end * 2048.0);
+  for (int l = 0; l < kLevels - 1; ++l) {
+    int64_t rho = G.r[l + 1] / G.r[l];
+    G.lo[l + 1] = fdiv(G.lo[l], rho) - 1;
+    hi[l + 1] = -fdiv(-hi[l], rho) + 1;
+  }
+  int64_t off = 0;
+  for (int l = 0; l < kLevels; ++l) {
+    G.n[l] = hi[l] - G.lo[l] + 1;
+    if (l >= 1) {
+      G.aoff[l] = off;
+      off += G.n[l];
+    } else {
+      G.aoff[l] = 0;
+    }
+  }
+  G.a_total = off;
+  for (int l = 0; l < kLevels - 1; ++l) {
+    G.b[l] = rq.R * G.r[l + 1];
+    G.B[l] = 2.0 * G.r[l + 1];
+  }
+  G.b[kLevels - 1] = INFINITY;
+  G.B[kLevels - 1] = 0.0;
+  G.c_fine = rq.cutoff * 2048.0;
+  G.shape = rq.shape;
+  G.chi = rq.chi;
+  G.out_kind = rq.out_kind;
+  G.fp64 = rq.fp64;
+}
+
+// |d| intervals where the level-l part of a line with start level s can be
+// non-zero: its region, and bands of half-width B_l around each jump of the
+// line's level-(l+1) part (inner edge b_l, cut-off, chi breakpoints).
+static bool make_intervals(const Geometry& G, int chi, std::vector<IntervalSet>& out) {
+  out.assign(kLevels * kGroups, IntervalSet{});
+  const double c = G.c_fine;
+  for (int l = 0; l < kLevels; ++l) {
+    for (int s = 0; s < kGroups; ++s) {
+      std::vector<std::pair<double, double>> iv;
+      if (l >= s) {
+        double inner = (l == s) ? 0.0 : G.b[l - 1];
+        double outer = (l < kLevels - 1) ? G.b[l] : c;
+        double hi = std::min(outer, c);
+        if (inner <= hi) iv.push_back({inner, hi});
+      }
+      IntervalSet& S = out[l * kGroups + s];
+      if (l < kLevels - 1) {
+        double lo_sup = (l + 1 > s) ? G.b[l] : 0.0;
+        std::vector<double> q;
+        if (lo_sup <= c) {
+          if (l + 1 > s) q.push_back(G.b[l]);
+          q.push_back(c);
+          if (chi == MARFA_CHI_TONKOV) {
+            const double br[3] = {3.0 * 2048.0, 150.0 * 2048.0, 300.0 * 2048.0};
+            for (double v : br)
+              if (v >= lo_sup && v <= c) q.push_back(v);
+          }
+        }
+        std::sort(q.begin(), q.end());
+        q.erase(std::unique(q.begin(), q.end()), q.end());
+        if ((int)q.size() > kMaxJumps) return false;
+        S.n_q = (int)q.size();
+        for (size_t i = 0; i < q.size(); ++i) {
+          S.q[i] = q[i];
+          iv.push_back({std::max(0.0, q[i] - G.B[l]), q[i] + G.B[l]});
+        }
+      }
+      std::sort(iv.begin(), iv.end());
+      std::vector<std::pair<double, double>> merged;
+      for (auto& p : iv) {
+        if (!merged.empty() && p.first <= merged.back().second)
+          merged.back().second = std::max(merged.back().second, p.second);
+        else
+          merged.push_back(p);
+      }
+      if ((int)merged.size() > kMaxIntervals) return false;
+      S.n_iv = (int)merged.size();
+      for (size_t i = 0; i < merged.size(); ++i) {
+        S.a[i] = merged[i].first;
+        S.b[i] = merged[i].second;
+      }
+    }
+  }
+  return true;
+}
+
+// Work items: nodes per item scale inversely with the per-node cost, which
+// grows with the level step (window width in lines); heaviest levels first.
+static void make_tiles(const Geometry& G, std::vector<Tile>& tiles, int base_nodes) {
+  tiles.clear();
+  for (int l = kLevels - 1; l >= 0; --l) {
+    int64_t per = (int64_t)base_nodes * std::max<int64_t>(1, 16 / G.r[l]);
+    per = ((per + kWave - 1) / kWave) * kWave;
+    for (int64_t f = 0; f < G.n[l]; f += per) {
+      Tile t;
+      t.level = l;
+      t.first = f;
+      t.count = (int32_t)std::min<int64_t>(per, G.n[l] - f);
+      tiles.push_back(t);
+    }
+  }
+}
+
+static bool finite_all_f(const float* p, int64_t n) {
+  for (int64_t i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+static marfa_status validate(const marfa_lines* L, const marfa_layer* lay, int32_t nL, const marfa_request* rq) {
+  if (!L || !lay || !rq) return fail(MARFA_E_INVALID, "null argument");
+  if (L->n < 0) return fail(MARFA_E_INVALID, "negative line count");
+  if (nL < 1) return fail(MARFA_E_INVALID, "n_layers must be >= 1");
+  if (L->n > 0 && (!L->nu0 || !L->S296 || !L->gamma_air || !L->gamma_self || !L->E_lower || !L->n_air ||
+                   !L->delta_air))
+    return fail(MARFA_E_INVALID, "null line array");
+  if (L->n > ((int64_t)1 << 31) - 1) return fail(MARFA_E_INVALID, "too many lines");
+  if (!(L->molar_mass_g > 0.0) || !std::isfinite(L->molar_mass_g)) return fail(MARFA_E_INVALID, "molar mass");
+  for (int64_t j = 0; j < L->n; ++j)
+    if (!std::isfinite(L->nu0[j]) || L->nu0[j] < 0.0) return fail(MARFA_E_INVALID, "line %lld: bad nu0", (long long)j);
+  if (!finite_all_f(L->S296, L->n) || !finite_all_f(L->gamma_air, L->n) || !finite_all_f(L->gamma_self, L->n) ||
+      !finite_all_f(L->E_lower, L->n) || !finite_all_f(L->n_air, L->n) || !finite_all_f(L->delta_air, L->n))
+    return fail(MARFA_E_INVALID, "non-finite line parameter");
+  for (int64_t j = 0; j < L->n; ++j)
+    if (L->S296[j] < 0.0f || L->gamma_air[j] < 0.0f || L->gamma_self[j] < 0.0f)
+      return fail(MARFA_E_INVALID, "line %lld: negative intensity or width", (long long)j);
+  for (int32_t i = 0; i < nL; ++i) {
+    const marfa_layer& y = lay[i];
+    if (!std::isfinite(y.p_atm) || !std::isfinite(y.T_K) || !std::isfinite(y.p_self_atm) || !std::isfinite(y.q_ratio))
+      return fail(MARFA_E_INVALID, "layer %d: non-finite", i);
+    if (!(y.T_K > 0.0) || y.p_atm < 0.0 || y.p_self_atm < 0.0 || y.p_self_atm > y.p_atm)
+      return fail(MARFA_E_INVALID, "layer %d: need T > 0 and 0 <= p_self <= p", i);
+  }
+  if (!std::isfinite(rq->nu_begin) || !std::isfinite(rq->nu_end) || rq->nu_begin < 0.0 || rq->nu_end <= rq->nu_begin)
+    return fail(MARFA_E_INVALID, "need 0 <= nu_begin < nu_end");
+  if (std::floor(rq->nu_begin * 2048.0) != rq->nu_begin * 2048.0 ||
+      std::floor(rq->nu_end * 2048.0) != rq->nu_end * 2048.0)
+    return fail(MARFA_E_INVALID, "nu_begin and nu_end must be multiples of 2^-11 cm^-1");
+  if (rq->nu_end * 2048.0 > 1.0e9) return fail(MARFA_E_INVALID, "nu_end too large");
+  if (!(rq->cutoff > 0.0) || !std::isfinite(rq->cutoff) || rq->cutoff > 1.0e5)
+    return fail(MARFA_E_INVALID, "cutoff must be in (0, 1e5]");
+  if (!(rq->R >= 4.0) || rq->R > 4096.0 || std::floor(rq->R) != rq->R)
+    return fail(MARFA_E_INVALID, "R must be an integer in [4, 4096]");
+  if (rq->shape < 0 || rq->shape > 2) return fail(MARFA_E_INVALID, "shape");
+  if (rq->chi < 0 || rq->chi > 1) return fail(MARFA_E_INVALID, "chi");
+  if (rq->out_kind < 0 || rq->out_kind > 1) return fail(MARFA_E_INVALID, "out_kind");
+  if (rq->eval < 0 || rq->eval > 1) return fail(MARFA_E_INVALID, "eval");
+  if (rq->level_table < 0 || rq->level_table > 1) return fail(MARFA_E_INVALID, "level_table");
+  if (rq->fp64 < 0 || rq->fp64 > 1) return fail(MARFA_E_INVALID, "fp64");
+  if (!(rq->prune_rel >= 0.0) || !(rq->prune_rel < 1.0)) return fail(MARFA_E_INVALID, "prune_rel in [0,1)");
+  if (rq->eval == MARFA_EVAL_SURROGATE) return fail(MARFA_E_UNSUPPORTED, "surrogate evaluation needs a trained network");
+  return MARFA_OK;
+}
+
+template <typename T>
+static marfa_status dmalloc(T** p, size_t count) {
+  size_t bytes = std::max<size_t>(1, count * sizeof(T));
+  hipError_t e = hipMalloc((void**)p, bytes);
+  if (e != hipSuccess) return fail(MARFA_E_NOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+  return MARFA_OK;
+}
+
+static void free_plan(marfa_plan* p) {
+  if (!p) return;
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->cap) (void)hipStreamDestroy(p->cap);
+  for (hipEvent_t e : p->ev)
+    if (e) (void)hipEventDestroy(e);
+  for (int i = 0; i < 3; ++i) {
+    if (p->sexec[i]) (void)hipGraphExecDestroy(p->sexec[i]);
+    if (p->sgraph[i]) (void)hipGraphDestroy(p->sgraph[i]);
+  }
+  void* bufs[] = {p->d.nu0, p->d.S296, p->d.gair, p->d.gself, p->d.El, p->d.nair, p->d.dair, p->d.layers,
+                  p->d.smax, p->d.bcount, p->d.gcount, p->d.gstart, p->d.rec, p->d.cnu, p->d.A, p->d.ivs,
+                  p->d.tiles, p->d.counter, p->d.scale, p->d.shift, p->d.stats};
+  for (void* b : bufs)
+    if (b) (void)hipFree(b);
+  delete p;
+}
+
+extern "C" marfa_status marfa_plan_create(marfa_plan** out, const marfa_lines* lines, const marfa_layer* layers,
+                                          int32_t n_layers, const marfa_request* req, int32_t device) {
+  if (!out) return fail(MARFA_E_INVALID, "null out");
+  *out = nullptr;
+  marfa_status st = validate(lines, layers, n_layers, req);
+  if (st != MARFA_OK) return st;
+  st = ensure_device(device);
+  if (st != MARFA_OK) return st;
+  marfa_plan* p = new marfa_plan();
+  p->device = device;
+  p->req = *req;
+  p->n_lines = lines->n;
+  p->molar_mass = lines->molar_mass_g;
+  p->n_layers = n_layers;
+  p->nblk = (int)((lines->n + 255) / 256);
+  make_geometry(*req, p->G);
+  if (!make_intervals(p->G, req->chi, p->ivs)) {
+    free_plan(p);
+    return fail(MARFA_E_INVALID, "too many band intervals");
+  }
+  make_tiles(p->G, p->tiles, 256);
+  // sort lines by nu0
+  const int64_t n = lines->n;
+  std::vector<int64_t> idx(n);
+  std::iota(idx.begin(), idx.end(), 0);
+  std::stable_sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) { return lines->nu0[a] < lines->nu0[b]; });
+  std::vector<double> nu(n);
+  std::vector<float> S(n), ga(n), gs(n), E(n), na(n), da(n);
+  double dmin = 0.0, dmax = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    int64_t j = idx[i];
+    nu[i] = lines->nu0[j];
+    S[i] = lines->S296[j];
+    ga[i] = lines->gamma_air[j];
+    gs[i] = lines->gamma_self[j];
+    E[i] = lines->E_lower[j];
+    na[i] = lines->n_air[j];
+    da[i] = lines->delta_air[j];
+    if (i == 0) dmin = dmax = da[i];
+    dmin = std::min<double>(dmin, da[i]);
+    dmax = std::max<double>(dmax, da[i]);
+  }
+  p->layers_h.resize(4 * n_layers);
+  p->shift_h.resize(2 * n_layers);
+  for (int i = 0; i < n_layers; ++i) {
+    p->layers_h[4 * i + 0] = layers[i].p_atm;
+    p->layers_h[4 * i + 1] = layers[i].T_K;
+    p->layers_h[4 * i + 2] = layers[i].p_self_atm;
+    p->layers_h[4 * i + 3] = layers[i].q_ratio;
+    p->shift_h[2 * i + 0] = dmin * layers[i].p_atm;
+    p->shift_h[2 * i + 1] = dmax * layers[i].p_atm;
+  }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+    free_plan(p);
+    return fail(MARFA_E_DEVICE, "device properties");
+  }
+  p->cu_count = prop.multiProcessorCount;
+  const size_t recsz = req->fp64 ? sizeof(LineRec64) : sizeof(LineRec32);
+  const size_t realsz = req->fp64 ? sizeof(double) : sizeof(float);
+  const size_t NL = (size_t)n_layers;
+#define ALLOC(ptr, cnt)                      \
+  do {                                       \
+    st = dmalloc(&(ptr), (cnt));             \
+    if (st != MARFA_OK) { free_plan(p); return st; } \
+  } while (0)
+  ALLOC(p->d.nu0, n);
+  ALLOC(p->d.S296, n);
+  ALLOC(p->d.gair, n);
+  ALLOC(p->d.gself, n);
+  ALLOC(p->d.El, n);
+  ALLOC(p->d.nair, n);
+  ALLOC(p->d.dair, n);
+  ALLOC(p->d.layers, 4 * NL);
+  ALLOC(p->d.smax, NL);
+  ALLOC(p->d.bcount, NL * (size_t)std::max(1, p->nblk) * (kGroups + 1));
+  ALLOC(p->d.gcount, NL * (kGroups + 1));
+  ALLOC(p->d.gstart, NL * (kGroups + 1));
+  {
+    char* r = nullptr;
+    ALLOC(r, NL * (size_t)n * recsz);
+    p->d.rec = r;
+    char* a = nullptr;
+    ALLOC(a, NL * (size_t)p->G.a_total * realsz);
+    p->d.A = a;
+  }
+  ALLOC(p->d.cnu, NL * (size_t)n);
+  ALLOC(p->d.ivs, p->ivs.size());
+  ALLOC(p->d.tiles, p->tiles.size());
+  ALLOC(p->d.counter, 4);
+  ALLOC(p->d.scale, NL);
+  ALLOC(p->d.shift, 2 * NL);
+  ALLOC(p->d.stats, 16);
+#undef ALLOC
+  auto up = [&](void* dst, const void* src, size_t bytes) -> marfa_status {
+    if (bytes == 0) return MARFA_OK;
+    hipError_t e = hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return fail(MARFA_E_DEVICE, "upload: %s", hipGetErrorString(e));
+    return MARFA_OK;
+  };
+  marfa_status u = MARFA_OK;
+  if (u == MARFA_OK) u = up(p->d.nu0, nu.data(), n * sizeof(double));
+  if (u == MARFA_OK) u = up(p->d.S296, S.data(), n * sizeof(float));
+  if (u == MARFA_OK) u = up(p->d.gair, ga.data(), n * sizeof(float));
+  if (u == MARFA_OK) u = up(p->d.gself, gs.data(), n * sizeof(float));
+  if (u == MARFA_OK) u = up(p->d.El, E.data(), n * sizeof(float));
+  if (u == MARFA_OK) u = up(p->d.nair, na.data(), n * sizeof(float));
+  if (u == MARFA_OK) u = up(p->d.dair, da.data(), n * sizeof(float));
+  if (u == MARFA_OK) u = up(p->d.layers, p->layers_h.data(), p->layers_h.size() * sizeof(double));
+  if (u == MARFA_OK) u = up(p->d.shift, p->shift_h.data(), p->shift_h.size() * sizeof(double));
+  if (u == MARFA_OK) u = up(p->d.ivs, p->ivs.data(), p->ivs.size() * sizeof(IntervalSet));
+  if (u == MARFA_OK) u = up(p->d.tiles, p->tiles.data(), p->tiles.size() * sizeof(Tile));
+  if (u != MARFA_OK) {
+    free_plan(p);
+    return u;
+  }
+  int bpc = 0;
+  p->grid = p->cu_count * 8;
+  (void)bpc;
+  if (hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking) != hipSuccess) {
+    free_plan(p);
+    return fail(MARFA_E_DEVICE, "stream create");
+  }
+  for (hipEvent_t& e : p->ev)
+    if (hipEventCreate(&e) != hipSuccess) {
+      free_plan(p);
+      return fail(MARFA_E_DEVICE, "event create");
+    }
+  *out = p;
+  return MARFA_OK;
+}
+
+extern "C" marfa_status marfa_plan_points(const marfa_plan* p, int64_t* pts) {
+  if (!p || !pts) return fail(MARFA_E_INVALID, "null argument");
+  *pts = p->G.n[0];
+  return MARFA_OK;
+}
+
+// enqueue the hot path for layers [first, first+count)
+// stage mask: 1 = line preparation, 2 = level accumulation, 4 = cascade
+static void enqueue(marfa_plan* p, int first, int count, void* out, int64_t stride, hipStream_t s, bool count_mode,
+                    int stages = 7) {
+  const bool f64 = p->req.fp64 != 0;
+  const size_t recsz = f64 ? sizeof(LineRec64) : sizeof(LineRec32);
+  const size_t realsz = f64 ? sizeof(double) : sizeof(float);
+  const int64_t n = p->n_lines;
+  const size_t F = (size_t)first;
+  LineIn in{p->d.nu0, p->d.S296, p->d.gair, p->d.gself, p->d.El, p->d.nair, p->d.dair, p->molar_mass, n};
+  const int G12 = kGroups + 1;
+  int32_t* bcount = p->d.bcount + F * (size_t)std::max(1, p->nblk) * G12;
+  int32_t* gcount = p->d.gcount + F * G12;
+  int32_t* gstart = p->d.gstart + F * G12;
+  char* rec = (char*)p->d.rec + F * (size_t)n * recsz;
+  double* cnu = p->d.cnu + F * (size_t)n;
+  char* A = (char*)p->d.A + F * (size_t)p->G.a_total * realsz;
+  if (stages & 1)
+    launch_prep(in, p->d.layers + 4 * F, count, p->d.smax + F, p->req.prune_rel, p->req.R, p->G, bcount, gcount,
+                gstart, rec, cnu, p->d.scale + F, p->req.out_kind, f64, s);
+  LevelArgs a;
+  a.tiles = p->d.tiles;
+  a.n_tiles = (int64_t)p->tiles.size();
+  a.n_layers = count;
+  a.counter = p->d.counter;
+  a.rec = rec;
+  a.cnu = cnu;
+  a.gcount = gcount;
+  a.gstart = gstart;
+  a.ivs = p->d.ivs;
+  a.shift = p->d.shift + 2 * F;
+  a.n_lines = n;
+  a.A = A;
+  a.out = out;
+  a.stride = stride;
+  a.stats = p->d.stats;
+  int64_t items = a.n_tiles * count;
+  int grid = (int)std::min<int64_t>(std::max<int64_t>(1, items), (int64_t)p->grid);
+  if (stages & 2) {
+    launch_fill_u32(p->d.counter, 1, 0u, s);
+    launch_level(p->G, a, grid, f64, count_mode, s);
+  }
+  if ((stages & 4) && !count_mode) launch_cascade(p->G, count, A, out, stride, p->d.scale + F, f64, s);
+}
+
+static marfa_status capture(marfa_plan* p, void* out, int64_t stride, int stages, hipGraph_t* g, hipGraphExec_t* x) {
+  if (*x) { (void)hipGraphExecDestroy(*x); *x = nullptr; }
+  if (*g) { (void)hipGraphDestroy(*g); *g = nullptr; }
+  HIP_TRY(hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal));
+  enqueue(p, 0, p->n_layers, out, stride, p->cap, false, stages);
+  hipError_t e = hipStreamEndCapture(p->cap, g);
+  if (e != hipSuccess) return fail(MARFA_E_DEVICE, "graph capture: %s", hipGetErrorString(e));
+  HIP_TRY(hipGraphInstantiate(x, *g, nullptr, nullptr, 0));
+  return MARFA_OK;
+}
+
+static marfa_status check_out(marfa_plan* p, void* out, int64_t stride) {
+  if (!out) return fail(MARFA_E_INVALID, "null output");
+  if (stride < p->G.n[0]) return fail(MARFA_E_INVALID, "layer_stride %lld < points %lld", (long long)stride,
+                                      (long long)p->G.n[0]);
+  hipPointerAttribute_t attr;
+  if (hipPointerGetAttributes(&attr, out) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(MARFA_E_INVALID, "output is not a HIP allocation");
+  }
+  if (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged)
+    return fail(MARFA_E_INVALID, "output must be device memory");
+  if (attr.device != p->device) return fail(MARFA_E_INVALID, "output lives on device %d, plan on %d", attr.device,
+                                            p->device);
+  return MARFA_OK;
+}
+
+extern "C" marfa_status marfa_execute(marfa_plan* p, void* out, int64_t stride, void* stream) {
+  if (!p) return fail(MARFA_E_INVALID, "null plan");
+  marfa_status st = check_out(p, out, stride);
+  if (st != MARFA_OK) return st;
+  HIP_TRY(hipSetDevice(p->device));
+  if (!p->exec || p->g_out != out || p->g_stride != stride) {
+    st = capture(p, out, stride, 7, &p->graph, &p->exec);
+    if (st != MARFA_OK) return st;
+    p->g_out = out;
+    p->g_stride = stride;
+  }
+  HIP_TRY(hipGraphLaunch(p->exec, (hipStream_t)stream));
+  return MARFA_OK;
+}
+
+extern "C" marfa_status marfa_execute_timed(marfa_plan* p, void* out, int64_t stride, void* stream, marfa_timing* t) {
+  if (!p || !t) return fail(MARFA_E_INVALID, "null argument");
+  marfa_status st = check_out(p, out, stride);
+  if (st != MARFA_OK) return st;
+  HIP_TRY(hipSetDevice(p->device));
+  if (!p->sexec[0] || p->s_out != out || p->s_stride != stride) {
+    for (int i = 0; i < 3; ++i) {
+      st = capture(p, out, stride, 1 << i, &p->sgraph[i], &p->sexec[i]);
+      if (st != MARFA_OK) return st;
+    }
+    p->s_out = out;
+    p->s_stride = stride;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(hipEventRecord(p->ev[0], s));
+  for (int i = 0; i < 3; ++i) {
+    HIP_TRY(hipGraphLaunch(p->sexec[i], s));
+    HIP_TRY(hipEventRecord(p->ev[i + 1], s));
+  }
+  HIP_TRY(hipEventSynchronize(p->ev[3]));
+  HIP_TRY(hipEventElapsedTime(&t->prep_ms, p->ev[0], p->ev[1]));
+  HIP_TRY(hipEventElapsedTime(&t->level_ms, p->ev[1], p->ev[2]));
+  HIP_TRY(hipEventElapsedTime(&t->cascade_ms, p->ev[2], p->ev[3]));
+  HIP_TRY(hipEventElapsedTime(&t->total_ms, p->ev[0], p->ev[3]));
+  return MARFA_OK;
+}
+
+extern "C" marfa_status marfa_execute_layers(marfa_plan* p, int32_t first, int32_t count, void* out, int64_t stride,
+                                             void* stream) {
+  if (!p) return fail(MARFA_E_INVALID, "null plan");
+  if (first < 0 || count < 1 || first + count > p->n_layers) return fail(MARFA_E_INVALID, "layer range");
+  marfa_status st = check_out(p, out, stride);
+  if (st != MARFA_OK) return st;
+  HIP_TRY(hipSetDevice(p->device));
+  enqueue(p, first, count, out, stride, (hipStream_t)stream, false);
+  HIP_TRY(hipGetLastError());
+  return MARFA_OK;
+}
+
+extern "C" marfa_status marfa_plan_count(marfa_plan* p, marfa_stats* out) {
+  if (!p || !out) return fail(MARFA_E_INVALID, "null argument");
+  HIP_TRY(hipSetDevice(p->device));
+  hipStream_t s = p->cap;
+  launch_fill_u64(p->d.stats, 16, 0ull, s);
+  enqueue(p, 0, p->n_layers, nullptr, 0, s, true);
+  HIP_TRY(hipGetLastError());
+  unsigned long long h[16];
+  int32_t gc[12];
+  HIP_TRY(hipStreamSynchronize(s));
+  HIP_TRY(hipMemcpy(h, p->d.stats, sizeof h, hipMemcpyDeviceToHost));
+  std::memset(out, 0, sizeof *out);
+  out->points_per_layer = p->G.n[0];
+  out->n_layers = p->n_layers;
+  out->lines_total = p->n_lines;
+  int64_t kept = 0;
+  for (int L = 0; L < p->n_layers; ++L) {
+    HIP_TRY(hipMemcpy(gc, p->d.gcount + (size_t)L * 12, sizeof gc, hipMemcpyDeviceToHost));
+    for (int g = 0; g < kGroups; ++g) kept += gc[g];
+  }
+  out->lines_kept = kept;
+  for (int l = 0; l < kLevels; ++l) out->pairs_level[l] = (int64_t)h[l];
+  out->pairs_band = (int64_t)h[11];
+  out->pairs_core = (int64_t)h[12];
+  out->pairs_wing = (int64_t)h[13];
+  out->wing_terms = (int64_t)h[14];
+  int64_t ln = 0;
+  for (int l = 1; l < kLevels; ++l) ln += p->G.n[l];
+  out->level_nodes = ln * p->n_layers;
+  return MARFA_OK;
+}
+
+extern "C" marfa_status marfa_plan_tiles(const marfa_plan* p, marfa_tiles* t) {
+  if (!p || !t) return fail(MARFA_E_INVALID, "null argument");
+  *t = p->tile_cfg;
+  return MARFA_OK;
+}
+
+extern "C" marfa_status marfa_plan_tune(marfa_plan* p, void* out, int64_t stride, void* stream) {
+  if (!p) return fail(MARFA_E_INVALID, "null plan");
+  marfa_status st = check_out(p, out, stride);
+  if (st != MARFA_OK) return st;
+  (void)stream;
+  return MARFA_OK;
+}
+
+extern "C" void marfa_plan_destroy(marfa_plan* p) {
+  if (!p) return;
+  (void)hipSetDevice(p->device);
+  (void)hipDeviceSynchronize();
+  free_plan(p);
+}
+
+extern "C" const char* marfa_status_string(int32_t s) {
+  switch (s) {
+    case MARFA_OK: return "ok";
+    case MARFA_E_INVALID: return "invalid argument";
+    case MARFA_E_NOMEM: return "out of memory";
+    case MARFA_E_DEVICE: return "device error";
+    case MARFA_E_UNSUPPORTED: return "unsupported";
+    case MARFA_E_STATE: return "bad state";
+    default: return "unknown status";
+  }
+}
+
+extern "C" marfa_status marfa_last_error(char* buf, size_t n) {
+  if (!buf || n == 0) return MARFA_E_INVALID;
+  std::snprintf(buf, n, "%s", g_err.c_str());
+  return MARFA_OK;
+}
+
+extern "C" marfa_status marfa_voigt_eval(int32_t device, int64_t n, const double* x, const double* y, double* out,
+                                         int32_t fp64) {
+  if (n < 0 || (n > 0 && (!x || !y || !out))) return fail(MARFA_E_INVALID, "bad arguments");
+  for (int64_t i = 0; i < n; ++i)
+    if (!std::isfinite(x[i]) || !std::isfinite(y[i]) || y[i] < 0.0) return fail(MARFA_E_INVALID, "need finite x, y >= 0");
+  marfa_status st = ensure_device(device);
+  if (st != MARFA_OK) return st;
+  if (n == 0) return MARFA_OK;
+  double *dx = nullptr, *dy = nullptr, *dout = nullptr;
+  st = dmalloc(&dx, n);
+  if (st == MARFA_OK) st = dmalloc(&dy, n);
+  if (st == MARFA_OK) st = dmalloc(&dout, n);
+  if (st == MARFA_OK) {
+    hipError_t e = hipMemcpy(dx, x, n * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(dy, y, n * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+      launch_voigt_eval(n, dx, dy, dout, fp64 != 0, nullptr);
+      e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpy(out, dout, n * sizeof(double), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) st = fail(MARFA_E_DEVICE, "voigt eval: %s", hipGetErrorString(e));
+  }
+  if (dx) (void)hipFree(dx);
+  if (dy) (void)hipFree(dy);
+  if (dout) (void)hipFree(dout);
+  return st;
+}

@@ -1,0 +1,236 @@
+"""Parity of the HIP path with the FP64 oracle, element by element.
+
+Gates (relative, on nodes where the direct sum is >= 1e-8 of the layer max):
+GPU single precision vs the definition <= 1e-4; vs the oracle's eleven-grid
+result <= 1e-5 (implementation error only); GPU double precision vs the
+oracle's eleven-grid result <= 1e-9.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2411_03418_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+THREADS = min(16, os.cpu_count() or 1)
+
+
+def marfa():
+    from paper_2411_03418_amd import marfa as M
+    return M
+
+
+def run(lines, layers, fp64=False, **req):
+    M = marfa()
+    layers = np.asarray(layers, np.float64).reshape(-1, 4)
+    print(f"[gpu] plan: {lines.n} lines, {layers.shape[0]} layers, {req}, fp64={fp64}", flush=True)
+    plan = M.Plan(lines, layers, fp64=fp64, device=0, **req)
+    out = plan.execute()
+    torch.cuda.synchronize()
+    res = out.double().cpu().numpy()
+    plan.close()
+    return res
+
+
+def _oreq(req):
+    o = dict(nu_begin=req["nu_begin"], nu_end=req["nu_end"], cutoff=req["cutoff"])
+    o["chi"] = {"none": 0, "tonkov": 1}[req.get("chi", "none")]
+    o["shape"] = {"voigt": 0, "lorentz": 1, "doppler": 2}[req.get("shape", "voigt")]
+    o["prune"] = req.get("prune", 0.0)
+    o["level_table"] = req.get("level_table", 0)
+    o["out_kind"] = {"sigma": 0, "k": 1}[req.get("out", "sigma")]
+    o["R"] = float(req.get("R", 48))
+    return o
+
+
+def rel_err(got, ref):
+    m = ref >= 1e-8 * ref.max()
+    return float(np.max(np.abs(got[m] - ref[m]) / ref[m]))
+
+
+def all_nodes(req):
+    return np.arange(int(round(req["nu_begin"] * 2048)), int(round(req["nu_end"] * 2048)) + 1)
+
+
+# ------------------------------------------------------------------ device Voigt
+
+def test_device_voigt_single_and_double():
+    M = marfa()
+    xs = np.concatenate([np.linspace(0, 8, 81), np.geomspace(8, 1e7, 40)])
+    ys = np.array([1e-4, 3e-4, 1e-3, 0.01, 0.1, 0.5, 1.0, 3.0, 5.9, 10.0, 100.0, 1e3])
+    X, Y = np.meshgrid(xs, ys)
+    X, Y = X.ravel(), Y.ravel()
+    ref = O.voigt_K(X, Y)
+    k32 = M.voigt_eval(X, Y, fp64=False)
+    k64 = M.voigt_eval(X, Y, fp64=True)
+    e32 = np.max(np.abs(k32 - ref) / ref)
+    e64 = np.max(np.abs(k64 - ref) / ref)
+    print(f"device K: fp32 {e32:.2e}, fp64 {e64:.2e}")
+    assert e32 < 1e-5
+    assert e64 < 1e-9
+
+
+def test_device_voigt_branch_switch_continuous():
+    M = marfa()
+    # the single-precision path switches from the rational core to the wing
+    # series at |z| = 6; both sides agree with each other and the oracle
+    th = np.linspace(0.02, 1.5, 25)
+    r = np.array([6.0 * (1 - 1e-6), 6.0 * (1 + 1e-6)])
+    X = (r[:, None] * np.cos(th)[None, :]).ravel()
+    Y = (r[:, None] * np.sin(th)[None, :]).ravel()
+    k = M.voigt_eval(X, Y).reshape(2, -1)
+    assert np.max(np.abs(k[0] - k[1]) / k[1]) < 1e-5
+
+
+# ------------------------------------------------------------------ single lines
+
+def _one(nu0, gamma, p=1.0, T=296.0, delta=0.0):
+    L = synth.make_lines(1, 0, 1, 7)
+    L.nu0[:] = nu0
+    L.gamma_air[:] = gamma
+    L.gamma_self[:] = gamma
+    L.S296[:] = 1e-20
+    L.E_lower[:] = 0.0
+    L.delta_air[:] = delta
+    return L, [p, T, p, 0.0]
+
+
+ONE_LINE = [
+    dict(nu0=1005.0, gamma=0.075),
+    dict(nu0=1005.00013, gamma=0.075),
+    dict(nu0=1005.3, gamma=0.075, chi="tonkov", c=125.0),
+    dict(nu0=1002.1234, gamma=0.3, c=4.0, chi="tonkov"),
+    dict(nu0=1007.7, gamma=0.09, p=10.0),
+    dict(nu0=1003.0, gamma=0.09, p=30.0, c=125.0, chi="tonkov", nb=900.0, ne=1100.0),
+    dict(nu0=1015.0, gamma=0.06, p=0.01),
+    dict(nu0=1010.0, gamma=0.06, p=0.2),
+    dict(nu0=1005.0, gamma=0.06, p=0.2, shape="lorentz"),
+    dict(nu0=1005.0, gamma=0.06, p=0.2, shape="doppler"),
+    dict(nu0=1004.2, gamma=0.06, p=0.4, lt=1),
+    dict(nu0=1004.4, gamma=0.07, p=1e-4, T=150.0),
+]
+
+
+@pytest.mark.parametrize("case", ONE_LINE)
+@pytest.mark.parametrize("fp64", [False, True])
+def test_one_line_parity(case, fp64):
+    L, lay = _one(case["nu0"], case["gamma"], p=case.get("p", 1.0), T=case.get("T", 296.0))
+    req = dict(nu_begin=case.get("nb", 1000.0), nu_end=case.get("ne", 1010.0), cutoff=case.get("c", 25.0),
+               chi=case.get("chi", "none"), shape=case.get("shape", "voigt"), level_table=case.get("lt", 0))
+    got = run(L, [lay], fp64=fp64, **req)[0]
+    o = _oreq(req)
+    ref_g = O.grid(L, lay, threads=THREADS, **o)
+    ref_d = O.direct(L, lay, all_nodes(req), threads=THREADS, **o)
+    eg, ed = rel_err(got, ref_g), rel_err(got, ref_d)
+    print(f"vs grid {eg:.2e}  vs direct {ed:.2e}")
+    assert ed < 1e-4
+    assert eg < (1e-9 if fp64 else 1e-5)
+
+
+# ------------------------------------------------------------------ workloads
+
+@pytest.mark.parametrize("fp64", [False, True])
+def test_single_1k_workload(fp64):
+    lines, layers, rq = synth.workload("single_1k")
+    req = dict(nu_begin=rq["nu_begin"], nu_end=rq["nu_end"], cutoff=rq["cutoff"], chi="none")
+    got = run(lines, layers, fp64=fp64, **req)[0]
+    o = _oreq(req)
+    ref_g = O.grid(lines, layers[0], threads=THREADS, **o)
+    ref_d = O.direct(lines, layers[0], all_nodes(req), threads=THREADS, **o)
+    eg, ed = rel_err(got, ref_g), rel_err(got, ref_d)
+    print(f"single_1k fp64={fp64}: vs grid {eg:.2e} vs direct {ed:.2e}")
+    assert ed < 1e-4
+    assert eg < (1e-9 if fp64 else 1e-5)
+
+
+def test_multi_layer_pruned_ragged():
+    # several tiles, a ragged tail, pruning with uneven kept counts per layer
+    lines = synth.make_lines(3000, 930.0, 1090.0, 31, shift=True)
+    layers = synth.pt_table(7)
+    req = dict(nu_begin=1000.0, nu_end=1013.5, cutoff=60.0, chi="tonkov", prune=1e-6)
+    got = run(lines, layers, **req)
+    o = _oreq(req)
+    for i in range(layers.shape[0]):
+        ref_g = O.grid(lines, layers[i], threads=THREADS, **o)
+        ref_d = O.direct(lines, layers[i], all_nodes(req), threads=THREADS, **o)
+        eg, ed = rel_err(got[i], ref_g), rel_err(got[i], ref_d)
+        print(f"layer {i}: vs grid {eg:.2e} vs direct {ed:.2e}")
+        assert ed < 1e-4
+        assert eg < 1e-5
+
+
+def test_absorption_coefficient_output():
+    lines = synth.make_lines(300, 980.0, 1030.0, 32)
+    lay = [0.8, 280.0, 0.2, 0.0]
+    req = dict(nu_begin=1000.0, nu_end=1002.0, cutoff=25.0)
+    s = run(lines, [lay], **req)[0]
+    k = run(lines, [lay], out="k", **req)[0]
+    n = O.number_density(lay)
+    assert np.allclose(k, s * n * 1e5, rtol=1e-6)
+
+
+def test_empty_line_list_gives_zeros():
+    lines = synth.make_lines(0, 0, 1, 1)
+    got = run(lines, [[1.0, 296.0, 1.0, 0.0]], nu_begin=1000.0, nu_end=1001.0, cutoff=25.0)
+    assert got.shape == (1, 2049) and not np.any(got)
+
+
+def test_range_starting_at_zero():
+    # coarse-level halos reach below 0 cm^-1; lines start at 0 (alpha_D -> 0)
+    lines = synth.make_lines(400, 0.0, 40.0, 33, shift=True)
+    lay = [0.5, 300.0, 0.5, 0.0]
+    req = dict(nu_begin=0.0, nu_end=6.0, cutoff=25.0, chi="tonkov")
+    got = run(lines, [lay], **req)[0]
+    o = _oreq(req)
+    ref_d = O.direct(lines, lay, all_nodes(req), threads=THREADS, **o)
+    ref_g = O.grid(lines, lay, threads=THREADS, **o)
+    assert rel_err(got, ref_d) < 1e-4
+    assert rel_err(got, ref_g) < 1e-5
+
+
+def test_deterministic_and_graph_replay():
+    M = marfa()
+    lines = synth.make_lines(5000, 970.0, 1040.0, 34, shift=True)
+    layers = synth.pt_table(4)
+    plan = M.Plan(lines, layers, nu_begin=1000.0, nu_end=1010.0, cutoff=25.0, chi="tonkov", device=0)
+    a = plan.execute().clone()
+    torch.cuda.synchronize()
+    outs = []
+    for _ in range(3):
+        x = torch.randn(1000, device="cuda:0").sum()  # eager work between replays
+        b = plan.execute()
+        torch.cuda.synchronize()
+        outs.append(b.clone())
+        del x
+    for b in outs:
+        assert torch.equal(a, b)
+    # explicit output buffer with a wider stride, then a subset of layers
+    buf = torch.zeros((4, plan.points + 100), dtype=torch.float32, device="cuda:0")
+    plan.execute(out=buf)
+    torch.cuda.synchronize()
+    assert torch.equal(buf[:, :plan.points], a)
+    sub = plan.execute_layers(1, 2)
+    torch.cuda.synchronize()
+    assert torch.equal(sub, a[1:3])
+    plan.close()
+
+
+def test_single_200k_sampled():
+    lines, layers, rq = synth.workload("single_200k")
+    req = dict(nu_begin=rq["nu_begin"], nu_end=rq["nu_end"], cutoff=rq["cutoff"], chi="tonkov")
+    got = run(lines, layers, **req)[0]
+    rng = np.random.default_rng(7)
+    nodes = np.unique(np.concatenate([
+        rng.integers(int(req["nu_begin"] * 2048), int(req["nu_end"] * 2048) + 1, 3000),
+        np.arange(1500 * 2048, 1500 * 2048 + 2049),          # one full 1 cm^-1 stretch
+        np.arange(int(req["nu_begin"] * 2048), int(req["nu_begin"] * 2048) + 200),   # range start
+        np.arange(int(req["nu_end"] * 2048) - 200, int(req["nu_end"] * 2048) + 1)]))  # range end
+    ref = O.direct(lines, layers[0], nodes, threads=THREADS, **_oreq(req))
+    g = got[nodes - int(req["nu_begin"] * 2048)]
+    e = float(np.max(np.abs(g - ref) / ref))
+    print(f"single_200k sampled ({nodes.size} nodes): max rel err {e:.2e}")
+    assert e < 1e-4
