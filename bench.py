@@ -156,7 +156,9 @@ def main():
                       "graph_total": float(np.mean(tot))},
         "pairs": {"total": int(sum(st["pairs_level"])), "core": int(st["pairs_core"]),
                   "wing": int(st["pairs_wing"]), "band": int(st["pairs_band"]),
-                  "per_level": [int(v) for v in st["pairs_level"]]},
+                  "per_level": [int(v) for v in st["pairs_level"]],
+                  "wave_iters_per_level": [int(v) for v in st["iters_level"]],
+                  "band_iters_per_level": [int(v) for v in st["band_iters_level"]]},
     }
     line.update(res)
     plan.close()

@@ -105,6 +105,8 @@ typedef struct {
   int64_t pairs_band;             /* pairs carrying a residual-band correction */
   int64_t wing_terms;             /* sum over wing pairs of series terms beyond the first */
   int64_t level_nodes;            /* nodes of levels 1..10 over all layers */
+  int64_t iters_level[11];        /* wavefront iterations over line windows, per level */
+  int64_t band_iters_level[11];   /* of which ran a residual-band correction */
 } marfa_stats;
 
 /* Create a plan: validates and copies the inputs, sorts lines by nu0, uploads

@@ -361,9 +361,9 @@ int orc_direct(const orc_lines* L, const orc_layer* lay, const orc_request* rq,
 /* < b_l, level 10 holds up to the cut-off.  T_l(d) is the part of the  */
 /* line that level l and all coarser levels together represent.  Level  */
 /* l receives D_l(m) = T_l(d_m) - sum_i w_i T_(l+1)(d_(m_i)) on its      */
-/* region and on bands of half-width 2 h_(l+1) around every jump of      */
-/* T_(l+1) (its inner edge, the cut-off, chi breakpoints); elsewhere     */
-/* D_l is the interpolation error of a smooth function and is dropped.   */
+/* region and on the nodes whose stencil straddles a jump of T_(l+1)     */
+/* (its inner edge, the cut-off, chi breakpoints); elsewhere D_l is the  */
+/* interpolation error of a smooth function and is dropped.              */
 /* Cascade: A_10 = sum D_10, A_l = sum D_l + P(A_(l+1)), sigma = A_0.   */
 /* P is the 3-point Lagrange interpolation on the nearest coarse node    */
 /* (ties to the lower one), injection at coinciding nodes.              */
@@ -479,6 +479,22 @@ static int stencil(const grid_geom* G, int l, int64_t m, int64_t* k, double* w) 
   return 3;
 }
 
+/* Does the 3-point stencil of node m (level l) straddle a jump of T_(l+1)?
+ * True when some jump point q lies in the closed |d| hull of the stencil's
+ * coarse nodes; only there does interpolating T_(l+1) smear a jump. */
+static int straddles(const grid_geom* G, const gline* ln, int l, int64_t m, const double* q, int nq) {
+  int64_t k[3];
+  double w[3];
+  if (stencil(G, l, m, k, w) != 3) return 0;
+  double d0 = (double)k[0] * G->h[l + 1] - ln->nu;
+  double d2 = (double)k[2] * G->h[l + 1] - ln->nu;
+  double lo = (d0 * d2 <= 0.0) ? 0.0 : fmin(fabs(d0), fabs(d2));
+  double hi = fmax(fabs(d0), fabs(d2));
+  for (int i = 0; i < nq; ++i)
+    if (q[i] >= lo && q[i] <= hi) return 1;
+  return 0;
+}
+
 /* the line's D_l at node m (level l) */
 static double D_at(const grid_geom* G, const gline* ln, int l, int64_t m) {
   double d = (double)m * G->h[l] - ln->nu;
@@ -539,8 +555,7 @@ static void add_line(const grid_geom* G, const gline* ln, double* const* A) {
         double d = (double)m * h - ln->nu;
         double ad = fabs(d);
         int use = in_region(G, ln, l, ad);
-        for (int k = 0; k < nq && !use; ++k)
-          if (fabs(ad - q[k]) <= G->B[l]) use = 1;
+        if (!use && nq > 0) use = straddles(G, ln, l, m, q, nq);
         if (use) A[l][m - G->lo[l]] += D_at(G, ln, l, m);
       }
       if (iv[i].b + 1 > cur) cur = iv[i].b + 1;

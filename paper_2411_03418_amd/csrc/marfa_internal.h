@@ -10,38 +10,61 @@ namespace marfa {
 
 constexpr int kLevels = 11;      // Section 2.4: eleven grids
 constexpr int kGroups = 11;      // lines grouped by start level 0..10
-constexpr int kMaxIntervals = 6; // disjoint |d| intervals per (level, start level)
+constexpr int kMaxIntervals = 8; // disjoint |d| windows per (level, start-level classes)
 constexpr int kMaxJumps = 5;     // jump points of T_(l+1) per (level, start level)
 constexpr int kWave = 64;        // CDNA wavefront
 constexpr int kWeidemanN32 = 32; // rational-series length, single-precision path
 constexpr int kWeidemanN64 = 48; // rational-series length, double-precision path
+constexpr int kBucketPerCm = 256; // line-index buckets per cm^-1 (8 finest steps)
 
 // Lattice geometry, identical for every layer.  Positions are in units of the
 // finest step h0 = 2^-11 cm^-1 ("fine units"); node m of level l sits at
 // X = m * r[l].
 struct Geometry {
   int32_t r[kLevels];        // level step in fine units
+  int32_t lnw[kLevels];      // log2 of nodes per wavefront tile (lanes = nodes x line slices)
   int64_t lo[kLevels];       // first node index of each level (incl. halo)
   int64_t n[kLevels];        // nodes per level
   int64_t aoff[kLevels];     // offset of level l >= 1 in a layer's level array
   int64_t a_total;           // level-array length per layer (levels 1..10)
   double b[kLevels];         // region boundary b_l = R r_(l+1), fine units (l < 10)
-  double B[kLevels];         // band half-width 2 r_(l+1), fine units (l < 10)
+  double hb[kLevels];        // band reach 1.5 r_(l+1) + 1, fine units (l < 10)
   double c_fine;             // cut-off in fine units
+  // jump points of T_(l+1) for lines starting at or below l (q1) and above l (q2)
+  double q1[kLevels][kMaxJumps], q2[kLevels][kMaxJumps];
+  int32_t nq1[kLevels], nq2[kLevels];
   int32_t shape, chi, out_kind, fp64;
+  int32_t nbucket;           // buckets of the per-layer line index (kBucketPerCm per cm^-1)
+  int32_t pad;
+  double bucket_origin;      // wavenumber of bucket 0 [cm^-1] (below every shifted centre)
+  int32_t ncoarse;           // 1 cm^-1 buckets of the coarse line index
+  int32_t pad2;
+  // wing series: term k is needed while e >= eterm[k] (single, double precision)
+  float eterm32[16];
+  double eterm64[64];
+  // Tonkov chi pieces as exp2(chi_c0[i] + chi_c1[i] |d|), |d| in cm (host-computed)
+  double chi_c0[3], chi_c1[3];
 };
 
-// For one (level l, start level s): the |d| intervals (fine units, closed)
-// that can hold a non-zero contribution, and the jump points of T_(l+1).
+// Region windows (|d| in fine units, closed, disjoint) scanned at one level
+// for one combination of start-level classes present in a layer (bit 0: lines
+// with s < l, bit 1: s == l, bit 2: s > l), and the jumps of T_(l+1) that the
+// residual-band pass corrects.
 struct IntervalSet {
   int32_t n_iv;
-  int32_t n_q;
+  int32_t n_jump;
   double a[kMaxIntervals], b[kMaxIntervals];
-  double q[kMaxJumps];
+  // chi over the whole window: exp2(c0 + c1 |d|) (fine units), or chi_mixed = 1
+  double chi_c0[kMaxIntervals], chi_c1[kMaxIntervals];
+  int32_t chi_mixed[kMaxIntervals];
+  // jumps of T_(l+1), ascending, with the classes of lines they apply to
+  // (bit 0: start level <= l, bit 1: start level > l)
+  double jq[kMaxJumps];
+  int32_t jmask[kMaxJumps];
 };
 
 // One work item of the level kernel: `count` consecutive nodes of one level,
-// processed by one workgroup in wavefront-sized sub-tiles.
+// processed by one workgroup in wavefront tiles.
 struct Tile {
   int32_t level;
   int32_t count;
@@ -55,15 +78,15 @@ struct LineRec32 {
   float Sp;       // S(T) / max S(T) of the layer
   float gam;      // gamma_L [cm^-1]
   float gam2;     // gamma_L^2
-  float ae;       // alpha_D^2 / (2 ln 2)
+  float ae;       // alpha_D^2 / (2 ln 2); the core branch holds for d^2 + gamma_L^2 < 72 ae
   float xs;       // sqrt(ln 2) / alpha_D, 0 when alpha_D = 0
-  float aD;       // alpha_D [cm^-1]
+  int32_t s;      // start level
 };
 
 struct LineRec64 {
   int32_t k0;
-  int32_t pad;
-  double frac, Sp, gam, gam2, ae, xs, aD;
+  int32_t s;
+  double frac, Sp, gam, gam2, ae, xs;
 };
 
 // Device-side workspace of a plan.
@@ -78,17 +101,21 @@ struct DeviceBuffers {
   float* dair = nullptr;
   double* layers = nullptr;        // [n_layers][4] p, T, p_self, q_ratio
   unsigned long long* smax = nullptr;  // [n_layers] bits of max S(T) (FP64)
-  int32_t* bcount = nullptr;       // [n_layers][n_blocks][12]
-  int32_t* gcount = nullptr;       // [n_layers][12]
-  int32_t* gstart = nullptr;       // [n_layers][12]
-  void* rec = nullptr;             // [n_layers][n_lines] LineRec32/64
-  double* cnu = nullptr;           // [n_layers][n_lines] nu0 of compacted lines
+  int32_t* bcount = nullptr;       // [n_layers][n_blocks] kept lines per block -> offsets
+  int32_t* scount = nullptr;       // [n_layers][n_blocks][12] lines per start level (12 = dropped)
+  int32_t* kept = nullptr;         // [n_layers] kept lines
+  int32_t* gcount = nullptr;       // [n_layers][12] lines per start level
+  void* rec = nullptr;             // [n_layers][n_lines] LineRec32/64, kept lines in nu0 order
+  double* cnu = nullptr;           // [n_layers][n_lines] shifted centre of the kept lines
+  int32_t* bucket = nullptr;       // [n_layers][nbucket+1] first kept line with nu~0 >= origin + b/kBucketPerCm
+  int32_t* coarse = nullptr;       // [n_layers][ncoarse+1] first kept line with nu~0 >= origin + b (cm)
   void* A = nullptr;               // [n_layers][a_total] level arrays 1..10
-  IntervalSet* ivs = nullptr;      // [11][11]
-  Tile* tiles = nullptr;           // [n_tiles] sorted heaviest first
+  IntervalSet* ivs = nullptr;      // [11][8]
+  Tile* tiles = nullptr;           // [n_tiles] heaviest first
   unsigned int* counter = nullptr; // work-queue counter
   double* scale = nullptr;         // [n_layers] output scale
-  double* shift = nullptr;         // [n_layers][2] nu0 - nu~0 range [cm^-1]
+  double* span = nullptr;          // [n_layers] max |(delta_i - delta_j) p| [cm^-1]
+  int32_t* perm = nullptr;         // [n_layers][n_lines] line indices in order of shifted centre
   unsigned long long* stats = nullptr;  // counters for marfa_plan_count
 };
 
@@ -107,25 +134,34 @@ struct LevelArgs {
   int32_t n_layers;
   unsigned int* counter; // work-queue counter (cleared before each launch)
   const void* rec;       // [layer][line] LineRec32/64
-  const double* cnu;     // [layer][line] nu0 of the compacted lines
+  const int32_t* bucket; // [layer][nbucket+1]
   const int32_t* gcount; // [layer][12]
-  const int32_t* gstart; // [layer][12]
   const IntervalSet* ivs;
-  const double* shift;   // [layer][2] range of nu~0 - nu0 [cm^-1]
   int64_t n_lines;
   void* A;               // [layer][a_total]
   void* out;             // [layer][stride]
   int64_t stride;
   unsigned long long* stats;  // counting mode only
+  int32_t max_item;      // largest work item (nodes), sizes the LDS accumulator
 };
 
 hipError_t upload_weideman(const double* a32, const double* a64, const double* L2);
 void launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t s);
 void launch_fill_u32(unsigned int* p, int64_t n, unsigned int v, hipStream_t s);
-void launch_prep(const LineIn& in, const double* layers, int nL, unsigned long long* smax, double prune, double R,
-                 const Geometry& G, int32_t* bcount, int32_t* gcount, int32_t* gstart, void* rec, double* cnu,
-                 double* scale, int out_kind, bool fp64, hipStream_t s);
+struct PrepArgs {
+  const int32_t* perm;   // [layer][line] order of shifted centres
+  unsigned long long* smax;
+  int32_t *bcount, *scount, *kept, *gcount, *bucket, *coarse;
+  void* rec;
+  double* cnu;
+  double* scale;
+  double prune, R;
+  int32_t out_kind, fp64;
+};
+void launch_prep(const LineIn& in, const double* layers, int nL, const Geometry& G, const PrepArgs& pa,
+                 hipStream_t s);
 void launch_level(const Geometry& G, const LevelArgs& a, int grid, bool fp64, bool count, hipStream_t s);
+void launch_rank(const LineIn& in, const double* layers, int nL, const double* span, int32_t* perm, hipStream_t s);
 void launch_cascade(const Geometry& G, int nL, void* A, void* out, int64_t stride, const double* scale, bool fp64,
                     hipStream_t s);
 void launch_voigt_eval(int64_t n, const double* x, const double* y, double* out, bool fp64, hipStream_t s);

@@ -129,6 +129,8 @@ __device__ __forceinline__ R tonkov(R a) {
 
 struct Counts {
   uint32_t core, wing, terms;
+  uint32_t iters;        // wavefront iterations over line windows (lane 0 counts)
+  uint32_t band_iters;   // iterations that ran the band correction
 };
 
 // g(d) = S' F(d) chi(|d|) [|d| <= c], d in fine units
@@ -230,96 +232,94 @@ __device__ __forceinline__ int start_level(double w, double R, const Geometry& G
   return s;
 }
 
+// start level of a kept line, kGroups if pruned
 __device__ __forceinline__ int line_key(const LineIn& in, int64_t j, const double* lay, double smax,
                                         double prune, double R, const Geometry& G, LineState& st) {
   st = line_state(in, j, lay);
   bool keep = prune <= 0.0 || st.S >= prune * smax;
-  if (!keep) return kGroups;  // dropped
+  if (!keep) return kGroups;
   return start_level(fmax(st.gL, st.aD), R, G);
 }
 
-__global__ void k_prep_count(LineIn in, const double* __restrict__ layers, const unsigned long long* smax,
-                             double prune, double R, Geometry G, int32_t* bcount, int nblk) {
+__global__ void k_prep_count(LineIn in, const double* __restrict__ layers, Geometry G, PrepArgs pa, int nblk) {
   __shared__ int cnt[kGroups + 1];
   if (threadIdx.x <= kGroups) cnt[threadIdx.x] = 0;
   __syncthreads();
-  int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   int L = blockIdx.y;
-  if (j < in.n) {
+  if (i < in.n) {
+    const int64_t j = pa.perm[(int64_t)L * in.n + i];
     LineState st;
-    int key = line_key(in, j, layers + 4 * L, __longlong_as_double((long long)smax[L]), prune, R, G, st);
+    int key = line_key(in, j, layers + 4 * L, __longlong_as_double((long long)pa.smax[L]), pa.prune, pa.R, G, st);
     atomicAdd(&cnt[key], 1);
   }
   __syncthreads();
-  if (threadIdx.x <= kGroups)
-    bcount[((int64_t)L * nblk + blockIdx.x) * (kGroups + 1) + threadIdx.x] = cnt[threadIdx.x];
+  int64_t blk = (int64_t)L * nblk + blockIdx.x;
+  if (threadIdx.x <= kGroups) pa.scount[blk * (kGroups + 1) + threadIdx.x] = cnt[threadIdx.x];
+  if (threadIdx.x == 0) {
+    int k = 0;
+    for (int g = 0; g < kGroups; ++g) k += cnt[g];
+    pa.bcount[blk] = k;
+  }
 }
 
-// exclusive offsets per (layer, group) over blocks, in place; group totals and starts
-__global__ void k_prep_scan(int32_t* bcount, int nblk, int32_t* gcount, int32_t* gstart) {
+// exclusive offsets of kept lines over blocks (in place), kept totals, and
+// lines per start level of each layer
+__global__ void k_prep_scan(PrepArgs pa, int nblk) {
   __shared__ int part[256];
-  __shared__ int tot[kGroups + 1];
   int L = blockIdx.x;
   int t = threadIdx.x;
   int chunk = (nblk + 255) / 256;
   int b0 = t * chunk, b1 = min(nblk, b0 + chunk);
-  for (int g = 0; g <= kGroups; ++g) {
-    int s = 0;
-    for (int b = b0; b < b1; ++b) s += bcount[((int64_t)L * nblk + b) * (kGroups + 1) + g];
-    part[t] = s;
+  int s = 0;
+  for (int b = b0; b < b1; ++b) s += pa.bcount[(int64_t)L * nblk + b];
+  part[t] = s;
+  __syncthreads();
+  for (int o = 1; o < 256; o <<= 1) {
+    int v = (t >= o) ? part[t - o] : 0;
     __syncthreads();
-    // Hillis-Steele inclusive scan
-    for (int o = 1; o < 256; o <<= 1) {
-      int v = (t >= o) ? part[t - o] : 0;
-      __syncthreads();
-      part[t] += v;
-      __syncthreads();
-    }
-    int run = part[t] - s;
-    for (int b = b0; b < b1; ++b) {
-      int64_t k = ((int64_t)L * nblk + b) * (kGroups + 1) + g;
-      int v = bcount[k];
-      bcount[k] = run;
-      run += v;
-    }
-    if (t == 255) tot[g] = part[255];
+    part[t] += v;
     __syncthreads();
   }
-  if (t == 0) {
-    int run = 0;
-    for (int g = 0; g <= kGroups; ++g) {
-      gcount[L * (kGroups + 1) + g] = tot[g];
-      gstart[L * (kGroups + 1) + g] = run;
-      run += tot[g];
-    }
+  int run = part[t] - s;
+  for (int b = b0; b < b1; ++b) {
+    int64_t k = (int64_t)L * nblk + b;
+    int v = pa.bcount[k];
+    pa.bcount[k] = run;
+    run += v;
+  }
+  if (t == 255) pa.kept[L] = part[255];
+  if (t <= kGroups) {
+    int c = 0;
+    for (int b = 0; b < nblk; ++b) c += pa.scount[((int64_t)L * nblk + b) * (kGroups + 1) + t];
+    pa.gcount[L * (kGroups + 1) + t] = c;
   }
 }
 
 template <typename R>
-__global__ void k_prep_scatter(LineIn in, const double* __restrict__ layers, const unsigned long long* smax,
-                               double prune, double R_, Geometry G, const int32_t* bcount, int nblk,
-                               const int32_t* gstart, typename RecOf<R>::T* rec, double* cnu) {
-  __shared__ int wcnt[4][kGroups + 1];
-  int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+__global__ void k_prep_scatter(LineIn in, const double* __restrict__ layers, Geometry G, PrepArgs pa, int nblk) {
+  __shared__ int wcnt[4];
+  int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   int L = blockIdx.y;
   int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  double sm = __longlong_as_double((long long)smax[L]);
-  int key = kGroups + 1;  // out of range: not a line
+  double sm = __longlong_as_double((long long)pa.smax[L]);
+  int key = kGroups;
   LineState st{0, 0, 0, 0};
-  if (j < in.n) key = line_key(in, j, layers + 4 * L, sm, prune, R_, G, st);
-  unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  int rank = 0;
-  for (int g = 0; g <= kGroups; ++g) {
-    unsigned long long m = __ballot(key == g);
-    if (key == g) rank = __popcll(m & lt);
-    if (lane == 0) wcnt[wv][g] = __popcll(m);
+  int64_t j = 0;
+  if (i < in.n) {
+    j = pa.perm[(int64_t)L * in.n + i];
+    key = line_key(in, j, layers + 4 * L, sm, pa.prune, pa.R, G, st);
   }
+  bool keep = key < kGroups;
+  unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  unsigned long long m = __ballot(keep);
+  int rank = __popcll(m & lt);
+  if (lane == 0) wcnt[wv] = __popcll(m);
   __syncthreads();
-  if (key >= kGroups) return;
+  if (!keep) return;
   int off = rank;
-  for (int w = 0; w < wv; ++w) off += wcnt[w][key];
-  int64_t dest = (int64_t)gstart[L * (kGroups + 1) + key] +
-                 bcount[((int64_t)L * nblk + blockIdx.x) * (kGroups + 1) + key] + off;
+  for (int w = 0; w < wv; ++w) off += wcnt[w];
+  int64_t dest = (int64_t)pa.bcount[(int64_t)L * nblk + blockIdx.x] + off;
   int64_t base = (int64_t)L * in.n;
   // FP64 placement of the shifted centre on the finest lattice
   double t = st.nut * 2048.0;
@@ -332,11 +332,75 @@ __global__ void k_prep_scatter(LineIn in, const double* __restrict__ layers, con
   r.Sp = sm > 0.0 ? R(st.S / sm) : R(0);
   r.gam = R(st.gL);
   r.gam2 = R(st.gL * st.gL);
-  r.ae = R(st.aD * st.aD / (2.0 * kLn2d));
-  r.xs = st.aD > 0.0 ? R(sqrt(kLn2d) / st.aD) : R(0);
-  r.aD = R(st.aD);
-  rec[base + dest] = r;
-  cnu[base + dest] = in.nu0[j];
+  // the Lorentz shape is the Voigt wing with alpha_D = 0
+  const bool lor = G.shape == MARFA_SHAPE_LORENTZ;
+  r.ae = lor ? R(0) : R(st.aD * st.aD / (2.0 * kLn2d));
+  r.xs = (st.aD > 0.0 && !lor) ? R(sqrt(kLn2d) / st.aD) : R(0);
+  r.s = key;
+  reinterpret_cast<typename RecOf<R>::T*>(pa.rec)[base + dest] = r;
+  pa.cnu[base + dest] = st.nut;
+}
+
+// coarse[c] = first kept line with nu~0 >= origin + c (1 cm^-1 buckets, per
+// layer): each line fills the buckets between its predecessor's and its own
+__global__ void k_prep_coarse(int64_t n_lines, Geometry G, PrepArgs pa) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int L = blockIdx.y;
+  const int64_t kept = pa.kept[L];
+  const double* cnu = pa.cnu + (int64_t)L * n_lines;
+  int32_t* co = pa.coarse + (int64_t)L * (G.ncoarse + 1);
+  const int64_t nc = G.ncoarse;
+  if (i > kept) return;
+  int64_t prev = (i == 0) ? -1 : (int64_t)floor(cnu[i - 1] - G.bucket_origin);
+  int64_t cur = (i == kept) ? nc : (int64_t)floor(cnu[i] - G.bucket_origin);
+  if (cur > nc) cur = nc;
+  for (int64_t b = prev + 1; b <= cur; ++b) co[b] = (int32_t)i;
+}
+
+// bucket[b] = first kept line with nu~0 >= origin + b / kBucketPerCm: a short
+// binary search inside the bucket's 1 cm^-1 coarse bucket
+__global__ void k_prep_bucket(int64_t n_lines, Geometry G, PrepArgs pa) {
+  int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int L = blockIdx.y;
+  if (b > G.nbucket) return;
+  const int64_t kept = pa.kept[L];
+  const double* cnu = pa.cnu + (int64_t)L * n_lines;
+  const int32_t* co = pa.coarse + (int64_t)L * (G.ncoarse + 1);
+  int32_t* bk = pa.bucket + (int64_t)L * (G.nbucket + 1);
+  if (b == G.nbucket) { bk[b] = (int32_t)kept; return; }
+  const int64_t c = b / kBucketPerCm;
+  int64_t lo = co[c < G.ncoarse ? c : G.ncoarse];
+  int64_t hi = co[c + 1 < G.ncoarse ? c + 1 : G.ncoarse];
+  const double v = G.bucket_origin + (double)b / kBucketPerCm;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (cnu[mid] < v) lo = mid + 1; else hi = mid;
+  }
+  bk[b] = (int32_t)lo;
+}
+
+// Position of line i in the order of shifted centres nu~0 = nu0 + delta p
+// (ties by index).  Lines are sorted by nu0 and |(delta_i - delta_j) p| <=
+// span, so only neighbours within span of nu0 can change places.
+__global__ void k_rank(LineIn in, const double* __restrict__ layers, const double* __restrict__ span,
+                       int32_t* perm) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int L = blockIdx.y;
+  if (i >= in.n) return;
+  const double p = layers[4 * L];
+  const double sp = span[L];
+  const double ni = in.nu0[i];
+  const double ti = ni + (double)in.dair[i] * p;
+  int64_t rank = i;
+  for (int64_t j = i + 1; j < in.n && in.nu0[j] <= ni + sp; ++j) {
+    const double tj = in.nu0[j] + (double)in.dair[j] * p;
+    if (tj < ti) ++rank;
+  }
+  for (int64_t j = i - 1; j >= 0 && in.nu0[j] >= ni - sp; --j) {
+    const double tj = in.nu0[j] + (double)in.dair[j] * p;
+    if (tj > ti) --rank;
+  }
+  perm[(int64_t)L * in.n + rank] = (int32_t)i;
 }
 
 __global__ void k_layer_scale(const double* __restrict__ layers, const unsigned long long* smax, int nL,
@@ -360,147 +424,406 @@ __device__ __forceinline__ int64_t floor_div(int64_t a, int64_t b) {
   return q;
 }
 
-__device__ __forceinline__ int64_t lower_bound(const double* a, int64_t n, double v) {
-  int64_t lo = 0, hi = n;
-  while (lo < hi) {
-    int64_t mid = (lo + hi) >> 1;
-    if (a[mid] < v) lo = mid + 1; else hi = mid;
-  }
-  return lo;
+// T_l(d) of a line with start level s: zero in the hole of a wing level
+template <typename R, bool COUNT>
+__device__ __forceinline__ R T_level(R d, int l, int s, const typename RecOf<R>::T& L, const Geometry& G,
+                                     R cfine, R b_prev, Counts& cnt) {
+  if (l > s && fabs(d) < b_prev) return R(0);
+  return line_value<R, COUNT>(d, L, G, cfine, cnt);
 }
 
-__device__ __forceinline__ int64_t upper_bound(const double* a, int64_t n, double v) {
-  int64_t lo = 0, hi = n;
-  while (lo < hi) {
-    int64_t mid = (lo + hi) >> 1;
-    if (a[mid] <= v) lo = mid + 1; else hi = mid;
-  }
-  return lo;
+template <typename R> __device__ __forceinline__ R fast_rcp(R x);
+template <> __device__ __forceinline__ float fast_rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <> __device__ __forceinline__ double fast_rcp<double>(double x) { return 1.0 / x; }
+template <typename R> __device__ __forceinline__ R fast_exp2(R x);
+template <> __device__ __forceinline__ float fast_exp2<float>(float x) { return __builtin_amdgcn_exp2f(x); }
+template <> __device__ __forceinline__ double fast_exp2<double>(double x) { return exp2(x); }
+
+template <typename R> struct Series;
+template <> struct Series<float> {
+  static constexpr int kMax = 10;
+  static __device__ __forceinline__ float thr(const Geometry& G, int k) { return G.eterm32[k]; }
+};
+template <> struct Series<double> {
+  static constexpr int kMax = 60;
+  static __device__ __forceinline__ double thr(const Geometry& G, int k) { return G.eterm64[k]; }
+};
+
+// chi of Eq.(10) without branches: exp2(c0 + c1 |d|) with the piece chosen by selects
+template <typename R>
+__device__ __forceinline__ R chi_any(R ad_fine, const Geometry& G) {
+  if (G.chi != MARFA_CHI_TONKOV) return R(1);
+  const R a = ad_fine * R(kH0);
+  R c0 = R(0), c1 = R(0);
+  c0 = a >= R(3) ? R(G.chi_c0[0]) : c0;
+  c1 = a >= R(3) ? R(G.chi_c1[0]) : c1;
+  c0 = a > R(150) ? R(G.chi_c0[1]) : c0;
+  c1 = a > R(150) ? R(G.chi_c1[1]) : c1;
+  c0 = a > R(300) ? R(G.chi_c0[2]) : c0;
+  c1 = a > R(300) ? R(G.chi_c1[2]) : c1;
+  return fast_exp2<R>(c0 + c1 * a);
 }
 
+// S' F(d) (without chi and the cut-off) for the Voigt shape (Lorentz: ae = 0):
+// the asymptotic wing series with a wave-uniform number of terms, and the
+// rational core for lanes with |z| < sqrt(kZ2).  `live` marks lanes whose
+// value is used (they alone steer the term count and the core branch).
+template <typename R, bool COUNT>
+__device__ __forceinline__ R shape_fast(R d, const typename RecOf<R>::T& L, const Geometry& G, bool live,
+                                        Counts& cnt) {
+  const R zc = R(2 * Prec<R>::kZ2);
+  const R dcm = d * R(kH0);
+  const R dd = dcm * dcm;
+  const R den = dd + R(L.gam2);
+  const bool core = den < zc * R(L.ae);
+  const R Q = fast_rcp<R>(den);
+  const R e = R(L.ae) * Q;
+  const R t = R(4) * dd * Q - R(2);
+  R U = t + R(1);
+  R sum = R(1) + e * U;
+  const bool wing = live && !core;
+  if (__any(wing && e >= Series<R>::thr(G, 2))) {
+    R Um = R(1), ck = e;
+#pragma unroll 4
+    for (int k = 2; k < Series<R>::kMax; ++k) {
+      ck *= R(2 * k - 1) * e;
+      const R Un = t * U - Um;
+      Um = U;
+      U = Un;
+      sum += ck * U;
+      if (COUNT && wing) cnt.terms++;
+      if (!__any(wing && e >= Series<R>::thr(G, k + 1))) break;
+    }
+  }
+  R f = R(L.gam) * Q * R(kInvPi) * sum;
+  if (__any(live && core)) {
+    if (live && core) {
+      const R x = R(L.xs) * dcm;
+      const R y = R(L.xs) * R(L.gam);
+      double K;
+      if (sizeof(R) == 4)
+        K = voigt_core<kWeidemanN32>(fabs((double)x), (double)y, c_weid32, c_weidL[0]);
+      else
+        K = voigt_core<kWeidemanN64>(fabs((double)x), (double)y, c_weid64, c_weidL[1]);
+      f = R((double)L.xs * kInvSqrtPi * K);
+    }
+  }
+  if (COUNT && live) { if (core) cnt.core++; else cnt.wing++; }
+  return R(L.Sp) * f;
+}
 
+// g(d) = S' F(d) chi(|d|) [|d| <= c] for any shape
+template <typename R, bool COUNT>
+__device__ __forceinline__ R g_any(R d, const typename RecOf<R>::T& L, const Geometry& G, R cfine, bool live,
+                                   Counts& cnt) {
+  if (G.shape == MARFA_SHAPE_DOPPLER) return live ? line_value<R, COUNT>(d, L, G, cfine, cnt) : R(0);
+  const R ad = fabs(d);
+  const R v = shape_fast<R, COUNT>(d, L, G, live && ad <= cfine, cnt) * chi_any<R>(ad, G);
+  return ad <= cfine ? v : R(0);
+}
+
+// Region pass: scan lines [j0, j1) of one window side (SGN = +1: d > 0,
+// -1: d < 0, 0: both) and add g(d) for every (node, line) pair in the line's
+// region at this level.
+template <typename R, bool COUNT, int SGN>
+__device__ __forceinline__ void scan_region(const typename RecOf<R>::T* __restrict__ rec, int32_t j0, int32_t j1,
+                                            int S, int slice, int32_t X, bool active, R ra, R rb, bool chi_one,
+                                            bool chi_mixed, R c0, R c1, int l, const Geometry& G, R cfine,
+                                            R b_prev, R b_cur, R& acc, Counts& cnt, uint32_t& n_used) {
+  using Rec = typename RecOf<R>::T;
+  const bool generic_shape = G.shape == MARFA_SHAPE_DOPPLER;
+  int32_t jn = j0 + slice;
+  Rec Lnext = rec[jn < j1 ? jn : j1 - 1];
+  for (int32_t J = j0; J < j1; J += S) {
+    const int32_t j = J + slice;
+    const Rec L = Lnext;
+    jn = j + S;
+    if (J + S < j1) Lnext = rec[jn < j1 ? jn : j1 - 1];
+    const R d = R(X - L.k0) - R(L.frac);
+    const R ad = fabs(d);
+    bool in_win = active && j < j1 && ad >= ra && ad <= rb;
+    if (SGN > 0) in_win = in_win && d > R(0);
+    if (SGN < 0) in_win = in_win && d < R(0);
+    const int ls = L.s;
+    const R rlo = (l == ls) ? R(0) : b_prev;
+    const bool in_reg = in_win && ls <= l && ad >= rlo && ad < b_cur && ad <= cfine;
+    R val;
+    if (!generic_shape) {
+      const R g = shape_fast<R, COUNT>(d, L, G, in_reg, cnt);
+      R chi;
+      if (chi_one) chi = R(1);
+      else if (!chi_mixed) chi = fast_exp2<R>(c0 + c1 * ad);
+      else chi = chi_any<R>(ad, G);
+      val = in_reg ? g * chi : R(0);
+    } else {
+      val = in_reg ? line_value<R, COUNT>(d, L, G, cfine, cnt) : R(0);
+    }
+    acc += val;
+    if (COUNT) {
+      if (in_reg) n_used++;
+      if ((threadIdx.x & 63) == 0) cnt.iters++;
+    }
+  }
+}
+
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ int64_t bucket_of(double nu, const Geometry& G) {
+  int64_t b = (int64_t)floor((nu - G.bucket_origin) * kBucketPerCm);
+  return b < 0 ? 0 : (b > G.nbucket ? G.nbucket : b);
+}
+
+// 3-point stencil of level-l node m on level l+1 (positions in fine units)
+template <typename R>
+__device__ __forceinline__ int stencil_of(const Geometry& G, int l, int64_t m, int32_t* Xs, R* ws) {
+  const int64_t rl = G.r[l];
+  const int64_t rho = G.r[l + 1] / rl;
+  const int64_t q = floor_div(m, rho);
+  const int64_t rem = m - q * rho;
+  const int64_t r1 = G.r[l + 1];
+  if (rem == 0) {
+    Xs[0] = Xs[1] = Xs[2] = (int32_t)(q * r1);
+    ws[0] = R(1); ws[1] = ws[2] = R(0);
+    return 1;
+  }
+  const double f = (double)rem / (double)rho;
+  double tt;
+  int64_t kc;
+  if (f <= 0.5) { kc = q; tt = f; } else { kc = q + 1; tt = f - 1.0; }
+  Xs[0] = (int32_t)((kc - 1) * r1); ws[0] = R(0.5 * tt * (tt - 1.0));
+  Xs[1] = (int32_t)(kc * r1);       ws[1] = R(1.0 - tt * tt);
+  Xs[2] = (int32_t)((kc + 1) * r1); ws[2] = R(0.5 * tt * (tt + 1.0));
+  return 3;
+}
+
+// Region pass of one wavefront tile: nw = 2^lnw consecutive nodes of level l;
+// lane = node * S + slice, S = 64 / nw.  For every region window the tile
+// walks the union of its nodes' line ranges, S consecutive lines per step
+// (coalesced loads); node sums are reduced over slices and stored to LDS.
+template <typename R, bool COUNT>
+__device__ void region_tile(const Geometry& G, const LevelArgs& a, int l, int layer, int lnw, int64_t rel0,
+                            int tile_left, const IntervalSet* iv, R* lds_acc, int64_t item_first, Counts& cnt,
+                            uint32_t& n_used) {
+  using Rec = typename RecOf<R>::T;
+  const int lane = threadIdx.x & 63;
+  const int nw = 1 << lnw;
+  const int lS = 6 - lnw;
+  const int S = 1 << lS;
+  const int node = lane >> lS;
+  const int slice = lane & (S - 1);
+  const int32_t rl = G.r[l];
+  const Rec* rec = reinterpret_cast<const Rec*>(a.rec) + (int64_t)layer * a.n_lines;
+  const int32_t* bk = a.bucket + (int64_t)layer * (G.nbucket + 1);
+  const R cfine = R(G.c_fine);
+  const R b_prev = (l > 0) ? R(G.b[l - 1]) : R(0);
+  const R b_cur = (l < kLevels - 1) ? R(G.b[l]) : R(INFINITY);
+  const int64_t m = G.lo[l] + rel0 + node;
+  const bool active = (rel0 + node < G.n[l]) && (node < tile_left);
+  const int32_t X = (int32_t)(m * rl);
+  const int64_t Xf = (G.lo[l] + rel0) * rl;
+  const int64_t Xl = Xf + (int64_t)(nw - 1) * rl;
+  // line ranges of every (window, side), fetched in one round
+  const int n_iv = uniform(iv->n_iv);
+  int nws = 0;
+  int my_bucket = 0;
+  for (int k = 0; k < n_iv; ++k) {
+    const double ia = iv->a[k], ib = iv->b[k];
+    const int nside = (ia == 0.0) ? 1 : 2;
+    for (int side = 0; side < nside; ++side, ++nws) {
+      double plo, phi;
+      if (nside == 1) { plo = (double)Xf - ib; phi = (double)Xl + ib; }
+      else if (side == 0) { plo = (double)Xf - ib; phi = (double)Xl - ia; }
+      else { plo = (double)Xf + ia; phi = (double)Xl + ib; }
+      const int64_t blo = bucket_of(plo * kH0, G);
+      const int64_t bhi = bucket_of(phi * kH0, G) + 1 > G.nbucket ? G.nbucket : bucket_of(phi * kH0, G) + 1;
+      if (lane == 2 * nws) my_bucket = (int)blo;
+      if (lane == 2 * nws + 1) my_bucket = (int)bhi;
+    }
+  }
+  const int32_t my_j = (lane < 2 * nws) ? bk[my_bucket] : 0;
+  R acc = R(0);
+  int ws_i = 0;
+  for (int k = 0; k < n_iv; ++k) {
+    const R ra = R(iv->a[k]), rb = R(iv->b[k]);
+    const bool chi_mixed = iv->chi_mixed[k] != 0;
+    const R c0 = R(iv->chi_c0[k]), c1 = R(iv->chi_c1[k]);
+    const bool chi_one = !chi_mixed && iv->chi_c0[k] == 0.0 && iv->chi_c1[k] == 0.0;
+    if (iv->a[k] == 0.0) {
+      const int32_t j0 = uniform(__shfl(my_j, 2 * ws_i)), j1 = uniform(__shfl(my_j, 2 * ws_i + 1));
+      ++ws_i;
+      if (j0 < j1)
+        scan_region<R, COUNT, 0>(rec, j0, j1, S, slice, X, active, ra, rb, chi_one, chi_mixed, c0, c1, l, G, cfine,
+                                 b_prev, b_cur, acc, cnt, n_used);
+    } else {
+      int32_t j0 = uniform(__shfl(my_j, 2 * ws_i)), j1 = uniform(__shfl(my_j, 2 * ws_i + 1));
+      ++ws_i;
+      if (j0 < j1)
+        scan_region<R, COUNT, 1>(rec, j0, j1, S, slice, X, active, ra, rb, chi_one, chi_mixed, c0, c1, l, G, cfine,
+                                 b_prev, b_cur, acc, cnt, n_used);
+      j0 = uniform(__shfl(my_j, 2 * ws_i));
+      j1 = uniform(__shfl(my_j, 2 * ws_i + 1));
+      ++ws_i;
+      if (j0 < j1)
+        scan_region<R, COUNT, -1>(rec, j0, j1, S, slice, X, active, ra, rb, chi_one, chi_mixed, c0, c1, l, G, cfine,
+                                  b_prev, b_cur, acc, cnt, n_used);
+    }
+  }
+  for (int o = S >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+  if (active && slice == 0) lds_acc[m - G.lo[l] - item_first] = acc;
+}
+
+// Residual-band pass: lane = one node of level l whose stencil on level l+1
+// has three points.  For every jump q of T_(l+1) and side, the lane walks the
+// lines whose |d| lies within reach of q (its own window), and for each line
+// whose stencil hull holds a jump — counted at the smallest such jump only —
+// adds D_l = T_l(d) - sum_i w_i T_(l+1)(d_i) minus the region value already
+// added.
+template <typename R, bool COUNT>
+__device__ void band_group(const Geometry& G, const LevelArgs& a, int l, int layer, int64_t rel0, int group_left,
+                           const IntervalSet* iv, R* lds_acc, int64_t item_first, Counts& cnt, uint32_t& n_used,
+                           uint32_t& n_band) {
+  using Rec = typename RecOf<R>::T;
+  const int lane = threadIdx.x & 63;
+  const int32_t rl = G.r[l];
+  const Rec* rec = reinterpret_cast<const Rec*>(a.rec) + (int64_t)layer * a.n_lines;
+  const int32_t* bk = a.bucket + (int64_t)layer * (G.nbucket + 1);
+  const R cfine = R(G.c_fine);
+  const R b_prev = (l > 0) ? R(G.b[l - 1]) : R(0);
+  const R b_cur = R(G.b[l]);
+  const double hb = G.hb[l];
+  const int64_t m = G.lo[l] + rel0 + lane;
+  int32_t Xs[3];
+  R ws[3];
+  const int ns = stencil_of<R>(G, l, m, Xs, ws);
+  const bool active = (rel0 + lane < G.n[l]) && (lane < group_left) && ns == 3;
+  if (!__any(active)) return;
+  const int32_t X = (int32_t)(m * rl);
+  const int nj = uniform(iv->n_jump);
+  R acc = R(0);
+  for (int k = 0; k < nj; ++k) {
+    const double q = iv->jq[k];
+    const R rq = R(q);
+    for (int side = 0; side < 2; ++side) {
+      // side 0: d > 0 (line below the node), side 1: d <= 0
+      const double plo = side == 0 ? (double)X - q - hb : (double)X + q - hb;
+      const double phi = side == 0 ? (double)X - q + hb : (double)X + q + hb;
+      const int64_t b0 = bucket_of(plo * kH0, G);
+      int64_t b1 = bucket_of(phi * kH0, G) + 1;
+      b1 = b1 > G.nbucket ? G.nbucket : b1;
+      const int32_t j0 = active ? bk[b0] : 0;
+      const int32_t j1 = active ? bk[b1] : 0;
+      for (int32_t j = j0; __any(j < j1); ++j) {
+        if (j < j1) {
+          const Rec L = rec[j];
+          const R d = R(X - L.k0) - R(L.frac);
+          const bool side_ok = side == 0 ? d > R(0) : !(d > R(0));
+          const int ls = L.s;
+          const int cls = (l >= ls) ? 1 : 2;
+          const R d0 = R(Xs[0] - L.k0) - R(L.frac);
+          const R d2 = R(Xs[2] - L.k0) - R(L.frac);
+          const R lo = (d0 * d2 <= R(0)) ? R(0) : fmin(fabs(d0), fabs(d2));
+          const R hi = fmax(fabs(d0), fabs(d2));
+          // the smallest straddled jump of this line's class
+          R qmin = R(INFINITY);
+          for (int i = 0; i < nj; ++i) {
+            const R qi = R(iv->jq[i]);
+            if ((iv->jmask[i] & cls) && qi >= lo && qi <= hi) qmin = fmin(qmin, qi);
+          }
+          if (side_ok && qmin == rq) {
+            const R ad = fabs(d);
+            const R rlo = (l == ls) ? R(0) : b_prev;
+            const bool in_reg = ls <= l && ad >= rlo && ad < b_cur && ad <= cfine;
+            const bool tl = ad <= cfine && !(l > ls && ad < b_prev);
+            R v = R(0);
+            if (tl && !in_reg) v = g_any<R, COUNT>(d, L, G, cfine, true, cnt);
+            const R d1 = R(Xs[1] - L.k0) - R(L.frac);
+            const R dv[3] = {d0, d1, d2};
+            for (int i = 0; i < 3; ++i) {
+              const R adi = fabs(dv[i]);
+              if (adi <= cfine && !(l + 1 > ls && adi < b_cur)) v -= ws[i] * g_any<R, COUNT>(dv[i], L, G, cfine, true, cnt);
+            }
+            acc += v;
+            if (COUNT) { n_band++; if (!in_reg) n_used++; }
+          }
+        }
+        if (COUNT && lane == 0) cnt.band_iters++;
+      }
+    }
+  }
+  if (active) lds_acc[m - G.lo[l] - item_first] += acc;
+}
+
+// Persistent work queue: each workgroup takes items (consecutive nodes of one
+// level of one layer, heaviest levels first).  Its four wavefronts split the
+// item into region tiles, then into band groups of 64 nodes; node sums meet in
+// LDS and are written once.
 template <typename R, bool COUNT>
 __global__ void __launch_bounds__(256) k_level(Geometry G, LevelArgs a) {
-  using Rec = typename RecOf<R>::T;
+  extern __shared__ char smem_raw[];
+  R* lds_acc = reinterpret_cast<R*>(smem_raw);
   __shared__ int64_t s_item;
-  const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
   const int64_t total = a.n_tiles * a.n_layers;
-  const R cfine = R(G.c_fine);
   for (;;) {
     __syncthreads();
     if (threadIdx.x == 0) s_item = (int64_t)atomicAdd(a.counter, 1u);
     __syncthreads();
-    const int64_t item = s_item;
+    const int64_t item_v = s_item;
+    const int64_t item = (int64_t)(((uint64_t)(uint32_t)uniform((int)(item_v >> 32)) << 32) |
+                                   (uint32_t)uniform((int)item_v));
     if (item >= total) break;
-    const Tile tile = a.tiles[item / a.n_layers];
-    const int layer = (int)(item % a.n_layers);
-    const int l = tile.level;
-    const int64_t rl = G.r[l];
-    const Rec* rec = reinterpret_cast<const Rec*>(a.rec) + (int64_t)layer * a.n_lines;
-    const double* cnu = a.cnu + (int64_t)layer * a.n_lines;
-    const double sh_lo = a.shift[2 * layer], sh_hi = a.shift[2 * layer + 1];
-    const int nsub = (tile.count + kWave - 1) / kWave;
-    for (int sub = wv; sub < nsub; sub += 4) {
-      const int64_t rel0 = tile.first + (int64_t)sub * kWave;
-      const int64_t m = G.lo[l] + rel0 + lane;
-      const bool active = (rel0 + lane < G.n[l]) && (sub * kWave + lane < tile.count);
-      const int64_t X = m * rl;
-      const int64_t Xf = (G.lo[l] + rel0) * rl;
-      const int64_t Xl = Xf + (int64_t)(kWave - 1) * rl;
-      // stencil on level l+1
-      int ns = 0;
-      int64_t Xs[3] = {0, 0, 0};
-      R ws[3] = {0, 0, 0};
-      if (l < kLevels - 1) {
-        int64_t rho = G.r[l + 1] / rl;
-        int64_t q = floor_div(m, rho);
-        int64_t rem = m - q * rho;
-        int64_t r1 = G.r[l + 1];
-        if (rem == 0) {
-          ns = 1; Xs[0] = q * r1; ws[0] = R(1);
-        } else {
-          double f = (double)rem / (double)rho, t;
-          int64_t kc;
-          if (f <= 0.5) { kc = q; t = f; } else { kc = q + 1; t = f - 1.0; }
-          ns = 3;
-          Xs[0] = (kc - 1) * r1; ws[0] = R(0.5 * t * (t - 1.0));
-          Xs[1] = kc * r1;       ws[1] = R(1.0 - t * t);
-          Xs[2] = (kc + 1) * r1; ws[2] = R(0.5 * t * (t + 1.0));
-        }
+    const int tix = uniform((int)(item / a.n_layers));
+    const int layer = uniform((int)(item % a.n_layers));
+    const int l = uniform(a.tiles[tix].level);
+    const int count = uniform(a.tiles[tix].count);
+    const int64_t first = a.tiles[tix].first;
+    const int32_t* gc = a.gcount + layer * (kGroups + 1);
+    int below = 0, above = 0;
+    for (int g = 0; g < l; ++g) below += gc[g];
+    for (int g = l + 1; g < kGroups; ++g) above += gc[g];
+    const int combo = uniform((below > 0 ? 1 : 0) | (gc[l] > 0 ? 2 : 0) | (above > 0 ? 4 : 0));
+    const IntervalSet* iv = a.ivs + (l * 8 + combo);
+    Counts cnt{0, 0, 0, 0, 0};
+    uint32_t n_used = 0, n_band = 0;
+    // region pass
+    const int lnw = G.lnw[l];
+    const int ntile = (count + (1 << lnw) - 1) >> lnw;
+    for (int t = wv; t < ntile; t += 4)
+      region_tile<R, COUNT>(G, a, l, layer, lnw, first + ((int64_t)t << lnw), count - (t << lnw), iv, lds_acc,
+                            first, cnt, n_used);
+    __syncthreads();
+    // residual-band pass
+    if (l < kLevels - 1 && iv->n_jump > 0) {
+      const int ngroup = (count + 63) >> 6;
+      for (int g = wv; g < ngroup; g += 4)
+        band_group<R, COUNT>(G, a, l, layer, first + ((int64_t)g << 6), count - (g << 6), iv, lds_acc, first, cnt,
+                             n_used, n_band);
+    }
+    __syncthreads();
+    if (COUNT) {
+      unsigned long long v[7] = {n_used, n_band, cnt.core, cnt.wing, cnt.terms, cnt.iters, cnt.band_iters};
+      for (int i = 0; i < 7; ++i) {
+        unsigned long long x = v[i];
+        for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+        v[i] = x;
       }
-      R acc = R(0);
-      Counts cnt{0, 0, 0};
-      uint32_t n_used = 0, n_band = 0;
-      for (int s = 0; s < kGroups; ++s) {
-        const int64_t gc = a.gcount[layer * (kGroups + 1) + s];
-        if (gc == 0) continue;
-        const int64_t gs = a.gstart[layer * (kGroups + 1) + s];
-        const IntervalSet& iv = a.ivs[l * kGroups + s];
-        if (iv.n_iv == 0) continue;
-        const R b_in = (l > 0) ? R(G.b[l - 1]) : R(0);
-        const R b_out = (l < kLevels - 1) ? R(G.b[l]) : R(0);
-        const R Bl = (l < kLevels - 1) ? R(G.B[l]) : R(0);
-        for (int k = 0; k < iv.n_iv; ++k) {
-          const double ia = iv.a[k], ib = iv.b[k];
-          const R ra = R(ia), rb = R(ib);
-          const int nside = (ia == 0.0) ? 1 : 2;
-          for (int side = 0; side < nside; ++side) {
-            double plo, phi;
-            int sgn;
-            if (nside == 1) { plo = (double)Xf - ib; phi = (double)Xl + ib; sgn = 0; }
-            else if (side == 0) { plo = (double)Xf - ib; phi = (double)Xl - ia; sgn = 1; }
-            else { plo = (double)Xf + ia; phi = (double)Xl + ib; sgn = -1; }
-            const double vlo = plo * kH0 - sh_hi - 1e-7, vhi = phi * kH0 - sh_lo + 1e-7;
-            const int64_t j0 = lower_bound(cnu + gs, gc, vlo);
-            const int64_t j1 = upper_bound(cnu + gs, gc, vhi);
-            for (int64_t j = gs + j0; j < gs + j1; ++j) {
-              const Rec L = rec[j];
-              const R d = R((int32_t)(X - L.k0)) - R(L.frac);
-              const R ad = fabs(d);
-              bool use = active && ad >= ra && ad <= rb && (sgn == 0 || (sgn > 0 ? d > R(0) : d < R(0)));
-              if (!use) continue;
-              bool in_reg = (l >= s) && ad <= cfine && (l == s || ad >= b_in) &&
-                            (l == kLevels - 1 || ad < b_out);
-              bool in_band = false;
-              for (int qi = 0; qi < iv.n_q; ++qi) in_band |= fabs(ad - R(iv.q[qi])) <= Bl;
-              if (!(in_reg || in_band)) continue;
-              // T_l(d): zero inside the hole of a wing level
-              R v = (l > s && ad < b_in) ? R(0) : line_value<R, COUNT>(d, L, G, cfine, cnt);
-              if (in_band) {
-                for (int i = 0; i < ns; ++i) {
-                  const R di = R((int32_t)(Xs[i] - L.k0)) - R(L.frac);
-                  const R adi = fabs(di);
-                  if (!(l + 1 > s && adi < b_out)) v -= ws[i] * line_value<R, COUNT>(di, L, G, cfine, cnt);
-                }
-              }
-              acc += v;
-              if (COUNT) { n_used++; n_band += in_band ? 1u : 0u; }
-            }
-          }
-        }
+      if (lane == 0) {
+        atomicAdd(&a.stats[l], v[0]);
+        atomicAdd(&a.stats[11], v[1]);
+        atomicAdd(&a.stats[12], v[2]);
+        atomicAdd(&a.stats[13], v[3]);
+        atomicAdd(&a.stats[14], v[4]);
+        atomicAdd(&a.stats[16 + l], v[5]);
+        atomicAdd(&a.stats[27 + l], v[6]);
       }
-      if (COUNT) {
-        // wave reductions, one atomic per counter per sub-tile
-        unsigned long long v[5] = {n_used, n_band, cnt.core, cnt.wing, cnt.terms};
-        for (int i = 0; i < 5; ++i) {
-          unsigned long long x = v[i];
-          for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
-          v[i] = x;
-        }
-        if (lane == 0) {
-          atomicAdd(&a.stats[l], v[0]);
-          atomicAdd(&a.stats[11], v[1]);
-          atomicAdd(&a.stats[12], v[2]);
-          atomicAdd(&a.stats[13], v[3]);
-          atomicAdd(&a.stats[14], v[4]);
-        }
-      } else if (active) {
-        const int64_t rel = m - G.lo[l];
+    } else {
+      for (int i = threadIdx.x; i < count; i += 256) {
+        const R v = lds_acc[i];
         if (l == 0)
-          reinterpret_cast<R*>(a.out)[(int64_t)layer * a.stride + rel] = acc;
+          reinterpret_cast<R*>(a.out)[(int64_t)layer * a.stride + first + i] = v;
         else
-          reinterpret_cast<R*>(a.A)[(int64_t)layer * G.a_total + G.aoff[l] + rel] = acc;
+          reinterpret_cast<R*>(a.A)[(int64_t)layer * G.a_total + G.aoff[l] + first + i] = v;
       }
     }
   }
@@ -545,11 +868,11 @@ __global__ void k_voigt_eval(int64_t n, const double* x, const double* y, double
   // alpha_D = sqrt(ln 2): x = d, y = gamma_L, F = K / sqrt(pi)
   L.k0 = 0; L.frac = 0; L.Sp = R(1);
   L.gam = R(y[i]); L.gam2 = R(y[i]) * R(y[i]);
-  L.ae = R(0.5); L.xs = R(1); L.aD = R(sqrt(kLn2d));
+  L.ae = R(0.5); L.xs = R(1); L.s = 0;
   Geometry G{};
   G.shape = MARFA_SHAPE_VOIGT;
   G.chi = MARFA_CHI_NONE;
-  Counts c{0, 0, 0};
+  Counts c{0, 0, 0, 0, 0};
   R d = R(x[i]) * R(2048);  // fine units
   R f = line_value<R, false>(d, L, G, R(INFINITY), c);
   out[i] = (double)f * 1.772453850905516;
@@ -573,37 +896,43 @@ void launch_fill_u32(unsigned int* p, int64_t n, unsigned int v, hipStream_t s) 
   if (n > 0) k_fill_u32<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(p, n, v);
 }
 
-void launch_prep(const LineIn& in, const double* layers, int nL, unsigned long long* smax, double prune, double R,
-                 const Geometry& G, int32_t* bcount, int32_t* gcount, int32_t* gstart, void* rec, double* cnu,
-                 double* scale, int out_kind, bool fp64, hipStream_t s) {
+void launch_prep(const LineIn& in, const double* layers, int nL, const Geometry& G, const PrepArgs& pa,
+                 hipStream_t s) {
   int nblk = (int)((in.n + 255) / 256);
-  launch_fill_u64(smax, nL, 0ull, s);
+  launch_fill_u64(pa.smax, nL, 0ull, s);
   if (nblk > 0) {
     dim3 grid(nblk, nL);
-    k_prep_smax<<<grid, 256, 0, s>>>(in, layers, smax);
-    k_prep_count<<<grid, 256, 0, s>>>(in, layers, smax, prune, R, G, bcount, nblk);
+    k_prep_smax<<<grid, 256, 0, s>>>(in, layers, pa.smax);
+    k_prep_count<<<grid, 256, 0, s>>>(in, layers, G, pa, nblk);
   }
-  k_prep_scan<<<nL, 256, 0, s>>>(bcount, nblk, gcount, gstart);
+  k_prep_scan<<<nL, 256, 0, s>>>(pa, nblk);
   if (nblk > 0) {
     dim3 grid(nblk, nL);
-    if (fp64)
-      k_prep_scatter<double><<<grid, 256, 0, s>>>(in, layers, smax, prune, R, G, bcount, nblk, gstart,
-                                                   (LineRec64*)rec, cnu);
-    else
-      k_prep_scatter<float><<<grid, 256, 0, s>>>(in, layers, smax, prune, R, G, bcount, nblk, gstart,
-                                                  (LineRec32*)rec, cnu);
+    if (pa.fp64) k_prep_scatter<double><<<grid, 256, 0, s>>>(in, layers, G, pa, nblk);
+    else k_prep_scatter<float><<<grid, 256, 0, s>>>(in, layers, G, pa, nblk);
   }
-  k_layer_scale<<<(nL + 255) / 256, 256, 0, s>>>(layers, smax, nL, out_kind, scale);
+  dim3 gc((unsigned)((in.n + 1 + 255) / 256), nL);
+  k_prep_coarse<<<gc, 256, 0, s>>>(in.n, G, pa);
+  dim3 gb((unsigned)((G.nbucket + 1 + 255) / 256), nL);
+  k_prep_bucket<<<gb, 256, 0, s>>>(in.n, G, pa);
+  k_layer_scale<<<(nL + 255) / 256, 256, 0, s>>>(layers, pa.smax, nL, pa.out_kind, pa.scale);
 }
 
 void launch_level(const Geometry& G, const LevelArgs& a, int grid, bool fp64, bool count, hipStream_t s) {
+  const size_t smem = (size_t)a.max_item * (fp64 ? sizeof(double) : sizeof(float));
   if (fp64) {
-    if (count) k_level<double, true><<<grid, 256, 0, s>>>(G, a);
-    else k_level<double, false><<<grid, 256, 0, s>>>(G, a);
+    if (count) k_level<double, true><<<grid, 256, smem, s>>>(G, a);
+    else k_level<double, false><<<grid, 256, smem, s>>>(G, a);
   } else {
-    if (count) k_level<float, true><<<grid, 256, 0, s>>>(G, a);
-    else k_level<float, false><<<grid, 256, 0, s>>>(G, a);
+    if (count) k_level<float, true><<<grid, 256, smem, s>>>(G, a);
+    else k_level<float, false><<<grid, 256, smem, s>>>(G, a);
   }
+}
+
+void launch_rank(const LineIn& in, const double* layers, int nL, const double* span, int32_t* perm, hipStream_t s) {
+  if (in.n <= 0) return;
+  dim3 grid((unsigned)((in.n + 255) / 256), nL);
+  k_rank<<<grid, 256, 0, s>>>(in, layers, span, perm);
 }
 
 void launch_cascade(const Geometry& G, int nL, void* A, void* out, int64_t stride, const double* scale, bool fp64,

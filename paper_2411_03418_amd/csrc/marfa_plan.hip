@@ -103,7 +103,7 @@ struct marfa_plan {
   std::vector<IntervalSet> ivs;
   std::vector<Tile> tiles;
   std::vector<double> layers_h;
-  std::vector<double> shift_h;
+  std::vector<double> span_h;
   DeviceBuffers d;
   int grid = 0;
   int cu_count = 0;
@@ -127,10 +127,15 @@ static int64_t fdiv(int64_t a, int64_t b) {
   return q;
 }
 
-static void make_geometry(const marfa_request& rq, Geometry& G) {
+// Nodes per wavefront tile by level: all 64 lanes on consecutive nodes at the
+// finest level (short windows), 16 nodes x 4 line slices above it.
+static int default_lnw(int l) { return l == 0 ? 6 : 4; }
+
+static void make_geometry(const marfa_request& rq, double nu_max, Geometry& G) {
   for (int l = 0; l < kLevels; ++l) {
     if (rq.level_table == 1) G.r[l] = 1 << l;
     else G.r[l] = l == 0 ? 1 : (1 << (l + 1));
+    G.lnw[l] = default_lnw(l);
   }
   G.lo[0] = (int64_t)std::llround(rq.nu_begin * 2048.0);
   int64_t hi[kLevels];
@@ -151,56 +156,81 @@ static void make_geometry(const marfa_request& rq, Geometry& G) {
     }
   }
   G.a_total = off;
+  const double c = rq.cutoff * 2048.0;
   for (int l = 0; l < kLevels - 1; ++l) {
     G.b[l] = rq.R * G.r[l + 1];
-    G.B[l] = 2.0 * G.r[l + 1];
+    G.hb[l] = 1.5 * G.r[l + 1] + 1.0;
   }
   G.b[kLevels - 1] = INFINITY;
-  G.B[kLevels - 1] = 0.0;
-  G.c_fine = rq.cutoff * 2048.0;
+  G.hb[kLevels - 1] = 0.0;
+  G.c_fine = c;
+  const double br[3] = {3.0 * 2048.0, 150.0 * 2048.0, 300.0 * 2048.0};
+  for (int l = 0; l < kLevels; ++l) {
+    G.nq1[l] = G.nq2[l] = 0;
+    if (l == kLevels - 1) continue;
+    // lines starting at or below l: T_(l+1) = g on [b_l, c]
+    if (G.b[l] <= c) {
+      std::vector<double> q{G.b[l], c};
+      if (rq.chi == MARFA_CHI_TONKOV)
+        for (double v : br)
+          if (v >= G.b[l] && v <= c) q.push_back(v);
+      std::sort(q.begin(), q.end());
+      q.erase(std::unique(q.begin(), q.end()), q.end());
+      for (size_t i = 0; i < q.size(); ++i) G.q1[l][i] = q[i];
+      G.nq1[l] = (int)q.size();
+    }
+    // lines starting above l: T_(l+1) = g on [0, c]
+    std::vector<double> q2{c};
+    if (rq.chi == MARFA_CHI_TONKOV)
+      for (double v : br)
+        if (v <= c) q2.push_back(v);
+    std::sort(q2.begin(), q2.end());
+    q2.erase(std::unique(q2.begin(), q2.end()), q2.end());
+    for (size_t i = 0; i < q2.size(); ++i) G.q2[l][i] = q2[i];
+    G.nq2[l] = (int)q2.size();
+  }
   G.shape = rq.shape;
   G.chi = rq.chi;
   G.out_kind = rq.out_kind;
   G.fp64 = rq.fp64;
+  G.nbucket = (int32_t)std::ceil((nu_max + 1.0) * kBucketPerCm) + 1;
+  G.ncoarse = (int32_t)std::ceil(nu_max + 1.0) + 1;
+  // term k of the wing series, bounded by (2k+1)!! e^k, matters while it is
+  // above the precision's cut: e >= (eps / (2k+1)!!)^(1/k)
+  auto fill = [](double eps, int kmax, auto* out) {
+    double df = 1.0;  // (2k+1)!!
+    for (int k = 1; k < kmax; ++k) {
+      df *= (2.0 * k + 1.0);
+      out[k] = std::pow(eps / df, 1.0 / k);
+    }
+    out[0] = 0.0;
+  };
+  fill(1e-8, 16, G.eterm32);
+  fill(1e-17, 64, G.eterm64);
+  // Eq.(10): 1.084 e^{-0.027|d|}, 0.208 e^{-0.016|d|}, 0.025 e^{-0.009|d|}
+  const double l2e = 1.0 / std::log(2.0);
+  G.chi_c0[0] = std::log2(1.084); G.chi_c1[0] = -0.027 * l2e;
+  G.chi_c0[1] = std::log2(0.208); G.chi_c1[1] = -0.016 * l2e;
+  G.chi_c0[2] = std::log2(0.025); G.chi_c1[2] = -0.009 * l2e;
 }
 
-// |d| intervals where the level-l part of a line with start level s can be
-// non-zero: its region, and bands of half-width B_l around each jump of the
-// line's level-(l+1) part (inner edge b_l, cut-off, chi breakpoints).
+// |d| windows a level must scan, for each combination of start-level classes
+// present in a layer (bit 0: s < l, bit 1: s == l, bit 2: s > l): regions and
+// the reach 1.5 h_(l+1) around the jumps of T_(l+1).  Each window carries the
+// jumps within its reach and, when chi is one exponential piece over the
+// whole window, that piece as exp2(c0 + c1 |d|).
 static bool make_intervals(const Geometry& G, int chi, std::vector<IntervalSet>& out) {
-  out.assign(kLevels * kGroups, IntervalSet{});
+  out.assign(kLevels * 8, IntervalSet{});
   const double c = G.c_fine;
   for (int l = 0; l < kLevels; ++l) {
-    for (int s = 0; s < kGroups; ++s) {
+    for (int combo = 0; combo < 8; ++combo) {
       std::vector<std::pair<double, double>> iv;
-      if (l >= s) {
-        double inner = (l == s) ? 0.0 : G.b[l - 1];
-        double outer = (l < kLevels - 1) ? G.b[l] : c;
-        double hi = std::min(outer, c);
-        if (inner <= hi) iv.push_back({inner, hi});
+      const bool top = (l == kLevels - 1);
+      if ((combo & 1) && l > 0) {
+        double hi = top ? c : std::min(G.b[l], c);
+        if (G.b[l - 1] <= hi) iv.push_back({G.b[l - 1], hi});
       }
-      IntervalSet& S = out[l * kGroups + s];
-      if (l < kLevels - 1) {
-        double lo_sup = (l + 1 > s) ? G.b[l] : 0.0;
-        std::vector<double> q;
-        if (lo_sup <= c) {
-          if (l + 1 > s) q.push_back(G.b[l]);
-          q.push_back(c);
-          if (chi == MARFA_CHI_TONKOV) {
-            const double br[3] = {3.0 * 2048.0, 150.0 * 2048.0, 300.0 * 2048.0};
-            for (double v : br)
-              if (v >= lo_sup && v <= c) q.push_back(v);
-          }
-        }
-        std::sort(q.begin(), q.end());
-        q.erase(std::unique(q.begin(), q.end()), q.end());
-        if ((int)q.size() > kMaxJumps) return false;
-        S.n_q = (int)q.size();
-        for (size_t i = 0; i < q.size(); ++i) {
-          S.q[i] = q[i];
-          iv.push_back({std::max(0.0, q[i] - G.B[l]), q[i] + G.B[l]});
-        }
-      }
+      if (combo & 2) iv.push_back({0.0, top ? c : std::min(G.b[l], c)});
       std::sort(iv.begin(), iv.end());
       std::vector<std::pair<double, double>> merged;
       for (auto& p : iv) {
@@ -210,14 +240,68 @@ static bool make_intervals(const Geometry& G, int chi, std::vector<IntervalSet>&
           merged.push_back(p);
       }
       if ((int)merged.size() > kMaxIntervals) return false;
+      IntervalSet& S = out[l * 8 + combo];
       S.n_iv = (int)merged.size();
       for (size_t i = 0; i < merged.size(); ++i) {
-        S.a[i] = merged[i].first;
-        S.b[i] = merged[i].second;
+        const double a = merged[i].first, b = merged[i].second;
+        S.a[i] = a;
+        S.b[i] = b;
+        const double A = a / 2048.0, B = b / 2048.0;
+        S.chi_mixed[i] = 0;
+        S.chi_c0[i] = 0.0;
+        S.chi_c1[i] = 0.0;
+        if (chi == MARFA_CHI_TONKOV) {
+          const int piece_a = A < 3.0 ? 0 : (A <= 150.0 ? 1 : (A <= 300.0 ? 2 : 3));
+          const int piece_b = B < 3.0 ? 0 : (B <= 150.0 ? 1 : (B <= 300.0 ? 2 : 3));
+          if (piece_a != piece_b) {
+            S.chi_mixed[i] = 1;
+          } else if (piece_a > 0) {
+            S.chi_c0[i] = G.chi_c0[piece_a - 1];
+            S.chi_c1[i] = G.chi_c1[piece_a - 1] / 2048.0;
+          }
+        }
+      }
+      // jumps of T_(l+1) for the classes present, merged by value
+      std::vector<std::pair<double, int>> jumps;
+      if (!top) {
+        if (combo & 3)
+          for (int i = 0; i < G.nq1[l]; ++i) jumps.push_back({G.q1[l][i], 1});
+        if (combo & 4)
+          for (int i = 0; i < G.nq2[l]; ++i) jumps.push_back({G.q2[l][i], 2});
+      }
+      std::sort(jumps.begin(), jumps.end());
+      std::vector<std::pair<double, int>> qs;
+      for (auto& jq : jumps) {
+        if (!qs.empty() && qs.back().first == jq.first) qs.back().second |= jq.second;
+        else qs.push_back(jq);
+      }
+      if ((int)qs.size() > kMaxJumps) return false;
+      S.n_jump = (int)qs.size();
+      for (size_t k = 0; k < qs.size(); ++k) {
+        S.jq[k] = qs[k].first;
+        S.jmask[k] = qs[k].second;
       }
     }
   }
   return true;
+}
+
+// Nodes per wavefront tile for each level: the fewest nodes (most line slices
+// per node, least union overhead) that still give every slice several lines
+// per window side, from the mean line density.
+static void choose_tiles(Geometry& G, double lines_per_cm) {
+  const double rho = lines_per_cm / 2048.0;  // lines per fine unit
+  G.lnw[0] = 6;
+  for (int l = 1; l < kLevels; ++l) {
+    const double width = (G.b[l - 1] > 0 ? (l < kLevels - 1 ? G.b[l] - G.b[l - 1] : G.c_fine - G.b[l - 1]) : 0.0);
+    int lnw = 0;
+    for (; lnw < 6; ++lnw) {
+      const double nw = (double)(1 << lnw);
+      const double iters = (width + (nw - 1) * G.r[l]) * rho * nw / 64.0;
+      if (iters >= 4.0) break;
+    }
+    G.lnw[l] = lnw;
+  }
 }
 
 // Work items: nodes per item scale inversely with the per-node cost, which
@@ -308,8 +392,8 @@ static void free_plan(marfa_plan* p) {
     if (p->sgraph[i]) (void)hipGraphDestroy(p->sgraph[i]);
   }
   void* bufs[] = {p->d.nu0, p->d.S296, p->d.gair, p->d.gself, p->d.El, p->d.nair, p->d.dair, p->d.layers,
-                  p->d.smax, p->d.bcount, p->d.gcount, p->d.gstart, p->d.rec, p->d.cnu, p->d.A, p->d.ivs,
-                  p->d.tiles, p->d.counter, p->d.scale, p->d.shift, p->d.stats};
+                  p->d.smax, p->d.bcount, p->d.scount, p->d.kept, p->d.gcount, p->d.bucket, p->d.coarse, p->d.rec, p->d.cnu,
+                  p->d.A, p->d.ivs, p->d.tiles, p->d.counter, p->d.scale, p->d.span, p->d.perm, p->d.stats};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   delete p;
@@ -330,7 +414,26 @@ extern "C" marfa_status marfa_plan_create(marfa_plan** out, const marfa_lines* l
   p->molar_mass = lines->molar_mass_g;
   p->n_layers = n_layers;
   p->nblk = (int)((lines->n + 255) / 256);
-  make_geometry(*req, p->G);
+  double nu_max = 0.0, nu_min = 0.0;
+  {
+    double dlo = 0.0, dhi = 0.0, pmax = 0.0;
+    for (int64_t j = 0; j < lines->n; ++j) {
+      nu_max = std::max(nu_max, lines->nu0[j]);
+      dlo = std::min<double>(dlo, lines->delta_air[j]);
+      dhi = std::max<double>(dhi, lines->delta_air[j]);
+    }
+    for (int i = 0; i < n_layers; ++i) pmax = std::max(pmax, layers[i].p_atm);
+    nu_min = std::min(0.0, dlo * pmax) - 1.0;   // lowest shifted centre, minus a margin
+    nu_max = nu_max + std::max(0.0, dhi * pmax);
+  }
+  make_geometry(*req, nu_max - nu_min, p->G);
+  p->G.bucket_origin = std::floor(nu_min);
+  {
+    double lo = INFINITY, hi = -INFINITY;
+    for (int64_t j = 0; j < lines->n; ++j) { lo = std::min(lo, lines->nu0[j]); hi = std::max(hi, lines->nu0[j]); }
+    const double span = lines->n > 0 ? std::max(1.0, hi - lo) : 1.0;
+    choose_tiles(p->G, (double)lines->n / span);
+  }
   if (!make_intervals(p->G, req->chi, p->ivs)) {
     free_plan(p);
     return fail(MARFA_E_INVALID, "too many band intervals");
@@ -358,14 +461,13 @@ extern "C" marfa_status marfa_plan_create(marfa_plan** out, const marfa_lines* l
     dmax = std::max<double>(dmax, da[i]);
   }
   p->layers_h.resize(4 * n_layers);
-  p->shift_h.resize(2 * n_layers);
+  p->span_h.resize(n_layers);
   for (int i = 0; i < n_layers; ++i) {
     p->layers_h[4 * i + 0] = layers[i].p_atm;
     p->layers_h[4 * i + 1] = layers[i].T_K;
     p->layers_h[4 * i + 2] = layers[i].p_self_atm;
     p->layers_h[4 * i + 3] = layers[i].q_ratio;
-    p->shift_h[2 * i + 0] = dmin * layers[i].p_atm;
-    p->shift_h[2 * i + 1] = dmax * layers[i].p_atm;
+    p->span_h[i] = (dmax - dmin) * layers[i].p_atm * (1.0 + 1e-12) + 1e-12;
   }
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
@@ -390,9 +492,12 @@ extern "C" marfa_status marfa_plan_create(marfa_plan** out, const marfa_lines* l
   ALLOC(p->d.dair, n);
   ALLOC(p->d.layers, 4 * NL);
   ALLOC(p->d.smax, NL);
-  ALLOC(p->d.bcount, NL * (size_t)std::max(1, p->nblk) * (kGroups + 1));
+  ALLOC(p->d.bcount, NL * (size_t)std::max(1, p->nblk));
+  ALLOC(p->d.scount, NL * (size_t)std::max(1, p->nblk) * (kGroups + 1));
+  ALLOC(p->d.kept, NL);
   ALLOC(p->d.gcount, NL * (kGroups + 1));
-  ALLOC(p->d.gstart, NL * (kGroups + 1));
+  ALLOC(p->d.bucket, NL * ((size_t)p->G.nbucket + 1));
+  ALLOC(p->d.coarse, NL * ((size_t)p->G.ncoarse + 1));
   {
     char* r = nullptr;
     ALLOC(r, NL * (size_t)n * recsz);
@@ -406,8 +511,9 @@ extern "C" marfa_status marfa_plan_create(marfa_plan** out, const marfa_lines* l
   ALLOC(p->d.tiles, p->tiles.size());
   ALLOC(p->d.counter, 4);
   ALLOC(p->d.scale, NL);
-  ALLOC(p->d.shift, 2 * NL);
-  ALLOC(p->d.stats, 16);
+  ALLOC(p->d.span, NL);
+  ALLOC(p->d.perm, NL * (size_t)n);
+  ALLOC(p->d.stats, 40);
 #undef ALLOC
   auto up = [&](void* dst, const void* src, size_t bytes) -> marfa_status {
     if (bytes == 0) return MARFA_OK;
@@ -424,16 +530,24 @@ extern "C" marfa_status marfa_plan_create(marfa_plan** out, const marfa_lines* l
   if (u == MARFA_OK) u = up(p->d.nair, na.data(), n * sizeof(float));
   if (u == MARFA_OK) u = up(p->d.dair, da.data(), n * sizeof(float));
   if (u == MARFA_OK) u = up(p->d.layers, p->layers_h.data(), p->layers_h.size() * sizeof(double));
-  if (u == MARFA_OK) u = up(p->d.shift, p->shift_h.data(), p->shift_h.size() * sizeof(double));
+  if (u == MARFA_OK) u = up(p->d.span, p->span_h.data(), p->span_h.size() * sizeof(double));
   if (u == MARFA_OK) u = up(p->d.ivs, p->ivs.data(), p->ivs.size() * sizeof(IntervalSet));
   if (u == MARFA_OK) u = up(p->d.tiles, p->tiles.data(), p->tiles.size() * sizeof(Tile));
   if (u != MARFA_OK) {
     free_plan(p);
     return u;
   }
-  int bpc = 0;
+  {
+    LineIn in{p->d.nu0, p->d.S296, p->d.gair, p->d.gself, p->d.El, p->d.nair, p->d.dair, p->molar_mass, n};
+    launch_rank(in, p->d.layers, n_layers, p->d.span, p->d.perm, nullptr);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+      free_plan(p);
+      return fail(MARFA_E_DEVICE, "line ordering: %s", hipGetErrorString(e));
+    }
+  }
   p->grid = p->cu_count * 8;
-  (void)bpc;
   if (hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking) != hipSuccess) {
     free_plan(p);
     return fail(MARFA_E_DEVICE, "stream create");
@@ -464,31 +578,41 @@ static void enqueue(marfa_plan* p, int first, int count, void* out, int64_t stri
   const size_t F = (size_t)first;
   LineIn in{p->d.nu0, p->d.S296, p->d.gair, p->d.gself, p->d.El, p->d.nair, p->d.dair, p->molar_mass, n};
   const int G12 = kGroups + 1;
-  int32_t* bcount = p->d.bcount + F * (size_t)std::max(1, p->nblk) * G12;
-  int32_t* gcount = p->d.gcount + F * G12;
-  int32_t* gstart = p->d.gstart + F * G12;
-  char* rec = (char*)p->d.rec + F * (size_t)n * recsz;
-  double* cnu = p->d.cnu + F * (size_t)n;
+  const size_t nb = (size_t)std::max(1, p->nblk);
+  PrepArgs pa;
+  pa.perm = p->d.perm + F * (size_t)n;
+  pa.smax = p->d.smax + F;
+  pa.bcount = p->d.bcount + F * nb;
+  pa.scount = p->d.scount + F * nb * G12;
+  pa.kept = p->d.kept + F;
+  pa.gcount = p->d.gcount + F * G12;
+  pa.bucket = p->d.bucket + F * ((size_t)p->G.nbucket + 1);
+  pa.coarse = p->d.coarse + F * ((size_t)p->G.ncoarse + 1);
+  pa.rec = (char*)p->d.rec + F * (size_t)n * recsz;
+  pa.cnu = p->d.cnu + F * (size_t)n;
+  pa.scale = p->d.scale + F;
+  pa.prune = p->req.prune_rel;
+  pa.R = p->req.R;
+  pa.out_kind = p->req.out_kind;
+  pa.fp64 = f64 ? 1 : 0;
   char* A = (char*)p->d.A + F * (size_t)p->G.a_total * realsz;
-  if (stages & 1)
-    launch_prep(in, p->d.layers + 4 * F, count, p->d.smax + F, p->req.prune_rel, p->req.R, p->G, bcount, gcount,
-                gstart, rec, cnu, p->d.scale + F, p->req.out_kind, f64, s);
+  if (stages & 1) launch_prep(in, p->d.layers + 4 * F, count, p->G, pa, s);
   LevelArgs a;
   a.tiles = p->d.tiles;
   a.n_tiles = (int64_t)p->tiles.size();
   a.n_layers = count;
   a.counter = p->d.counter;
-  a.rec = rec;
-  a.cnu = cnu;
-  a.gcount = gcount;
-  a.gstart = gstart;
+  a.rec = pa.rec;
+  a.bucket = pa.bucket;
+  a.gcount = pa.gcount;
   a.ivs = p->d.ivs;
-  a.shift = p->d.shift + 2 * F;
   a.n_lines = n;
   a.A = A;
   a.out = out;
   a.stride = stride;
   a.stats = p->d.stats;
+  a.max_item = 0;
+  for (const Tile& t : p->tiles) a.max_item = std::max(a.max_item, t.count);
   int64_t items = a.n_tiles * count;
   int grid = (int)std::min<int64_t>(std::max<int64_t>(1, items), (int64_t)p->grid);
   if (stages & 2) {
@@ -583,10 +707,10 @@ extern "C" marfa_status marfa_plan_count(marfa_plan* p, marfa_stats* out) {
   if (!p || !out) return fail(MARFA_E_INVALID, "null argument");
   HIP_TRY(hipSetDevice(p->device));
   hipStream_t s = p->cap;
-  launch_fill_u64(p->d.stats, 16, 0ull, s);
+  launch_fill_u64(p->d.stats, 40, 0ull, s);
   enqueue(p, 0, p->n_layers, nullptr, 0, s, true);
   HIP_TRY(hipGetLastError());
-  unsigned long long h[16];
+  unsigned long long h[40];
   int32_t gc[12];
   HIP_TRY(hipStreamSynchronize(s));
   HIP_TRY(hipMemcpy(h, p->d.stats, sizeof h, hipMemcpyDeviceToHost));
@@ -599,12 +723,17 @@ extern "C" marfa_status marfa_plan_count(marfa_plan* p, marfa_stats* out) {
     HIP_TRY(hipMemcpy(gc, p->d.gcount + (size_t)L * 12, sizeof gc, hipMemcpyDeviceToHost));
     for (int g = 0; g < kGroups; ++g) kept += gc[g];
   }
+  (void)gc;
   out->lines_kept = kept;
   for (int l = 0; l < kLevels; ++l) out->pairs_level[l] = (int64_t)h[l];
   out->pairs_band = (int64_t)h[11];
   out->pairs_core = (int64_t)h[12];
   out->pairs_wing = (int64_t)h[13];
   out->wing_terms = (int64_t)h[14];
+  for (int l = 0; l < kLevels; ++l) {
+    out->iters_level[l] = (int64_t)h[16 + l];
+    out->band_iters_level[l] = (int64_t)h[27 + l];
+  }
   int64_t ln = 0;
   for (int l = 1; l < kLevels; ++l) ln += p->G.n[l];
   out->level_nodes = ln * p->n_layers;

@@ -48,7 +48,8 @@ class Stats(C.Structure):
     _fields_ = [("points_per_layer", C.c_int64), ("n_layers", C.c_int32), ("lines_total", C.c_int64),
                 ("lines_kept", C.c_int64), ("pairs_level", C.c_int64 * 11), ("pairs_core", C.c_int64),
                 ("pairs_wing", C.c_int64), ("pairs_band", C.c_int64), ("wing_terms", C.c_int64),
-                ("level_nodes", C.c_int64)]
+                ("level_nodes", C.c_int64), ("iters_level", C.c_int64 * 11),
+                ("band_iters_level", C.c_int64 * 11)]
 
 
 class Timing(C.Structure):
@@ -184,7 +185,8 @@ class Plan:
         return dict(points_per_layer=s.points_per_layer, n_layers=s.n_layers, lines_total=s.lines_total,
                     lines_kept=s.lines_kept, pairs_level=list(s.pairs_level), pairs_core=s.pairs_core,
                     pairs_wing=s.pairs_wing, pairs_band=s.pairs_band, wing_terms=s.wing_terms,
-                    level_nodes=s.level_nodes)
+                    level_nodes=s.level_nodes, iters_level=list(s.iters_level),
+                    band_iters_level=list(s.band_iters_level))
 
     def execute_timed(self, out=None, stream=None):
         """Run all layers as three stage graphs with HIP events between them on
