@@ -57,6 +57,13 @@ struct IntervalSet {
   // chi over the whole window: exp2(c0 + c1 |d|) (fine units), or chi_mixed = 1
   double chi_c0[kMaxIntervals], chi_c1[kMaxIntervals];
   int32_t chi_mixed[kMaxIntervals];
+  // fast region test for layers whose lines all start below l: |d| in
+  // [ra, rbx) (rbx exclusive: min(b_l, next value above the cut-off)), and chi
+  // over that range as exp2(fc0 + fc1 |d|) unless fchi_mixed
+  double ra64, rbx64;
+  float ra32, rbx32;
+  double fc0, fc1;
+  int32_t fchi_mixed, fast_ok;
   // jumps of T_(l+1), ascending, with the classes of lines they apply to
   // (bit 0: start level <= l, bit 1: start level > l)
   double jq[kMaxJumps];
@@ -75,7 +82,7 @@ struct Tile {
 struct LineRec32 {
   int32_t k0;     // floor(nu~0 * 2048)
   float frac;     // nu~0 * 2048 - k0, in [0, 1)
-  float Sp;       // S(T) / max S(T) of the layer
+  float A;        // S'/pi gamma_L with S' = S(T)/max S(T) (Voigt, Lorentz); S' (Doppler)
   float gam;      // gamma_L [cm^-1]
   float gam2;     // gamma_L^2
   float ae;       // alpha_D^2 / (2 ln 2); the core branch holds for d^2 + gamma_L^2 < 72 ae
@@ -86,8 +93,11 @@ struct LineRec32 {
 struct LineRec64 {
   int32_t k0;
   int32_t s;
-  double frac, Sp, gam, gam2, ae, xs;
+  double frac, A, gam, gam2, ae, xs;
+  double pad;     // 64-byte records: four 16-byte loads
 };
+static_assert(sizeof(LineRec32) == 32, "LineRec32 is loaded as two 16-byte words");
+static_assert(sizeof(LineRec64) == 64, "LineRec64 is loaded as four 16-byte words");
 
 // Device-side workspace of a plan.
 struct DeviceBuffers {
@@ -107,6 +117,7 @@ struct DeviceBuffers {
   int32_t* gcount = nullptr;       // [n_layers][12] lines per start level
   void* rec = nullptr;             // [n_layers][n_lines] LineRec32/64, kept lines in nu0 order
   double* cnu = nullptr;           // [n_layers][n_lines] shifted centre of the kept lines
+  void* csp = nullptr;             // [n_layers][n_lines] S(T)/max S(T) of the kept lines (FP32/FP64)
   int32_t* bucket = nullptr;       // [n_layers][nbucket+1] first kept line with nu~0 >= origin + b/kBucketPerCm
   int32_t* coarse = nullptr;       // [n_layers][ncoarse+1] first kept line with nu~0 >= origin + b (cm)
   void* A = nullptr;               // [n_layers][a_total] level arrays 1..10
@@ -134,6 +145,7 @@ struct LevelArgs {
   int32_t n_layers;
   unsigned int* counter; // work-queue counter (cleared before each launch)
   const void* rec;       // [layer][line] LineRec32/64
+  const void* csp;       // [layer][line] S(T)/max S(T)
   const int32_t* bucket; // [layer][nbucket+1]
   const int32_t* gcount; // [layer][12]
   const IntervalSet* ivs;
@@ -154,6 +166,7 @@ struct PrepArgs {
   int32_t *bcount, *scount, *kept, *gcount, *bucket, *coarse;
   void* rec;
   double* cnu;
+  void* csp;
   double* scale;
   double prune, R;
   int32_t out_kind, fp64;

@@ -135,7 +135,7 @@ struct Counts {
 
 // g(d) = S' F(d) chi(|d|) [|d| <= c], d in fine units
 template <typename R, bool COUNT>
-__device__ __forceinline__ R line_value(R d, const typename RecOf<R>::T& L, const Geometry& G, R cfine,
+__device__ __forceinline__ R line_value(R d, const typename RecOf<R>::T& L, R Sp, const Geometry& G, R cfine,
                                         Counts& cnt) {
   R ad = fabs(d);
   if (ad > cfine) return R(0);
@@ -166,7 +166,7 @@ __device__ __forceinline__ R line_value(R d, const typename RecOf<R>::T& L, cons
     }
   }
   R chi = (G.chi == MARFA_CHI_TONKOV) ? tonkov<R>(ad * R(kH0)) : R(1);
-  return R(L.Sp) * f * chi;
+  return Sp * f * chi;
 }
 
 // ------------------------------------------------------------------
@@ -329,7 +329,8 @@ __global__ void k_prep_scatter(LineIn in, const double* __restrict__ layers, Geo
   if (fr >= R(1)) { k0 += 1.0; fr = R(0); }
   r.k0 = (int32_t)k0;
   r.frac = fr;
-  r.Sp = sm > 0.0 ? R(st.S / sm) : R(0);
+  const double sp = sm > 0.0 ? st.S / sm : 0.0;
+  r.A = G.shape == MARFA_SHAPE_DOPPLER ? R(sp) : R(sp * st.gL * kInvPi);
   r.gam = R(st.gL);
   r.gam2 = R(st.gL * st.gL);
   // the Lorentz shape is the Voigt wing with alpha_D = 0
@@ -338,6 +339,7 @@ __global__ void k_prep_scatter(LineIn in, const double* __restrict__ layers, Geo
   r.xs = (st.aD > 0.0 && !lor) ? R(sqrt(kLn2d) / st.aD) : R(0);
   r.s = key;
   reinterpret_cast<typename RecOf<R>::T*>(pa.rec)[base + dest] = r;
+  reinterpret_cast<R*>(pa.csp)[base + dest] = R(sp);
   pa.cnu[base + dest] = st.nut;
 }
 
@@ -426,10 +428,10 @@ __device__ __forceinline__ int64_t floor_div(int64_t a, int64_t b) {
 
 // T_l(d) of a line with start level s: zero in the hole of a wing level
 template <typename R, bool COUNT>
-__device__ __forceinline__ R T_level(R d, int l, int s, const typename RecOf<R>::T& L, const Geometry& G,
+__device__ __forceinline__ R T_level(R d, int l, int s, const typename RecOf<R>::T& L, R Sp, const Geometry& G,
                                      R cfine, R b_prev, Counts& cnt) {
   if (l > s && fabs(d) < b_prev) return R(0);
-  return line_value<R, COUNT>(d, L, G, cfine, cnt);
+  return line_value<R, COUNT>(d, L, Sp, G, cfine, cnt);
 }
 
 template <typename R> __device__ __forceinline__ R fast_rcp(R x);
@@ -467,22 +469,23 @@ __device__ __forceinline__ R chi_any(R ad_fine, const Geometry& G) {
 // S' F(d) (without chi and the cut-off) for the Voigt shape (Lorentz: ae = 0):
 // the asymptotic wing series with a wave-uniform number of terms, and the
 // rational core for lanes with |z| < sqrt(kZ2).  `live` marks lanes whose
-// value is used (they alone steer the term count and the core branch).
+// value is used (they alone steer the term count and the core branch).  The
+// wing is A Q sum with A = S' gamma_L / pi and Q = 1/(d^2 + gamma_L^2); the
+// core needs S' itself (sp[j]).
 template <typename R, bool COUNT>
-__device__ __forceinline__ R shape_fast(R d, const typename RecOf<R>::T& L, const Geometry& G, bool live,
-                                        Counts& cnt) {
-  const R zc = R(2 * Prec<R>::kZ2);
+__device__ __forceinline__ R shape_fast(R d, const typename RecOf<R>::T& L, const R* __restrict__ sp, int32_t j,
+                                        const Geometry& G, bool live, Counts& cnt) {
   const R dcm = d * R(kH0);
-  const R dd = dcm * dcm;
-  const R den = dd + R(L.gam2);
-  const bool core = den < zc * R(L.ae);
+  const R den = fma(dcm, dcm, R(L.gam2));
   const R Q = fast_rcp<R>(den);
   const R e = R(L.ae) * Q;
-  const R t = R(4) * dd * Q - R(2);
-  R U = t + R(1);
-  R sum = R(1) + e * U;
+  const bool core = e > R(0.5 / Prec<R>::kZ2);     // |z|^2 = 1/(2e) < kZ2
+  // U_2 = 4 d^2 Q - 1 = 3 - 4 gamma^2 Q
+  R U = fma(R(-4) * R(L.gam2), Q, R(3));
+  R sum = fma(e, U, R(1));
   const bool wing = live && !core;
-  if (__any(wing && e >= Series<R>::thr(G, 2))) {
+  if (__builtin_amdgcn_ballot_w64(wing && e >= Series<R>::thr(G, 2))) {
+    const R t = U - R(1);
     R Um = R(1), ck = e;
 #pragma unroll 4
     for (int k = 2; k < Series<R>::kMax; ++k) {
@@ -492,11 +495,11 @@ __device__ __forceinline__ R shape_fast(R d, const typename RecOf<R>::T& L, cons
       U = Un;
       sum += ck * U;
       if (COUNT && wing) cnt.terms++;
-      if (!__any(wing && e >= Series<R>::thr(G, k + 1))) break;
+      if (!__builtin_amdgcn_ballot_w64(wing && e >= Series<R>::thr(G, k + 1))) break;
     }
   }
-  R f = R(L.gam) * Q * R(kInvPi) * sum;
-  if (__any(live && core)) {
+  R f = R(L.A) * Q * sum;
+  if (__builtin_amdgcn_ballot_w64(live && core)) {
     if (live && core) {
       const R x = R(L.xs) * dcm;
       const R y = R(L.xs) * R(L.gam);
@@ -505,20 +508,20 @@ __device__ __forceinline__ R shape_fast(R d, const typename RecOf<R>::T& L, cons
         K = voigt_core<kWeidemanN32>(fabs((double)x), (double)y, c_weid32, c_weidL[0]);
       else
         K = voigt_core<kWeidemanN64>(fabs((double)x), (double)y, c_weid64, c_weidL[1]);
-      f = R((double)L.xs * kInvSqrtPi * K);
+      f = sp[j] * R((double)L.xs * kInvSqrtPi * K);
     }
   }
   if (COUNT && live) { if (core) cnt.core++; else cnt.wing++; }
-  return R(L.Sp) * f;
+  return f;
 }
 
 // g(d) = S' F(d) chi(|d|) [|d| <= c] for any shape
 template <typename R, bool COUNT>
-__device__ __forceinline__ R g_any(R d, const typename RecOf<R>::T& L, const Geometry& G, R cfine, bool live,
-                                   Counts& cnt) {
-  if (G.shape == MARFA_SHAPE_DOPPLER) return live ? line_value<R, COUNT>(d, L, G, cfine, cnt) : R(0);
+__device__ __forceinline__ R g_any(R d, const typename RecOf<R>::T& L, const R* __restrict__ sp, int32_t j,
+                                   const Geometry& G, R cfine, bool live, Counts& cnt) {
+  if (G.shape == MARFA_SHAPE_DOPPLER) return live ? line_value<R, COUNT>(d, L, sp[j], G, cfine, cnt) : R(0);
   const R ad = fabs(d);
-  const R v = shape_fast<R, COUNT>(d, L, G, live && ad <= cfine, cnt) * chi_any<R>(ad, G);
+  const R v = shape_fast<R, COUNT>(d, L, sp, j, G, live && ad <= cfine, cnt) * chi_any<R>(ad, G);
   return ad <= cfine ? v : R(0);
 }
 
@@ -526,7 +529,8 @@ __device__ __forceinline__ R g_any(R d, const typename RecOf<R>::T& L, const Geo
 // -1: d < 0, 0: both) and add g(d) for every (node, line) pair in the line's
 // region at this level.
 template <typename R, bool COUNT, int SGN>
-__device__ __forceinline__ void scan_region(const typename RecOf<R>::T* __restrict__ rec, int32_t j0, int32_t j1,
+__device__ __forceinline__ void scan_region(const typename RecOf<R>::T* __restrict__ rec, const R* __restrict__ sp,
+                                            int32_t j0, int32_t j1,
                                             int S, int slice, int32_t X, bool active, R ra, R rb, bool chi_one,
                                             bool chi_mixed, R c0, R c1, int l, const Geometry& G, R cfine,
                                             R b_prev, R b_cur, R& acc, Counts& cnt, uint32_t& n_used) {
@@ -549,14 +553,14 @@ __device__ __forceinline__ void scan_region(const typename RecOf<R>::T* __restri
     const bool in_reg = in_win && ls <= l && ad >= rlo && ad < b_cur && ad <= cfine;
     R val;
     if (!generic_shape) {
-      const R g = shape_fast<R, COUNT>(d, L, G, in_reg, cnt);
+      const R g = shape_fast<R, COUNT>(d, L, sp, j, G, in_reg, cnt);
       R chi;
       if (chi_one) chi = R(1);
       else if (!chi_mixed) chi = fast_exp2<R>(c0 + c1 * ad);
       else chi = chi_any<R>(ad, G);
       val = in_reg ? g * chi : R(0);
     } else {
-      val = in_reg ? line_value<R, COUNT>(d, L, G, cfine, cnt) : R(0);
+      val = in_reg ? line_value<R, COUNT>(d, L, sp[j], G, cfine, cnt) : R(0);
     }
     acc += val;
     if (COUNT) {
@@ -567,6 +571,67 @@ __device__ __forceinline__ void scan_region(const typename RecOf<R>::T* __restri
 }
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Line record through a raw buffer resource: 32-bit offsets, and lines past
+// the resource's end read as zero (zero intensity), so no clamping is needed.
+template <typename R> struct RecBuf;
+template <> struct RecBuf<float> {
+  static __device__ __forceinline__ LineRec32 load(__amdgpu_buffer_rsrc_t r, int32_t j) {
+    LineRec32 L;
+    auto a = __builtin_amdgcn_raw_buffer_load_b128(r, j * (int32_t)sizeof(LineRec32), 0, 0);
+    auto b = __builtin_amdgcn_raw_buffer_load_b128(r, j * (int32_t)sizeof(LineRec32) + 16, 0, 0);
+    __builtin_memcpy(&L, &a, 16);
+    __builtin_memcpy(reinterpret_cast<char*>(&L) + 16, &b, 16);
+    return L;
+  }
+};
+template <> struct RecBuf<double> {
+  static __device__ __forceinline__ LineRec64 load(__amdgpu_buffer_rsrc_t r, int32_t j) {
+    LineRec64 L;
+    char* o = reinterpret_cast<char*>(&L);
+    for (int k = 0; k < 4; ++k) {
+      auto a = __builtin_amdgcn_raw_buffer_load_b128(r, j * (int32_t)sizeof(LineRec64) + 16 * k, 0, 0);
+      __builtin_memcpy(o + 16 * k, &a, 16);
+    }
+    return L;
+  }
+};
+
+// Fast region scan for layers whose lines all start below level l: one side
+// (SGN) of the annulus, |d| in [ra, rbx), chi one exponential piece (or any).
+template <typename R, bool COUNT, int SGN>
+__device__ __forceinline__ void scan_fast(__amdgpu_buffer_rsrc_t rs, const R* __restrict__ sp, int32_t j0,
+                                          int32_t j1, int S, int slice, int32_t X, R ra, R rbx, bool chi_none,
+                                          bool chi_mixed, R c0, R c1, const Geometry& G, R& acc, Counts& cnt,
+                                          uint32_t& n_used) {
+  using Rec = typename RecOf<R>::T;
+  const R c1s = SGN > 0 ? c1 : -c1;   // chi exponent slope in the signed distance
+  auto step = [&](const Rec& L, int32_t j) {
+    const R d = R(X - L.k0) - R(L.frac);
+    const bool in_reg = SGN > 0 ? (d >= ra && d < rbx) : (d <= -ra && d > -rbx);
+    const R g = shape_fast<R, COUNT>(d, L, sp, j, G, in_reg, cnt);
+    R chi;
+    if (chi_none) chi = R(1);
+    else if (!chi_mixed) chi = fast_exp2<R>(fma(c1s, d, c0));
+    else chi = chi_any<R>(fabs(d), G);
+    acc += in_reg ? g * chi : R(0);
+    if (COUNT && in_reg) n_used++;
+  };
+  int32_t j = j0 + slice;
+  Rec La = RecBuf<R>::load(rs, j);
+  for (int32_t J = j0; J < j1; J += 2 * S) {
+    const Rec Lb = RecBuf<R>::load(rs, J + S + slice);
+    step(La, J + slice);
+    La = RecBuf<R>::load(rs, J + 2 * S + slice);
+    if (COUNT && (threadIdx.x & 63) == 0) cnt.iters++;
+    if (J + S < j1) {
+      step(Lb, J + S + slice);
+      if (COUNT && (threadIdx.x & 63) == 0) cnt.iters++;
+    }
+  }
+}
+
+
 
 __device__ __forceinline__ int64_t bucket_of(double nu, const Geometry& G) {
   int64_t b = (int64_t)floor((nu - G.bucket_origin) * kBucketPerCm);
@@ -613,6 +678,7 @@ __device__ void region_tile(const Geometry& G, const LevelArgs& a, int l, int la
   const int slice = lane & (S - 1);
   const int32_t rl = G.r[l];
   const Rec* rec = reinterpret_cast<const Rec*>(a.rec) + (int64_t)layer * a.n_lines;
+  const R* sp = reinterpret_cast<const R*>(a.csp) + (int64_t)layer * a.n_lines;
   const int32_t* bk = a.bucket + (int64_t)layer * (G.nbucket + 1);
   const R cfine = R(G.c_fine);
   const R b_prev = (l > 0) ? R(G.b[l - 1]) : R(0);
@@ -642,6 +708,30 @@ __device__ void region_tile(const Geometry& G, const LevelArgs& a, int l, int la
   }
   const int32_t my_j = (lane < 2 * nws) ? bk[my_bucket] : 0;
   R acc = R(0);
+  if (iv->fast_ok && G.shape != MARFA_SHAPE_DOPPLER) {
+    // lines all start below l: one annulus window, two sides
+    const R ra = active ? (sizeof(R) == 4 ? R(iv->ra32) : R(iv->ra64)) : R(INFINITY);
+    const R rbx = sizeof(R) == 4 ? R(iv->rbx32) : R(iv->rbx64);
+    const bool chi_mixed = iv->fchi_mixed != 0;
+    const bool chi_none = !chi_mixed && iv->fc0 == 0.0 && iv->fc1 == 0.0;
+    const R c0 = R(iv->fc0), c1 = R(iv->fc1);
+    for (int side = 0; side < 2; ++side) {
+      const int32_t j0 = uniform(__shfl(my_j, 2 * side)), j1 = uniform(__shfl(my_j, 2 * side + 1));
+      if (j0 >= j1) continue;
+      // the resource ends at line j1: loads past the window read zero-intensity lines
+      const __amdgpu_buffer_rsrc_t rs =
+          __builtin_amdgcn_make_buffer_rsrc((void*)rec, 0, (int)(j1 * (int32_t)sizeof(Rec)), 0x00020000);
+      if (side == 0)
+        scan_fast<R, COUNT, 1>(rs, sp, j0, j1, S, slice, X, ra, rbx, chi_none, chi_mixed, c0, c1, G, acc, cnt,
+                               n_used);
+      else
+        scan_fast<R, COUNT, -1>(rs, sp, j0, j1, S, slice, X, ra, rbx, chi_none, chi_mixed, c0, c1, G, acc, cnt,
+                                n_used);
+    }
+    for (int o = S >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    if (active && slice == 0) lds_acc[m - G.lo[l] - item_first] = acc;
+    return;
+  }
   int ws_i = 0;
   for (int k = 0; k < n_iv; ++k) {
     const R ra = R(iv->a[k]), rb = R(iv->b[k]);
@@ -652,19 +742,19 @@ __device__ void region_tile(const Geometry& G, const LevelArgs& a, int l, int la
       const int32_t j0 = uniform(__shfl(my_j, 2 * ws_i)), j1 = uniform(__shfl(my_j, 2 * ws_i + 1));
       ++ws_i;
       if (j0 < j1)
-        scan_region<R, COUNT, 0>(rec, j0, j1, S, slice, X, active, ra, rb, chi_one, chi_mixed, c0, c1, l, G, cfine,
+        scan_region<R, COUNT, 0>(rec, sp, j0, j1, S, slice, X, active, ra, rb, chi_one, chi_mixed, c0, c1, l, G, cfine,
                                  b_prev, b_cur, acc, cnt, n_used);
     } else {
       int32_t j0 = uniform(__shfl(my_j, 2 * ws_i)), j1 = uniform(__shfl(my_j, 2 * ws_i + 1));
       ++ws_i;
       if (j0 < j1)
-        scan_region<R, COUNT, 1>(rec, j0, j1, S, slice, X, active, ra, rb, chi_one, chi_mixed, c0, c1, l, G, cfine,
+        scan_region<R, COUNT, 1>(rec, sp, j0, j1, S, slice, X, active, ra, rb, chi_one, chi_mixed, c0, c1, l, G, cfine,
                                  b_prev, b_cur, acc, cnt, n_used);
       j0 = uniform(__shfl(my_j, 2 * ws_i));
       j1 = uniform(__shfl(my_j, 2 * ws_i + 1));
       ++ws_i;
       if (j0 < j1)
-        scan_region<R, COUNT, -1>(rec, j0, j1, S, slice, X, active, ra, rb, chi_one, chi_mixed, c0, c1, l, G, cfine,
+        scan_region<R, COUNT, -1>(rec, sp, j0, j1, S, slice, X, active, ra, rb, chi_one, chi_mixed, c0, c1, l, G, cfine,
                                   b_prev, b_cur, acc, cnt, n_used);
     }
   }
@@ -686,6 +776,7 @@ __device__ void band_group(const Geometry& G, const LevelArgs& a, int l, int lay
   const int lane = threadIdx.x & 63;
   const int32_t rl = G.r[l];
   const Rec* rec = reinterpret_cast<const Rec*>(a.rec) + (int64_t)layer * a.n_lines;
+  const R* sp = reinterpret_cast<const R*>(a.csp) + (int64_t)layer * a.n_lines;
   const int32_t* bk = a.bucket + (int64_t)layer * (G.nbucket + 1);
   const R cfine = R(G.c_fine);
   const R b_prev = (l > 0) ? R(G.b[l - 1]) : R(0);
@@ -735,12 +826,12 @@ __device__ void band_group(const Geometry& G, const LevelArgs& a, int l, int lay
             const bool in_reg = ls <= l && ad >= rlo && ad < b_cur && ad <= cfine;
             const bool tl = ad <= cfine && !(l > ls && ad < b_prev);
             R v = R(0);
-            if (tl && !in_reg) v = g_any<R, COUNT>(d, L, G, cfine, true, cnt);
+            if (tl && !in_reg) v = g_any<R, COUNT>(d, L, sp, j, G, cfine, true, cnt);
             const R d1 = R(Xs[1] - L.k0) - R(L.frac);
             const R dv[3] = {d0, d1, d2};
             for (int i = 0; i < 3; ++i) {
               const R adi = fabs(dv[i]);
-              if (adi <= cfine && !(l + 1 > ls && adi < b_cur)) v -= ws[i] * g_any<R, COUNT>(dv[i], L, G, cfine, true, cnt);
+              if (adi <= cfine && !(l + 1 > ls && adi < b_cur)) v -= ws[i] * g_any<R, COUNT>(dv[i], L, sp, j, G, cfine, true, cnt);
             }
             acc += v;
             if (COUNT) { n_band++; if (!in_reg) n_used++; }
@@ -866,7 +957,7 @@ __global__ void k_voigt_eval(int64_t n, const double* x, const double* y, double
   if (i >= n) return;
   typename RecOf<R>::T L{};
   // alpha_D = sqrt(ln 2): x = d, y = gamma_L, F = K / sqrt(pi)
-  L.k0 = 0; L.frac = 0; L.Sp = R(1);
+  L.k0 = 0; L.frac = 0; L.A = R(y[i] * kInvPi);
   L.gam = R(y[i]); L.gam2 = R(y[i]) * R(y[i]);
   L.ae = R(0.5); L.xs = R(1); L.s = 0;
   Geometry G{};
@@ -874,7 +965,7 @@ __global__ void k_voigt_eval(int64_t n, const double* x, const double* y, double
   G.chi = MARFA_CHI_NONE;
   Counts c{0, 0, 0, 0, 0};
   R d = R(x[i]) * R(2048);  // fine units
-  R f = line_value<R, false>(d, L, G, R(INFINITY), c);
+  R f = line_value<R, false>(d, L, R(1), G, R(INFINITY), c);
   out[i] = (double)f * 1.772453850905516;
 }
 

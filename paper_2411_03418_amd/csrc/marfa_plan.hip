@@ -261,6 +261,42 @@ static bool make_intervals(const Geometry& G, int chi, std::vector<IntervalSet>&
           }
         }
       }
+      // fast region test when every line starts below l (one annulus window)
+      S.fast_ok = 0;
+      if (combo == 1 && l > 0 && S.n_iv == 1) {
+        const double ra = G.b[l - 1];
+        const double bl = top ? INFINITY : G.b[l];
+        double rbx64;
+        float rbx32;
+        bool incl_c = c < bl;
+        if (incl_c) {
+          rbx64 = std::nextafter(c, INFINITY);
+          rbx32 = std::nextafterf((float)c, INFINITY);
+        } else {
+          rbx64 = bl;
+          rbx32 = (float)bl;
+        }
+        S.fast_ok = 1;
+        S.ra64 = ra;
+        S.rbx64 = rbx64;
+        S.ra32 = (float)ra;
+        S.rbx32 = rbx32;
+        // chi over [ra, rbx): lowest and highest |d| of the range, in cm
+        auto piece_incl = [](double x) { return x < 3.0 ? 0 : (x <= 150.0 ? 1 : (x <= 300.0 ? 2 : 3)); };
+        auto piece_below = [](double x) { return x <= 3.0 ? 0 : (x <= 150.0 ? 1 : (x <= 300.0 ? 2 : 3)); };
+        const int pa = piece_incl(ra / 2048.0);
+        const int pb = incl_c ? piece_incl(c / 2048.0) : piece_below(bl / 2048.0);
+        S.fchi_mixed = 0;
+        S.fc0 = 0.0;
+        S.fc1 = 0.0;
+        if (chi == MARFA_CHI_TONKOV) {
+          if (pa != pb) S.fchi_mixed = 1;
+          else if (pa > 0) {
+            S.fc0 = G.chi_c0[pa - 1];
+            S.fc1 = G.chi_c1[pa - 1] / 2048.0;
+          }
+        }
+      }
       // jumps of T_(l+1) for the classes present, merged by value
       std::vector<std::pair<double, int>> jumps;
       if (!top) {
@@ -334,7 +370,8 @@ static marfa_status validate(const marfa_lines* L, const marfa_layer* lay, int32
   if (L->n > 0 && (!L->nu0 || !L->S296 || !L->gamma_air || !L->gamma_self || !L->E_lower || !L->n_air ||
                    !L->delta_air))
     return fail(MARFA_E_INVALID, "null line array");
-  if (L->n > ((int64_t)1 << 31) - 1) return fail(MARFA_E_INVALID, "too many lines");
+  // line records are addressed with 32-bit byte offsets (64-byte records)
+  if (L->n > ((int64_t)1 << 25) - 1) return fail(MARFA_E_INVALID, "too many lines (at most 2^25 - 1)");
   if (!(L->molar_mass_g > 0.0) || !std::isfinite(L->molar_mass_g)) return fail(MARFA_E_INVALID, "molar mass");
   for (int64_t j = 0; j < L->n; ++j)
     if (!std::isfinite(L->nu0[j]) || L->nu0[j] < 0.0) return fail(MARFA_E_INVALID, "line %lld: bad nu0", (long long)j);
@@ -392,7 +429,7 @@ static void free_plan(marfa_plan* p) {
     if (p->sgraph[i]) (void)hipGraphDestroy(p->sgraph[i]);
   }
   void* bufs[] = {p->d.nu0, p->d.S296, p->d.gair, p->d.gself, p->d.El, p->d.nair, p->d.dair, p->d.layers,
-                  p->d.smax, p->d.bcount, p->d.scount, p->d.kept, p->d.gcount, p->d.bucket, p->d.coarse, p->d.rec, p->d.cnu,
+                  p->d.smax, p->d.bcount, p->d.scount, p->d.kept, p->d.gcount, p->d.bucket, p->d.coarse, p->d.rec, p->d.cnu, p->d.csp,
                   p->d.A, p->d.ivs, p->d.tiles, p->d.counter, p->d.scale, p->d.span, p->d.perm, p->d.stats};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
@@ -507,6 +544,11 @@ extern "C" marfa_status marfa_plan_create(marfa_plan** out, const marfa_lines* l
     p->d.A = a;
   }
   ALLOC(p->d.cnu, NL * (size_t)n);
+  {
+    char* c = nullptr;
+    ALLOC(c, NL * (size_t)n * realsz);
+    p->d.csp = c;
+  }
   ALLOC(p->d.ivs, p->ivs.size());
   ALLOC(p->d.tiles, p->tiles.size());
   ALLOC(p->d.counter, 4);
@@ -590,6 +632,7 @@ static void enqueue(marfa_plan* p, int first, int count, void* out, int64_t stri
   pa.coarse = p->d.coarse + F * ((size_t)p->G.ncoarse + 1);
   pa.rec = (char*)p->d.rec + F * (size_t)n * recsz;
   pa.cnu = p->d.cnu + F * (size_t)n;
+  pa.csp = (char*)p->d.csp + F * (size_t)n * realsz;
   pa.scale = p->d.scale + F;
   pa.prune = p->req.prune_rel;
   pa.R = p->req.R;
@@ -603,6 +646,7 @@ static void enqueue(marfa_plan* p, int first, int count, void* out, int64_t stri
   a.n_layers = count;
   a.counter = p->d.counter;
   a.rec = pa.rec;
+  a.csp = pa.csp;
   a.bucket = pa.bucket;
   a.gcount = pa.gcount;
   a.ivs = p->d.ivs;
