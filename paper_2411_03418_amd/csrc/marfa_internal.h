@@ -68,6 +68,11 @@ struct IntervalSet {
   // (bit 0: start level <= l, bit 1: start level > l)
   double jq[kMaxJumps];
   int32_t jmask[kMaxJumps];
+  // line-major band pass: usable when every jump exceeds 2 r_(l+1) + 2 (no
+  // stencil hull around a line centre can hold one) and rho is 2 or 4;
+  // lc_eps widens the centre estimate past single-precision rounding of d
+  int32_t lc_ok, pad_lc;
+  double lc_eps;
 };
 
 // One work item of the level kernel: `count` consecutive nodes of one level,

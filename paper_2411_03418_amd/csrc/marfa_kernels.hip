@@ -844,6 +844,133 @@ __device__ void band_group(const Geometry& G, const LevelArgs& a, int l, int lay
   if (active) lds_acc[m - G.lo[l] - item_first] += acc;
 }
 
+// Residual-band pass, line-major form, for one wavefront owning the item's
+// nodes [own_lo, own_hi).  For a jump q of T_(l+1) and a side, put the
+// line's jump point at P = nu~0 + q (nodes above the line) or nu~0 - q (nodes
+// below).  A level-l node's stencil hull [(kc-1) r1, (kc+1) r1] holds P only
+// if its nearest level-(l+1) centre kc is within one step of P / r1, so the
+// nodes to correct are the (RHO - 1) three-point nodes around each of three
+// centres.  Lane = line: T_(l+1) is evaluated once at the five level-(l+1)
+// nodes around P, every candidate node gets D_l = T_l(d) - sum w_i T_(l+1)(d_i)
+// minus the region value (zero unless its hull straddles q and q is the
+// smallest straddled jump), and a segmented sum over lanes with the same
+// centre estimate -- non-decreasing in line order -- merges corrections of a
+// node before one lane adds them to its LDS slot.  Per slot there is one
+// writer and a fixed summation order, so results are reproducible.
+template <typename R, bool COUNT, int RHO>
+__device__ void band_lines(const Geometry& G, const LevelArgs& a, int l, int layer, int64_t item_first, int own_lo,
+                           int own_hi, const IntervalSet* iv, R* lds_acc, Counts& cnt, uint32_t& n_used,
+                           uint32_t& n_band) {
+  using Rec = typename RecOf<R>::T;
+  const int lane = threadIdx.x & 63;
+  if (own_hi <= own_lo) return;
+  const int32_t rl = G.r[l];
+  const int32_t r1 = G.r[l + 1];
+  const Rec* rec = reinterpret_cast<const Rec*>(a.rec) + (int64_t)layer * a.n_lines;
+  const R* sp = reinterpret_cast<const R*>(a.csp) + (int64_t)layer * a.n_lines;
+  const int32_t* bk = a.bucket + (int64_t)layer * (G.nbucket + 1);
+  const R cfine = R(G.c_fine);
+  const R b_prev = (l > 0) ? R(G.b[l - 1]) : R(0);
+  const R b_cur = R(G.b[l]);
+  const double eps = iv->lc_eps;
+  const double inv_r1 = 1.0 / (double)r1;
+  const int nj = uniform(iv->n_jump);
+  R jq[kMaxJumps];
+  int jm[kMaxJumps];
+#pragma unroll
+  for (int i = 0; i < kMaxJumps; ++i) {
+    jq[i] = i < nj ? R(iv->jq[i]) : R(INFINITY);
+    jm[i] = i < nj ? iv->jmask[i] : 0;
+  }
+  const int64_t base = G.lo[l] + item_first;   // absolute index of the item's first node
+  const int64_t m_a = base + own_lo, m_b = base + own_hi - 1;
+  for (int k = 0; k < nj; ++k) {
+    const double q = iv->jq[k];
+    const R rq = R(q);
+    const int mask = iv->jmask[k];
+    for (int side = 0; side < 2; ++side) {
+      const double sq = side == 0 ? q : -q;
+      // lines whose candidate nodes can reach [m_a, m_b]
+      const double plo = (double)(m_a * rl) - 2.5 * r1 - 2.0 - sq;
+      const double phi = (double)(m_b * rl) + 2.5 * r1 + 2.0 - sq;
+      const int64_t b0 = bucket_of(plo * kH0, G);
+      int64_t b1 = bucket_of(phi * kH0, G) + 1;
+      b1 = b1 > G.nbucket ? G.nbucket : b1;
+      const int32_t j0 = uniform(bk[b0]), j1 = uniform(bk[b1]);
+      for (int32_t J = j0; J < j1; J += kWave) {
+        const int32_t jl = (J + lane < j1) ? J + lane : j1 - 1;
+        const Rec L = rec[jl];
+        const int ls = L.s;
+        const int cls = (l >= ls) ? 1 : 2;
+        const bool ok = (J + lane < j1) && (mask & cls);
+        const double P = (double)L.k0 + (double)L.frac + sq;
+        const int64_t u = (int64_t)floor(P * inv_r1 + eps);
+        // T_(l+1) at level-(l+1) nodes u-2 .. u+2
+        R dd[5], T1[5];
+#pragma unroll
+        for (int i = 0; i < 5; ++i) {
+          dd[i] = R((int32_t)((u - 2 + i) * r1) - L.k0) - R(L.frac);
+          const R adi = fabs(dd[i]);
+          const bool act = ok && adi <= cfine && !(l + 1 > ls && adi < b_cur);
+          const R g = g_any<R, COUNT>(dd[i], L, sp, jl, G, cfine, act, cnt);
+          T1[i] = act ? g : R(0);
+        }
+        // segments of lanes with equal u (u is non-decreasing over lanes)
+        const int32_t u32 = (int32_t)u;
+        uint32_t same = 0;
+#pragma unroll
+        for (int st = 0; st < 6; ++st) {
+          const int32_t uo = __shfl_up(u32, 1 << st);
+          if (lane >= (1 << st) && uo == u32) same |= 1u << st;
+        }
+        const int32_t un = __shfl_down(u32, 1);
+        const bool seg_end = lane == 63 || un != u32;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const int64_t kc = u - 1 + c;
+          const R d0 = dd[c], d2 = dd[c + 2];
+          const R lo = (d0 * d2 <= R(0)) ? R(0) : fmin(fabs(d0), fabs(d2));
+          const R hi = fmax(fabs(d0), fabs(d2));
+          R qmin = R(INFINITY);
+#pragma unroll
+          for (int i = 0; i < kMaxJumps; ++i)
+            if ((jm[i] & cls) && jq[i] >= lo && jq[i] <= hi) qmin = fmin(qmin, jq[i]);
+          const bool strad = ok && qmin == rq;
+#pragma unroll
+          for (int jj = -RHO / 2 + 1; jj <= RHO / 2; ++jj) {
+            if (jj == 0) continue;
+            const int64_t m = kc * RHO + jj;
+            const R d = R((int32_t)(m * rl) - L.k0) - R(L.frac);
+            const bool side_ok = side == 0 ? d > R(0) : !(d > R(0));
+            const bool own = m >= m_a && m <= m_b;
+            const bool use = strad && own && side_ok;
+            const R ad = fabs(d);
+            const R rlo = (l == ls) ? R(0) : b_prev;
+            const bool in_reg = ls <= l && ad >= rlo && ad < b_cur && ad <= cfine;
+            const bool tl = ad <= cfine && !(l > ls && ad < b_prev);
+            const bool need = use && tl && !in_reg;
+            R gl = R(0);
+            if (__builtin_amdgcn_ballot_w64(need)) gl = g_any<R, COUNT>(d, L, sp, jl, G, cfine, need, cnt);
+            const double tt = (double)jj / (double)RHO;
+            const R v0 = (need ? gl : R(0)) -
+                         (R(0.5 * tt * (tt - 1.0)) * T1[c] + R(1.0 - tt * tt) * T1[c + 1] +
+                          R(0.5 * tt * (tt + 1.0)) * T1[c + 2]);
+            R v = use ? v0 : R(0);
+#pragma unroll
+            for (int st = 0; st < 6; ++st) {
+              const R vo = __shfl_up(v, 1 << st);
+              if (same & (1u << st)) v += vo;
+            }
+            if (seg_end && own) lds_acc[m - base] += v;
+            if (COUNT && use) { n_band++; if (!in_reg) n_used++; }
+          }
+        }
+        if (COUNT && lane == 0) cnt.band_iters++;
+      }
+    }
+  }
+}
+
 // Persistent work queue: each workgroup takes items (consecutive nodes of one
 // level of one layer, heaviest levels first).  Its four wavefronts split the
 // item into region tiles, then into band groups of 64 nodes; node sums meet in
@@ -886,10 +1013,20 @@ __global__ void __launch_bounds__(256) k_level(Geometry G, LevelArgs a) {
     __syncthreads();
     // residual-band pass
     if (l < kLevels - 1 && iv->n_jump > 0) {
-      const int ngroup = (count + 63) >> 6;
-      for (int g = wv; g < ngroup; g += 4)
-        band_group<R, COUNT>(G, a, l, layer, first + ((int64_t)g << 6), count - (g << 6), iv, lds_acc, first, cnt,
-                             n_used, n_band);
+      if (iv->lc_ok) {
+        // each wavefront owns a contiguous quarter of the item's nodes
+        const int own_lo = (int)(((int64_t)count * wv) >> 2);
+        const int own_hi = (int)(((int64_t)count * (wv + 1)) >> 2);
+        if (G.r[l + 1] == 2 * G.r[l])
+          band_lines<R, COUNT, 2>(G, a, l, layer, first, own_lo, own_hi, iv, lds_acc, cnt, n_used, n_band);
+        else
+          band_lines<R, COUNT, 4>(G, a, l, layer, first, own_lo, own_hi, iv, lds_acc, cnt, n_used, n_band);
+      } else {
+        const int ngroup = (count + 63) >> 6;
+        for (int g = wv; g < ngroup; g += 4)
+          band_group<R, COUNT>(G, a, l, layer, first + ((int64_t)g << 6), count - (g << 6), iv, lds_acc, first, cnt,
+                               n_used, n_band);
+      }
     }
     __syncthreads();
     if (COUNT) {

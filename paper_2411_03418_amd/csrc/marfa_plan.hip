@@ -317,6 +317,19 @@ static bool make_intervals(const Geometry& G, int chi, std::vector<IntervalSet>&
         S.jq[k] = qs[k].first;
         S.jmask[k] = qs[k].second;
       }
+      S.lc_ok = 0;
+      S.lc_eps = 0.0;
+      if (!top && !qs.empty()) {
+        const double r1 = G.r[l + 1];
+        const int rho = G.r[l + 1] / G.r[l];
+        const double qlo = qs.front().first, qhi = qs.back().first;
+        // single-precision d carries at most half an ulp of |d| <= qhi + 3 r1
+        const double eps = 4.0 * std::ldexp(qhi + 3.0 * r1, -24) / r1 + 1e-9;
+        if ((rho == 2 || rho == 4) && qlo > 2.0 * r1 + 2.0 && eps < 0.4 && qhi + 3.0 * r1 < 16777216.0) {
+          S.lc_ok = 1;
+          S.lc_eps = eps;
+        }
+      }
     }
   }
   return true;

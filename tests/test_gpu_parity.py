@@ -163,6 +163,23 @@ def test_multi_layer_pruned_ragged():
         assert eg < 1e-5
 
 
+@pytest.mark.parametrize("fp64", [False, True])
+def test_small_cutoff_node_major_band(fp64):
+    # a cut-off below two coarsest steps: stencil hulls around a line centre
+    # can hold the cut-off jump, so the top levels take the node-major band pass
+    lines = synth.make_lines(500, 995.0, 1015.0, 35, shift=True)
+    lay = [0.3, 260.0, 0.05, 0.0]
+    req = dict(nu_begin=1000.0, nu_end=1010.0, cutoff=1.5)
+    got = run(lines, [lay], fp64=fp64, **req)[0]
+    o = _oreq(req)
+    ref_d = O.direct(lines, lay, all_nodes(req), threads=THREADS, **o)
+    ref_g = O.grid(lines, lay, threads=THREADS, **o)
+    eg, ed = rel_err(got, ref_g), rel_err(got, ref_d)
+    print(f"small cut-off fp64={fp64}: vs grid {eg:.2e} vs direct {ed:.2e}")
+    assert ed < 1e-4
+    assert eg < (1e-9 if fp64 else 1e-5)
+
+
 def test_absorption_coefficient_output():
     lines = synth.make_lines(300, 980.0, 1030.0, 32)
     lay = [0.8, 280.0, 0.2, 0.0]
