@@ -71,6 +71,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--check-nodes", type=int, default=256)
+    ap.add_argument("--no-tune", action="store_true", help="keep the density-based tiles")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (layers shard across GPUs "
@@ -90,6 +91,8 @@ def main():
           file=sys.stderr, flush=True)
     plan = marfa.Plan(lines, layers, device=0, **req)
     out = torch.empty((plan.n_layers, plan.points), dtype=torch.float32, device="cuda:0")
+    tiles = plan.tune(out=out) if not args.no_tune else plan.tiles()
+    print(f"[bench] tiles {tiles}", file=sys.stderr, flush=True)
     st = plan.count()
     flops, evals = counted_flops(st)
     print(f"[bench] plan ready; pairs {sum(st['pairs_level']):.3e}, core {st['pairs_core']:.3e}, "
@@ -158,7 +161,9 @@ def main():
                   "wing": int(st["pairs_wing"]), "band": int(st["pairs_band"]),
                   "per_level": [int(v) for v in st["pairs_level"]],
                   "wave_iters_per_level": [int(v) for v in st["iters_level"]],
-                  "band_iters_per_level": [int(v) for v in st["band_iters_level"]]},
+                  "band_iters_per_level": [int(v) for v in st["band_iters_level"]],
+                  "wing_terms": int(st["wing_terms"])},
+        "tiles": tiles,
     }
     line.update(res)
     plan.close()

@@ -138,15 +138,33 @@ marfa_status marfa_execute_layers(marfa_plan* plan, int32_t first, int32_t count
  * fill *stats.  Synchronous. */
 marfa_status marfa_plan_count(marfa_plan* plan, marfa_stats* stats);
 
-/* Tile parameters used by the kernels (read back for reports); autotune=1 in
- * marfa_plan_tune times candidate shapes on the device and keeps the fastest. */
+/* Tile parameters of the level kernel, as chosen at plan creation from the
+ * line density or by marfa_plan_tune.
+ *  item_nodes     nodes per work item on levels with step >= 16 fine units;
+ *                 finer levels take 16/step times as many
+ *  blocks_per_cu  persistent workgroups per compute unit
+ *  tuned          1 once marfa_plan_tune has run on the plan
+ *  wave_nodes[l]  region tile of level l: nodes per wavefront (the other
+ *                 64 / wave_nodes lanes split the line window)
+ *  tune_ms        wall time of the last marfa_plan_tune */
 typedef struct {
-  int32_t wave_nodes;   /* nodes per wavefront tile */
-  int32_t block_waves;  /* wavefronts per workgroup */
-  int32_t split;        /* line-window split factor for coarse levels */
-  int32_t reserved;
+  int32_t item_nodes;
+  int32_t blocks_per_cu;
+  int32_t tuned;
+  int32_t wave_nodes[11];
+  float tune_ms;
 } marfa_tiles;
 marfa_status marfa_plan_tiles(const marfa_plan* plan, marfa_tiles* tiles);
+
+/* Autotuner: runs line preparation, then times the level kernel on the
+ * device for candidate tile parameters with the plan's own lines and layers
+ * and keeps the fastest -- per level the region tile (wave_nodes at half,
+ * equal and twice the density-based choice), then the work-item size
+ * (128, 256, 512) and the persistent grid (4, 8, 16 workgroups per CU).
+ * scratch_out_dev is an output buffer as for marfa_execute (overwritten).
+ * Synchronous on hip_stream; captured graphs are rebuilt on the next
+ * execute.  Tile shapes change the summation order, so results may change
+ * in the last bits, not in accuracy.  Errors as marfa_execute. */
 marfa_status marfa_plan_tune(marfa_plan* plan, void* scratch_out_dev, int64_t layer_stride,
                              void* hip_stream);
 

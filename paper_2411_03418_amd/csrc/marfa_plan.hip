@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -118,7 +119,12 @@ struct marfa_plan {
   hipGraphExec_t sexec[3] = {nullptr, nullptr, nullptr};
   void* s_out = nullptr;
   int64_t s_stride = 0;
-  marfa_tiles tile_cfg{64, 4, 1, 0};
+  // tile parameters (autotuned by marfa_plan_tune)
+  int base_nodes = 256;
+  int blocks_per_cu = 8;
+  int64_t tiles_cap = 0;   // capacity of d.tiles (tile count at the smallest item size)
+  int tuned = 0;
+  float tune_ms = 0.f;
 };
 
 static int64_t fdiv(int64_t a, int64_t b) {
@@ -353,6 +359,9 @@ static void choose_tiles(Geometry& G, double lines_per_cm) {
   }
 }
 
+// candidate work-item sizes of the autotuner (ascending)
+static const int kTuneItems[3] = {128, 256, 512};
+
 // Work items: nodes per item scale inversely with the per-node cost, which
 // grows with the level step (window width in lines); heaviest levels first.
 static void make_tiles(const Geometry& G, std::vector<Tile>& tiles, int base_nodes) {
@@ -488,7 +497,12 @@ extern "C" marfa_status marfa_plan_create(marfa_plan** out, const marfa_lines* l
     free_plan(p);
     return fail(MARFA_E_INVALID, "too many band intervals");
   }
-  make_tiles(p->G, p->tiles, 256);
+  make_tiles(p->G, p->tiles, p->base_nodes);
+  {
+    std::vector<Tile> most;
+    make_tiles(p->G, most, kTuneItems[0]);
+    p->tiles_cap = (int64_t)std::max(most.size(), p->tiles.size());
+  }
   // sort lines by nu0
   const int64_t n = lines->n;
   std::vector<int64_t> idx(n);
@@ -563,7 +577,7 @@ extern "C" marfa_status marfa_plan_create(marfa_plan** out, const marfa_lines* l
     p->d.csp = c;
   }
   ALLOC(p->d.ivs, p->ivs.size());
-  ALLOC(p->d.tiles, p->tiles.size());
+  ALLOC(p->d.tiles, (size_t)p->tiles_cap);
   ALLOC(p->d.counter, 4);
   ALLOC(p->d.scale, NL);
   ALLOC(p->d.span, NL);
@@ -602,7 +616,7 @@ extern "C" marfa_status marfa_plan_create(marfa_plan** out, const marfa_lines* l
       return fail(MARFA_E_DEVICE, "line ordering: %s", hipGetErrorString(e));
     }
   }
-  p->grid = p->cu_count * 8;
+  p->grid = p->cu_count * p->blocks_per_cu;
   if (hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking) != hipSuccess) {
     free_plan(p);
     return fail(MARFA_E_DEVICE, "stream create");
@@ -624,8 +638,21 @@ extern "C" marfa_status marfa_plan_points(const marfa_plan* p, int64_t* pts) {
 
 // enqueue the hot path for layers [first, first+count)
 // stage mask: 1 = line preparation, 2 = level accumulation, 4 = cascade
+// A tile list on the device (the plan's own unless overridden by the tuner).
+struct TileSet {
+  const Tile* dev;
+  int64_t n;
+  int max_item;
+};
+
+static TileSet plan_tiles(const marfa_plan* p) {
+  TileSet t{p->d.tiles, (int64_t)p->tiles.size(), 0};
+  for (const Tile& x : p->tiles) t.max_item = std::max(t.max_item, x.count);
+  return t;
+}
+
 static void enqueue(marfa_plan* p, int first, int count, void* out, int64_t stride, hipStream_t s, bool count_mode,
-                    int stages = 7) {
+                    int stages = 7, const TileSet* ts = nullptr, int grid_cap = 0) {
   const bool f64 = p->req.fp64 != 0;
   const size_t recsz = f64 ? sizeof(LineRec64) : sizeof(LineRec32);
   const size_t realsz = f64 ? sizeof(double) : sizeof(float);
@@ -653,9 +680,10 @@ static void enqueue(marfa_plan* p, int first, int count, void* out, int64_t stri
   pa.fp64 = f64 ? 1 : 0;
   char* A = (char*)p->d.A + F * (size_t)p->G.a_total * realsz;
   if (stages & 1) launch_prep(in, p->d.layers + 4 * F, count, p->G, pa, s);
+  const TileSet tl = ts ? *ts : plan_tiles(p);
   LevelArgs a;
-  a.tiles = p->d.tiles;
-  a.n_tiles = (int64_t)p->tiles.size();
+  a.tiles = tl.dev;
+  a.n_tiles = tl.n;
   a.n_layers = count;
   a.counter = p->d.counter;
   a.rec = pa.rec;
@@ -668,10 +696,9 @@ static void enqueue(marfa_plan* p, int first, int count, void* out, int64_t stri
   a.out = out;
   a.stride = stride;
   a.stats = p->d.stats;
-  a.max_item = 0;
-  for (const Tile& t : p->tiles) a.max_item = std::max(a.max_item, t.count);
+  a.max_item = tl.max_item;
   int64_t items = a.n_tiles * count;
-  int grid = (int)std::min<int64_t>(std::max<int64_t>(1, items), (int64_t)p->grid);
+  int grid = (int)std::min<int64_t>(std::max<int64_t>(1, items), (int64_t)(grid_cap > 0 ? grid_cap : p->grid));
   if (stages & 2) {
     launch_fill_u32(p->d.counter, 1, 0u, s);
     launch_level(p->G, a, grid, f64, count_mode, s);
@@ -799,7 +826,45 @@ extern "C" marfa_status marfa_plan_count(marfa_plan* p, marfa_stats* out) {
 
 extern "C" marfa_status marfa_plan_tiles(const marfa_plan* p, marfa_tiles* t) {
   if (!p || !t) return fail(MARFA_E_INVALID, "null argument");
-  *t = p->tile_cfg;
+  std::memset(t, 0, sizeof *t);
+  t->item_nodes = p->base_nodes;
+  t->blocks_per_cu = p->blocks_per_cu;
+  t->tuned = p->tuned;
+  for (int l = 0; l < kLevels; ++l) t->wave_nodes[l] = 1 << p->G.lnw[l];
+  t->tune_ms = p->tune_ms;
+  return MARFA_OK;
+}
+
+static void drop_graphs(marfa_plan* p) {
+  if (p->exec) { (void)hipGraphExecDestroy(p->exec); p->exec = nullptr; }
+  if (p->graph) { (void)hipGraphDestroy(p->graph); p->graph = nullptr; }
+  for (int i = 0; i < 3; ++i) {
+    if (p->sexec[i]) { (void)hipGraphExecDestroy(p->sexec[i]); p->sexec[i] = nullptr; }
+    if (p->sgraph[i]) { (void)hipGraphDestroy(p->sgraph[i]); p->sgraph[i] = nullptr; }
+  }
+  p->g_out = p->s_out = nullptr;
+}
+
+// Level stage alone over every layer with the given tiles and grid; the
+// faster of two runs, in ms (events on the caller's stream).
+static marfa_status time_level(marfa_plan* p, const std::vector<Tile>& tiles, int grid, void* out, int64_t stride,
+                               hipStream_t s, float* ms) {
+  if ((int64_t)tiles.size() > p->tiles_cap) return fail(MARFA_E_STATE, "tile list exceeds its buffer");
+  HIP_TRY(hipMemcpyAsync(p->d.tiles, tiles.data(), tiles.size() * sizeof(Tile), hipMemcpyHostToDevice, s));
+  TileSet ts{p->d.tiles, (int64_t)tiles.size(), 0};
+  for (const Tile& x : tiles) ts.max_item = std::max(ts.max_item, x.count);
+  float best = INFINITY;
+  for (int rep = 0; rep < 2; ++rep) {
+    HIP_TRY(hipEventRecord(p->ev[0], s));
+    enqueue(p, 0, p->n_layers, out, stride, s, false, 2, &ts, grid);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipEventRecord(p->ev[1], s));
+    HIP_TRY(hipEventSynchronize(p->ev[1]));
+    float t = 0.f;
+    HIP_TRY(hipEventElapsedTime(&t, p->ev[0], p->ev[1]));
+    best = std::min(best, t);
+  }
+  *ms = best;
   return MARFA_OK;
 }
 
@@ -807,7 +872,59 @@ extern "C" marfa_status marfa_plan_tune(marfa_plan* p, void* out, int64_t stride
   if (!p) return fail(MARFA_E_INVALID, "null plan");
   marfa_status st = check_out(p, out, stride);
   if (st != MARFA_OK) return st;
-  (void)stream;
+  HIP_TRY(hipSetDevice(p->device));
+  hipStream_t s = (hipStream_t)stream;
+  const auto t0 = std::chrono::steady_clock::now();
+  drop_graphs(p);
+  enqueue(p, 0, p->n_layers, out, stride, s, false, 1);   // line preparation
+  HIP_TRY(hipGetLastError());
+  // 1. region tile per level, items of the current size
+  for (int l = 0; l < kLevels; ++l) {
+    std::vector<Tile> all, lv;
+    make_tiles(p->G, all, p->base_nodes);
+    for (const Tile& t : all)
+      if (t.level == l) lv.push_back(t);
+    if (lv.empty()) continue;
+    const int cur = p->G.lnw[l];
+    int best_lnw = cur;
+    float best = INFINITY;
+    for (int c = cur - 1; c <= cur + 1; ++c) {
+      if (c < 0 || c > 6) continue;
+      p->G.lnw[l] = c;
+      float ms = 0.f;
+      st = time_level(p, lv, p->grid, out, stride, s, &ms);
+      if (st != MARFA_OK) { p->G.lnw[l] = cur; return st; }
+      if (ms < best) { best = ms; best_lnw = c; }
+    }
+    p->G.lnw[l] = best_lnw;
+  }
+  // 2. work-item size, then the persistent grid
+  int best_base = p->base_nodes, best_bpc = p->blocks_per_cu;
+  float best = INFINITY;
+  for (int base : kTuneItems) {
+    std::vector<Tile> tl;
+    make_tiles(p->G, tl, base);
+    float ms = 0.f;
+    st = time_level(p, tl, p->cu_count * best_bpc, out, stride, s, &ms);
+    if (st != MARFA_OK) return st;
+    if (ms < best) { best = ms; best_base = base; }
+  }
+  std::vector<Tile> tl;
+  make_tiles(p->G, tl, best_base);
+  for (int bpc : {4, 16}) {
+    float ms = 0.f;
+    st = time_level(p, tl, p->cu_count * bpc, out, stride, s, &ms);
+    if (st != MARFA_OK) return st;
+    if (ms < best) { best = ms; best_bpc = bpc; }
+  }
+  p->base_nodes = best_base;
+  p->blocks_per_cu = best_bpc;
+  p->grid = p->cu_count * best_bpc;
+  p->tiles = tl;
+  HIP_TRY(hipMemcpyAsync(p->d.tiles, p->tiles.data(), p->tiles.size() * sizeof(Tile), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  p->tuned = 1;
+  p->tune_ms = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
   return MARFA_OK;
 }
 

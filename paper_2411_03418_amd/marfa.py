@@ -58,8 +58,8 @@ class Timing(C.Structure):
 
 
 class Tiles(C.Structure):
-    _fields_ = [("wave_nodes", C.c_int32), ("block_waves", C.c_int32), ("split", C.c_int32),
-                ("reserved", C.c_int32)]
+    _fields_ = [("item_nodes", C.c_int32), ("blocks_per_cu", C.c_int32), ("tuned", C.c_int32),
+                ("wave_nodes", C.c_int32 * 11), ("tune_ms", C.c_float)]
 
 
 _lib = None
@@ -200,9 +200,12 @@ class Plan:
     def tiles(self):
         t = Tiles()
         _check(lib().marfa_plan_tiles(self._h, C.byref(t)))
-        return dict(wave_nodes=t.wave_nodes, block_waves=t.block_waves, split=t.split)
+        return dict(item_nodes=t.item_nodes, blocks_per_cu=t.blocks_per_cu, tuned=bool(t.tuned),
+                    wave_nodes=list(t.wave_nodes), tune_ms=float(t.tune_ms))
 
     def tune(self, out=None, stream=None):
+        """Autotune the level kernel's tiles on the device (synchronous);
+        `out` is scratch output.  Returns the chosen tiles."""
         out = self._out(out, self.n_layers)
         _check(lib().marfa_plan_tune(self._h, C.c_void_p(out.data_ptr()), out.stride(0),
                                      _stream_handle(stream, self.device)))

@@ -2,8 +2,15 @@
 
 Gates (relative, on nodes where the direct sum is >= 1e-8 of the layer max):
 GPU single precision vs the definition <= 1e-4; vs the oracle's eleven-grid
-result <= 1e-5 (implementation error only); GPU double precision vs the
-oracle's eleven-grid result <= 1e-9.
+result <= FP32_VS_GRID (implementation error only); GPU double precision vs
+the oracle's eleven-grid result <= 1e-9.
+
+FP32_VS_GRID = 3e-5: the eleven-grid result at a weak node next to a strong
+line's cut-off is a coarse-level sum holding that line's wing minus a band
+correction of the same size, so single-precision rounding of the coarse sums
+(about 1e-7 of their value) is amplified by their ratio to the node value;
+with summation orders from other tile shapes this reaches 1.5e-5 at nodes
+near 1e-8 of the layer max.
 """
 import os
 
@@ -17,6 +24,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 THREADS = min(16, os.cpu_count() or 1)
+FP32_VS_GRID = 3e-5
 
 
 def marfa():
@@ -128,7 +136,7 @@ def test_one_line_parity(case, fp64):
     eg, ed = rel_err(got, ref_g), rel_err(got, ref_d)
     print(f"vs grid {eg:.2e}  vs direct {ed:.2e}")
     assert ed < 1e-4
-    assert eg < (1e-9 if fp64 else 1e-5)
+    assert eg < (1e-9 if fp64 else FP32_VS_GRID)
 
 
 # ------------------------------------------------------------------ workloads
@@ -144,7 +152,7 @@ def test_single_1k_workload(fp64):
     eg, ed = rel_err(got, ref_g), rel_err(got, ref_d)
     print(f"single_1k fp64={fp64}: vs grid {eg:.2e} vs direct {ed:.2e}")
     assert ed < 1e-4
-    assert eg < (1e-9 if fp64 else 1e-5)
+    assert eg < (1e-9 if fp64 else FP32_VS_GRID)
 
 
 def test_multi_layer_pruned_ragged():
@@ -160,7 +168,7 @@ def test_multi_layer_pruned_ragged():
         eg, ed = rel_err(got[i], ref_g), rel_err(got[i], ref_d)
         print(f"layer {i}: vs grid {eg:.2e} vs direct {ed:.2e}")
         assert ed < 1e-4
-        assert eg < 1e-5
+        assert eg < FP32_VS_GRID
 
 
 @pytest.mark.parametrize("fp64", [False, True])
@@ -177,7 +185,7 @@ def test_small_cutoff_node_major_band(fp64):
     eg, ed = rel_err(got, ref_g), rel_err(got, ref_d)
     print(f"small cut-off fp64={fp64}: vs grid {eg:.2e} vs direct {ed:.2e}")
     assert ed < 1e-4
-    assert eg < (1e-9 if fp64 else 1e-5)
+    assert eg < (1e-9 if fp64 else FP32_VS_GRID)
 
 
 def test_absorption_coefficient_output():
@@ -206,7 +214,7 @@ def test_range_starting_at_zero():
     ref_d = O.direct(lines, lay, all_nodes(req), threads=THREADS, **o)
     ref_g = O.grid(lines, lay, threads=THREADS, **o)
     assert rel_err(got, ref_d) < 1e-4
-    assert rel_err(got, ref_g) < 1e-5
+    assert rel_err(got, ref_g) < FP32_VS_GRID
 
 
 def test_deterministic_and_graph_replay():
@@ -234,6 +242,34 @@ def test_deterministic_and_graph_replay():
     torch.cuda.synchronize()
     assert torch.equal(sub, a[1:3])
     plan.close()
+
+
+def test_autotune_keeps_parity():
+    M = marfa()
+    lines = synth.make_lines(3000, 930.0, 1090.0, 36, shift=True)
+    layers = synth.pt_table(5)
+    req = dict(nu_begin=1000.0, nu_end=1012.0, cutoff=60.0, chi="tonkov", prune=1e-6)
+    plan = M.Plan(lines, layers, device=0, **req)
+    before = plan.tiles()
+    assert not before["tuned"]
+    a = plan.execute().clone()
+    t = plan.tune()
+    print("tuned tiles", t)
+    assert t["tuned"] and t["tune_ms"] > 0
+    assert t["item_nodes"] in (128, 256, 512) and t["blocks_per_cu"] in (4, 8, 16)
+    assert all(w in (1, 2, 4, 8, 16, 32, 64) for w in t["wave_nodes"])
+    b = plan.execute()
+    torch.cuda.synchronize()
+    got = b.double().cpu().numpy()
+    c = plan.execute().clone()   # replays of the re-captured graph are identical
+    torch.cuda.synchronize()
+    assert torch.equal(b, c)
+    assert torch.allclose(a, b, rtol=1e-5, atol=0)
+    plan.close()
+    o = _oreq(req)
+    for i in range(layers.shape[0]):
+        ref_g = O.grid(lines, layers[i], threads=THREADS, **o)
+        assert rel_err(got[i], ref_g) < FP32_VS_GRID
 
 
 def test_single_200k_sampled():
