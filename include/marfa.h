@@ -82,7 +82,9 @@ typedef struct {
   int32_t shape;              /* marfa_shape */
   int32_t chi;                /* marfa_chi */
   int32_t out_kind;           /* marfa_output */
-  int32_t eval;               /* marfa_eval */
+  int32_t eval;               /* MARFA_EVAL_PLAIN; MARFA_EVAL_SURROGATE is refused here
+                                 (MARFA_E_UNSUPPORTED): attach a trained network to a
+                                 plain plan with marfa_plan_set_surrogate */
   double prune_rel;
   double R;
   int32_t level_table;
@@ -180,6 +182,90 @@ marfa_status marfa_execute_timed(marfa_plan* plan, void* out_dev, int64_t layer_
                                  marfa_timing* t);
 
 void marfa_plan_destroy(marfa_plan* plan);
+
+/* ------------------------------------------------------------------
+ * Learned line shape (the surrogate of the Voigt x chi line shape).
+ *
+ * A 3-64-64-64-64-1 SiLU network, weights rounded to BF16, evaluated and
+ * trained with BF16-in / FP32-accumulate matrix-core instructions.  For a
+ * line with Voigt parameters x = sqrt(ln2) d / alpha_D, y = sqrt(ln2)
+ * gamma_L / alpha_D (Eq.(7)-(8)) it predicts t = log(K chi) - log(Kb), the
+ * residual of K(x, y) chi(|d|) (Eq.(10)) against the analytic base
+ *   Kb = y / (sqrt(pi) (x^2 + y^2 + 1/2)) + exp(-x^2) / (1 + sqrt(pi) y)^2,
+ * from the inputs f = (asinh|x| / 8, log10(y) / 2, max(|d| - 3, 0) / c)
+ * (|d|, c in cm^-1).  A network serves one (chi, cut-off) pair.  Parameters
+ * are 12801 FP32 values packed as W0[64][3], b0[64], W1[64][64], b1[64],
+ * W2, b2, W3, b3, W4[1][64], b4[1] (row-major [out][in]).
+ * ------------------------------------------------------------------ */
+typedef struct marfa_surrogate marfa_surrogate;
+
+/* Lines and layers a surrogate is trained for: line centres in
+ * [nu_lo, nu_hi] cm^-1 and temperatures in [T_lo, T_hi] K (the Doppler widths
+ * of the samples), molar mass in g/mol.  All > 0, lo <= hi. */
+typedef struct {
+  double nu_lo, nu_hi;
+  double T_lo, T_hi;
+  double molar_mass_g;
+} marfa_sample_cfg;
+
+/* Training run: n_train samples drawn once (n_val more for validation),
+ * `epochs` passes in mini-batches of `batch` (a multiple of 32), Adam with
+ * a cosine learning-rate schedule from lr_max to lr_min after a 2 % warm-up,
+ * samples from a counter-based generator seeded by `seed`. */
+typedef struct {
+  int64_t n_train, n_val;
+  int32_t epochs, batch;
+  float lr_max, lr_min;
+  uint64_t seed;
+} marfa_train_cfg;
+
+/* Outcome: final mini-batch loss, validation mean-squared and mean/max
+ * absolute error of t, wall time, optimizer steps, and the largest |x| of
+ * the training distribution (pairs beyond it use the plain line shape). */
+typedef struct {
+  float train_loss, val_loss, val_max_abs, val_mean_abs;
+  float ms;
+  int64_t steps;
+  double x_max;
+} marfa_train_report;
+
+/* New network for (chi, cutoff) on `device`: Glorot-uniform weights from a
+ * counter-based generator seeded by `seed`, zero biases.  Errors:
+ * MARFA_E_INVALID (unknown chi, cutoff <= 0), MARFA_E_DEVICE, MARFA_E_NOMEM. */
+marfa_status marfa_surrogate_create(marfa_surrogate** out, int32_t chi, double cutoff, uint64_t seed,
+                                    int32_t device);
+/* Replace / read the FP32 parameters (host arrays of n = 12801 values);
+ * setting them resets the optimizer state.  Synchronous. */
+marfa_status marfa_surrogate_set_params(marfa_surrogate* s, const float* params, int64_t n);
+marfa_status marfa_surrogate_get_params(const marfa_surrogate* s, float* params, int64_t n);
+/* Network output t for n samples: X_dev [n][3] features, out_dev [n], both
+ * device memory on the surrogate's device.  Asynchronous on hip_stream. */
+marfa_status marfa_surrogate_forward(marfa_surrogate* s, const float* X_dev, int64_t n, float* out_dev,
+                                     void* hip_stream);
+/* Mean-squared error over n samples (targets T_dev [n]) and its gradient
+ * with respect to the 12801 parameters, evaluated with the BF16-rounded
+ * weights the forward pass uses; loss and grad are host outputs.  Synchronous. */
+marfa_status marfa_surrogate_loss_grad(marfa_surrogate* s, const float* X_dev, const float* T_dev, int64_t n,
+                                       float* loss, float* grad);
+/* n training samples on the device (features X_dev [n][3], targets T_dev
+ * [n]) with targets from the double-precision device line shape.
+ * Asynchronous on hip_stream. */
+marfa_status marfa_surrogate_make_samples(marfa_surrogate* s, const marfa_sample_cfg* c, uint64_t seed, int64_t n,
+                                          float* X_dev, float* T_dev, void* hip_stream);
+/* Draw samples and train on the device (forward, backward and Adam kernels);
+ * synchronous; fills *report and marks the network trained. */
+marfa_status marfa_surrogate_train(marfa_surrogate* s, const marfa_sample_cfg* c, const marfa_train_cfg* cfg,
+                                   marfa_train_report* report);
+void marfa_surrogate_destroy(marfa_surrogate* s);
+
+/* Evaluate the plan's line shapes with a trained surrogate (NULL: the plain
+ * line shape again).  Pairs outside the trained domain (y outside
+ * [1e-4, 1e3] or |x| above the report's x_max) take the plain line shape.
+ * Requires a single-precision Voigt plan with the surrogate's chi and
+ * cut-off.  The surrogate must outlive its use by the plan.  Errors:
+ * MARFA_E_INVALID (mismatch), MARFA_E_UNSUPPORTED (untrained network, a
+ * cut-off under two coarsest steps). */
+marfa_status marfa_plan_set_surrogate(marfa_plan* plan, const marfa_surrogate* s);
 
 const char* marfa_status_string(int32_t status);
 /* Copy the calling thread's last error text into buf (NUL-terminated). */

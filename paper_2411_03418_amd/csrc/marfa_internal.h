@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include "marfa.h"
+#include "marfa_mlp.h"
 
 namespace marfa {
 
@@ -160,6 +161,11 @@ struct LevelArgs {
   int64_t stride;
   unsigned long long* stats;  // counting mode only
   int32_t max_item;      // largest work item (nodes), sizes the LDS accumulator
+  // learned line shape (single-precision Voigt plans with a surrogate)
+  int32_t surr;
+  float mlp_xmax;        // pairs with |x| above it use the plain shape
+  float mlp_inv_c;       // 1 / cut-off [cm]
+  MlpDev mlp;
 };
 
 hipError_t upload_weideman(const double* a32, const double* a64, const double* L2);
@@ -179,6 +185,19 @@ struct PrepArgs {
 void launch_prep(const LineIn& in, const double* layers, int nL, const Geometry& G, const PrepArgs& pa,
                  hipStream_t s);
 void launch_level(const Geometry& G, const LevelArgs& a, int grid, bool fp64, bool count, hipStream_t s);
+// training samples of the learned line shape (ranges of the lines and layers it serves)
+struct MlpSampleCfg {
+  double nu_lo, nu_hi;     // line centres [cm^-1]
+  double T_lo, T_hi;       // temperatures [K]
+  double molar_mass;       // [g/mol]
+  double y_lo, y_hi;       // Voigt y range
+  double cutoff;           // [cm^-1]
+  int32_t chi, pad;
+};
+void launch_mlp_samples(const MlpSampleCfg& c, uint64_t seed, int64_t n, float* X, float* T, hipStream_t s);
+// error text of the calling thread, and device set-up (Weideman tables)
+marfa_status marfa_set_error(marfa_status st, const char* msg);
+marfa_status marfa_use_device(int device);
 void launch_rank(const LineIn& in, const double* layers, int nL, const double* span, int32_t* perm, hipStream_t s);
 void launch_cascade(const Geometry& G, int nL, void* A, void* out, int64_t stride, const double* scale, bool fp64,
                     hipStream_t s);

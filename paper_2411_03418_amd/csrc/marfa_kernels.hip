@@ -525,15 +525,53 @@ __device__ __forceinline__ R g_any(R d, const typename RecOf<R>::T& L, const R* 
   return ad <= cfine ? v : R(0);
 }
 
+// S' F(d) chi(|d|) through the learned line shape, for one (line, node) pair
+// per lane; wave-collective (all 64 lanes call it together).  Pairs outside
+// the trained domain that are live use the plain shape.  With A = S'
+// gamma_L / pi and y = xs gamma_L: S' F chi = A sqrt(pi) xs^2 / y Kb e^t.
+template <bool COUNT>
+__device__ float g_surr(float d, const LineRec32& L, const float* __restrict__ sp, int32_t j, const Geometry& G,
+                        const LevelArgs& a, bool live, Counts& cnt) {
+  const float dcm = d * float(kH0);
+  const float x = L.xs * dcm;
+  const float y = L.xs * L.gam;
+  const bool dom = y >= kMlpYMin && y <= kMlpYMax && fabsf(x) <= a.mlp_xmax;
+  float f1, f2, f3;
+  mlp_features(x, dom ? y : 1.0f, fabsf(dcm), a.mlp_inv_c, f1, f2, f3);
+  const float t = mlp_forward_wave(a.mlp, f1, f2, f3);
+  float v = L.A * 1.7724538509055160f * L.xs * L.xs * __builtin_amdgcn_rcpf(dom ? y : 1.0f) * mlp_base(x, y) *
+            __expf(t);
+  v = dom ? v : 0.0f;
+  if (__builtin_amdgcn_ballot_w64(live && !dom)) {
+    const float pv = shape_fast<float, COUNT>(d, L, sp, j, G, live && !dom, cnt) * chi_any<float>(fabsf(d), G);
+    v = dom ? v : pv;
+  }
+  return v;
+}
+
+// g(d) with the cut-off, plain or learned (wave-collective when SURR)
+template <typename R, bool COUNT, bool SURR>
+__device__ __forceinline__ R g_eval(R d, const typename RecOf<R>::T& L, const R* __restrict__ sp, int32_t j,
+                                    const Geometry& G, R cfine, bool live, Counts& cnt, const LevelArgs& a) {
+  if constexpr (SURR) {
+    const float v = g_surr<COUNT>(d, L, sp, j, G, a, live && fabsf(d) <= cfine, cnt);
+    return fabsf(d) <= cfine ? v : 0.0f;
+  } else {
+    (void)a;
+    return g_any<R, COUNT>(d, L, sp, j, G, cfine, live, cnt);
+  }
+}
+
 // Region pass: scan lines [j0, j1) of one window side (SGN = +1: d > 0,
 // -1: d < 0, 0: both) and add g(d) for every (node, line) pair in the line's
 // region at this level.
-template <typename R, bool COUNT, int SGN>
+template <typename R, bool COUNT, int SGN, bool SURR>
 __device__ __forceinline__ void scan_region(const typename RecOf<R>::T* __restrict__ rec, const R* __restrict__ sp,
                                             int32_t j0, int32_t j1,
                                             int S, int slice, int32_t X, bool active, R ra, R rb, bool chi_one,
                                             bool chi_mixed, R c0, R c1, int l, const Geometry& G, R cfine,
-                                            R b_prev, R b_cur, R& acc, Counts& cnt, uint32_t& n_used) {
+                                            R b_prev, R b_cur, R& acc, Counts& cnt, uint32_t& n_used,
+                                            const LevelArgs& a) {
   using Rec = typename RecOf<R>::T;
   const bool generic_shape = G.shape == MARFA_SHAPE_DOPPLER;
   int32_t jn = j0 + slice;
@@ -552,7 +590,11 @@ __device__ __forceinline__ void scan_region(const typename RecOf<R>::T* __restri
     const R rlo = (l == ls) ? R(0) : b_prev;
     const bool in_reg = in_win && ls <= l && ad >= rlo && ad < b_cur && ad <= cfine;
     R val;
-    if (!generic_shape) {
+    if constexpr (SURR) {
+      (void)generic_shape;
+      const float g = g_surr<COUNT>(d, L, sp, j, G, a, in_reg, cnt);
+      val = in_reg ? g : R(0);
+    } else if (!generic_shape) {
       const R g = shape_fast<R, COUNT>(d, L, sp, j, G, in_reg, cnt);
       R chi;
       if (chi_one) chi = R(1);
@@ -599,22 +641,28 @@ template <> struct RecBuf<double> {
 
 // Fast region scan for layers whose lines all start below level l: one side
 // (SGN) of the annulus, |d| in [ra, rbx), chi one exponential piece (or any).
-template <typename R, bool COUNT, int SGN>
+template <typename R, bool COUNT, int SGN, bool SURR>
 __device__ __forceinline__ void scan_fast(__amdgpu_buffer_rsrc_t rs, const R* __restrict__ sp, int32_t j0,
                                           int32_t j1, int S, int slice, int32_t X, R ra, R rbx, bool chi_none,
                                           bool chi_mixed, R c0, R c1, const Geometry& G, R& acc, Counts& cnt,
-                                          uint32_t& n_used) {
+                                          uint32_t& n_used, const LevelArgs& a) {
   using Rec = typename RecOf<R>::T;
   const R c1s = SGN > 0 ? c1 : -c1;   // chi exponent slope in the signed distance
   auto step = [&](const Rec& L, int32_t j) {
     const R d = R(X - L.k0) - R(L.frac);
     const bool in_reg = SGN > 0 ? (d >= ra && d < rbx) : (d <= -ra && d > -rbx);
-    const R g = shape_fast<R, COUNT>(d, L, sp, j, G, in_reg, cnt);
-    R chi;
-    if (chi_none) chi = R(1);
-    else if (!chi_mixed) chi = fast_exp2<R>(fma(c1s, d, c0));
-    else chi = chi_any<R>(fabs(d), G);
-    acc += in_reg ? g * chi : R(0);
+    if constexpr (SURR) {
+      const float g = g_surr<COUNT>(d, L, sp, j, G, a, in_reg, cnt);
+      acc += in_reg ? g : R(0);
+    } else {
+      (void)a;
+      const R g = shape_fast<R, COUNT>(d, L, sp, j, G, in_reg, cnt);
+      R chi;
+      if (chi_none) chi = R(1);
+      else if (!chi_mixed) chi = fast_exp2<R>(fma(c1s, d, c0));
+      else chi = chi_any<R>(fabs(d), G);
+      acc += in_reg ? g * chi : R(0);
+    }
     if (COUNT && in_reg) n_used++;
   };
   int32_t j = j0 + slice;
@@ -665,7 +713,7 @@ __device__ __forceinline__ int stencil_of(const Geometry& G, int l, int64_t m, i
 // lane = node * S + slice, S = 64 / nw.  For every region window the tile
 // walks the union of its nodes' line ranges, S consecutive lines per step
 // (coalesced loads); node sums are reduced over slices and stored to LDS.
-template <typename R, bool COUNT>
+template <typename R, bool COUNT, bool SURR>
 __device__ void region_tile(const Geometry& G, const LevelArgs& a, int l, int layer, int lnw, int64_t rel0,
                             int tile_left, const IntervalSet* iv, R* lds_acc, int64_t item_first, Counts& cnt,
                             uint32_t& n_used) {
@@ -722,11 +770,11 @@ __device__ void region_tile(const Geometry& G, const LevelArgs& a, int l, int la
       const __amdgpu_buffer_rsrc_t rs =
           __builtin_amdgcn_make_buffer_rsrc((void*)rec, 0, (int)(j1 * (int32_t)sizeof(Rec)), 0x00020000);
       if (side == 0)
-        scan_fast<R, COUNT, 1>(rs, sp, j0, j1, S, slice, X, ra, rbx, chi_none, chi_mixed, c0, c1, G, acc, cnt,
-                               n_used);
+        scan_fast<R, COUNT, 1, SURR>(rs, sp, j0, j1, S, slice, X, ra, rbx, chi_none, chi_mixed, c0, c1, G, acc,
+                                      cnt, n_used, a);
       else
-        scan_fast<R, COUNT, -1>(rs, sp, j0, j1, S, slice, X, ra, rbx, chi_none, chi_mixed, c0, c1, G, acc, cnt,
-                                n_used);
+        scan_fast<R, COUNT, -1, SURR>(rs, sp, j0, j1, S, slice, X, ra, rbx, chi_none, chi_mixed, c0, c1, G, acc,
+                                      cnt, n_used, a);
     }
     for (int o = S >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
     if (active && slice == 0) lds_acc[m - G.lo[l] - item_first] = acc;
@@ -742,20 +790,20 @@ __device__ void region_tile(const Geometry& G, const LevelArgs& a, int l, int la
       const int32_t j0 = uniform(__shfl(my_j, 2 * ws_i)), j1 = uniform(__shfl(my_j, 2 * ws_i + 1));
       ++ws_i;
       if (j0 < j1)
-        scan_region<R, COUNT, 0>(rec, sp, j0, j1, S, slice, X, active, ra, rb, chi_one, chi_mixed, c0, c1, l, G, cfine,
-                                 b_prev, b_cur, acc, cnt, n_used);
+        scan_region<R, COUNT, 0, SURR>(rec, sp, j0, j1, S, slice, X, active, ra, rb, chi_one, chi_mixed, c0, c1, l, G, cfine,
+                                 b_prev, b_cur, acc, cnt, n_used, a);
     } else {
       int32_t j0 = uniform(__shfl(my_j, 2 * ws_i)), j1 = uniform(__shfl(my_j, 2 * ws_i + 1));
       ++ws_i;
       if (j0 < j1)
-        scan_region<R, COUNT, 1>(rec, sp, j0, j1, S, slice, X, active, ra, rb, chi_one, chi_mixed, c0, c1, l, G, cfine,
-                                 b_prev, b_cur, acc, cnt, n_used);
+        scan_region<R, COUNT, 1, SURR>(rec, sp, j0, j1, S, slice, X, active, ra, rb, chi_one, chi_mixed, c0, c1, l, G, cfine,
+                                 b_prev, b_cur, acc, cnt, n_used, a);
       j0 = uniform(__shfl(my_j, 2 * ws_i));
       j1 = uniform(__shfl(my_j, 2 * ws_i + 1));
       ++ws_i;
       if (j0 < j1)
-        scan_region<R, COUNT, -1>(rec, sp, j0, j1, S, slice, X, active, ra, rb, chi_one, chi_mixed, c0, c1, l, G, cfine,
-                                  b_prev, b_cur, acc, cnt, n_used);
+        scan_region<R, COUNT, -1, SURR>(rec, sp, j0, j1, S, slice, X, active, ra, rb, chi_one, chi_mixed, c0, c1, l, G, cfine,
+                                  b_prev, b_cur, acc, cnt, n_used, a);
     }
   }
   for (int o = S >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
@@ -857,7 +905,7 @@ __device__ void band_group(const Geometry& G, const LevelArgs& a, int l, int lay
 // centre estimate -- non-decreasing in line order -- merges corrections of a
 // node before one lane adds them to its LDS slot.  Per slot there is one
 // writer and a fixed summation order, so results are reproducible.
-template <typename R, bool COUNT, int RHO>
+template <typename R, bool COUNT, int RHO, bool SURR>
 __device__ void band_lines(const Geometry& G, const LevelArgs& a, int l, int layer, int64_t item_first, int own_lo,
                            int own_hi, const IntervalSet* iv, R* lds_acc, Counts& cnt, uint32_t& n_used,
                            uint32_t& n_band) {
@@ -912,7 +960,7 @@ __device__ void band_lines(const Geometry& G, const LevelArgs& a, int l, int lay
           dd[i] = R((int32_t)((u - 2 + i) * r1) - L.k0) - R(L.frac);
           const R adi = fabs(dd[i]);
           const bool act = ok && adi <= cfine && !(l + 1 > ls && adi < b_cur);
-          const R g = g_any<R, COUNT>(dd[i], L, sp, jl, G, cfine, act, cnt);
+          const R g = g_eval<R, COUNT, SURR>(dd[i], L, sp, jl, G, cfine, act, cnt, a);
           T1[i] = act ? g : R(0);
         }
         // segments of lanes with equal u (u is non-decreasing over lanes)
@@ -950,7 +998,7 @@ __device__ void band_lines(const Geometry& G, const LevelArgs& a, int l, int lay
             const bool tl = ad <= cfine && !(l > ls && ad < b_prev);
             const bool need = use && tl && !in_reg;
             R gl = R(0);
-            if (__builtin_amdgcn_ballot_w64(need)) gl = g_any<R, COUNT>(d, L, sp, jl, G, cfine, need, cnt);
+            if (__builtin_amdgcn_ballot_w64(need)) gl = g_eval<R, COUNT, SURR>(d, L, sp, jl, G, cfine, need, cnt, a);
             const double tt = (double)jj / (double)RHO;
             const R v0 = (need ? gl : R(0)) -
                          (R(0.5 * tt * (tt - 1.0)) * T1[c] + R(1.0 - tt * tt) * T1[c + 1] +
@@ -975,7 +1023,7 @@ __device__ void band_lines(const Geometry& G, const LevelArgs& a, int l, int lay
 // level of one layer, heaviest levels first).  Its four wavefronts split the
 // item into region tiles, then into band groups of 64 nodes; node sums meet in
 // LDS and are written once.
-template <typename R, bool COUNT>
+template <typename R, bool COUNT, bool SURR>
 __global__ void __launch_bounds__(256) k_level(Geometry G, LevelArgs a) {
   extern __shared__ char smem_raw[];
   R* lds_acc = reinterpret_cast<R*>(smem_raw);
@@ -1008,7 +1056,7 @@ __global__ void __launch_bounds__(256) k_level(Geometry G, LevelArgs a) {
     const int lnw = G.lnw[l];
     const int ntile = (count + (1 << lnw) - 1) >> lnw;
     for (int t = wv; t < ntile; t += 4)
-      region_tile<R, COUNT>(G, a, l, layer, lnw, first + ((int64_t)t << lnw), count - (t << lnw), iv, lds_acc,
+      region_tile<R, COUNT, SURR>(G, a, l, layer, lnw, first + ((int64_t)t << lnw), count - (t << lnw), iv, lds_acc,
                             first, cnt, n_used);
     __syncthreads();
     // residual-band pass
@@ -1018,9 +1066,9 @@ __global__ void __launch_bounds__(256) k_level(Geometry G, LevelArgs a) {
         const int own_lo = (int)(((int64_t)count * wv) >> 2);
         const int own_hi = (int)(((int64_t)count * (wv + 1)) >> 2);
         if (G.r[l + 1] == 2 * G.r[l])
-          band_lines<R, COUNT, 2>(G, a, l, layer, first, own_lo, own_hi, iv, lds_acc, cnt, n_used, n_band);
+          band_lines<R, COUNT, 2, SURR>(G, a, l, layer, first, own_lo, own_hi, iv, lds_acc, cnt, n_used, n_band);
         else
-          band_lines<R, COUNT, 4>(G, a, l, layer, first, own_lo, own_hi, iv, lds_acc, cnt, n_used, n_band);
+          band_lines<R, COUNT, 4, SURR>(G, a, l, layer, first, own_lo, own_hi, iv, lds_acc, cnt, n_used, n_band);
       } else {
         const int ngroup = (count + 63) >> 6;
         for (int g = wv; g < ngroup; g += 4)
@@ -1087,23 +1135,74 @@ __global__ void k_cascade(Geometry G, int l, R* A, R* out, int64_t stride, const
   }
 }
 
-// device Voigt for tests: K(x, y) through the hot-path shape code
+// K(x, y) through the hot-path shape code: a line with alpha_D = sqrt(ln 2)
+// (so x = d and y = gamma_L in cm^-1) and unit intensity has F = K / sqrt(pi)
 template <typename R>
-__global__ void k_voigt_eval(int64_t n, const double* x, const double* y, double* out) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+__device__ double device_K(double x, double y) {
   typename RecOf<R>::T L{};
-  // alpha_D = sqrt(ln 2): x = d, y = gamma_L, F = K / sqrt(pi)
-  L.k0 = 0; L.frac = 0; L.A = R(y[i] * kInvPi);
-  L.gam = R(y[i]); L.gam2 = R(y[i]) * R(y[i]);
+  L.k0 = 0; L.frac = 0; L.A = R(y * kInvPi);
+  L.gam = R(y); L.gam2 = R(y) * R(y);
   L.ae = R(0.5); L.xs = R(1); L.s = 0;
   Geometry G{};
   G.shape = MARFA_SHAPE_VOIGT;
   G.chi = MARFA_CHI_NONE;
   Counts c{0, 0, 0, 0, 0};
-  R d = R(x[i]) * R(2048);  // fine units
+  R d = R(x) * R(2048);  // fine units
   R f = line_value<R, false>(d, L, R(1), G, R(INFINITY), c);
-  out[i] = (double)f * 1.772453850905516;
+  return (double)f * 1.772453850905516;
+}
+
+// device Voigt for tests
+template <typename R>
+__global__ void k_voigt_eval(int64_t n, const double* x, const double* y, double* out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  out[i] = device_K<R>(x[i], y[i]);
+}
+
+// ------------------------------------------------------------------
+// training samples of the learned line shape
+// ------------------------------------------------------------------
+__device__ __forceinline__ uint64_t splitmix64(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+__device__ __forceinline__ double uniform01(uint64_t seed, uint64_t ctr) {
+  return (double)(splitmix64(seed ^ splitmix64(ctr)) >> 11) * 0x1.0p-53;
+}
+
+// Sample i: a line centre nu0 and temperature T uniform over the configured
+// ranges (alpha_D from Section 2.2's Doppler width), y log-uniform, and the
+// distance |d| from a mixture -- log-uniform over [1e-6, c], uniform over
+// [0, c], and uniform over the Doppler core (x in [0, 8]).  Inputs are the
+// network features; the target is log(K chi) - log(Kb) with K from the
+// double-precision device line shape and chi from Eq.(10).
+__global__ void k_mlp_samples(MlpSampleCfg c, uint64_t seed, int64_t n, float* __restrict__ X,
+                              float* __restrict__ T) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint64_t b = (uint64_t)i * 8;
+  const double nu0 = c.nu_lo + (c.nu_hi - c.nu_lo) * uniform01(seed, b + 0);
+  const double Tk = c.T_lo + (c.T_hi - c.T_lo) * uniform01(seed, b + 1);
+  const double aD = nu0 / kCLight * sqrt(2.0 * kLn2d * kBoltzmann * kNA * Tk / (c.molar_mass * 1e-3));
+  const double y = exp(log(c.y_lo) + (log(c.y_hi) - log(c.y_lo)) * uniform01(seed, b + 2));
+  const double u = uniform01(seed, b + 3), v = uniform01(seed, b + 4);
+  const double sq = sqrt(kLn2d);
+  double ad;
+  if (u < 0.35) ad = exp(log(1e-6) + (log(c.cutoff) - log(1e-6)) * v);
+  else if (u < 0.65) ad = c.cutoff * v;
+  else ad = fmin(c.cutoff, 8.0 * aD / sq * v);
+  const double x = sq * ad / aD;
+  const double K = device_K<double>(x, y);
+  const double chi = c.chi == MARFA_CHI_TONKOV ? tonkov<double>(ad) : 1.0;
+  const double x2 = x * x, up = 1.0 + 1.7724538509055160 * y;
+  const double kb = y / (1.7724538509055160 * (x2 + y * y + 0.5)) + exp(-x2) / (up * up);
+  X[3 * i + 0] = (float)(asinh(x) * 0.125);
+  X[3 * i + 1] = (float)(log10(y) * 0.5);
+  X[3 * i + 2] = (float)(fmax(ad - 3.0, 0.0) / c.cutoff);
+  T[i] = (float)(log(K * chi) - log(kb));
 }
 
 // ------------------------------------------------------------------
@@ -1149,11 +1248,12 @@ void launch_prep(const LineIn& in, const double* layers, int nL, const Geometry&
 void launch_level(const Geometry& G, const LevelArgs& a, int grid, bool fp64, bool count, hipStream_t s) {
   const size_t smem = (size_t)a.max_item * (fp64 ? sizeof(double) : sizeof(float));
   if (fp64) {
-    if (count) k_level<double, true><<<grid, 256, smem, s>>>(G, a);
-    else k_level<double, false><<<grid, 256, smem, s>>>(G, a);
+    if (count) k_level<double, true, false><<<grid, 256, smem, s>>>(G, a);
+    else k_level<double, false, false><<<grid, 256, smem, s>>>(G, a);
   } else {
-    if (count) k_level<float, true><<<grid, 256, smem, s>>>(G, a);
-    else k_level<float, false><<<grid, 256, smem, s>>>(G, a);
+    if (count) k_level<float, true, false><<<grid, 256, smem, s>>>(G, a);
+    else if (a.surr) k_level<float, false, true><<<grid, 256, smem, s>>>(G, a);
+    else k_level<float, false, false><<<grid, 256, smem, s>>>(G, a);
   }
 }
 
@@ -1172,6 +1272,11 @@ void launch_cascade(const Geometry& G, int nL, void* A, void* out, int64_t strid
     else
       k_cascade<float><<<grid, 256, 0, s>>>(G, l, (float*)A, (float*)out, stride, scale);
   }
+}
+
+void launch_mlp_samples(const MlpSampleCfg& c, uint64_t seed, int64_t n, float* X, float* T, hipStream_t s) {
+  if (n <= 0) return;
+  k_mlp_samples<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(c, seed, n, X, T);
 }
 
 void launch_voigt_eval(int64_t n, const double* x, const double* y, double* out, bool fp64, hipStream_t s) {

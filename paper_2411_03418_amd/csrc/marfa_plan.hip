@@ -90,6 +90,11 @@ static marfa_status ensure_device(int device) {
   return MARFA_OK;
 }
 
+namespace marfa {
+marfa_status marfa_set_error(marfa_status st, const char* msg) { return fail(st, "%s", msg); }
+marfa_status marfa_use_device(int device) { return ensure_device(device); }
+}  // namespace marfa
+
 // ------------------------------------------------------------------
 // plan
 // ------------------------------------------------------------------
@@ -125,7 +130,15 @@ struct marfa_plan {
   int64_t tiles_cap = 0;   // capacity of d.tiles (tile count at the smallest item size)
   int tuned = 0;
   float tune_ms = 0.f;
+  // learned line shape
+  const marfa_surrogate* surr = nullptr;
+  MlpDev mlp{};
+  float mlp_xmax = 0.f, mlp_inv_c = 0.f;
 };
+
+// evaluation view of a trained surrogate (defined with the surrogate object)
+bool marfa_surrogate_view(const marfa_surrogate* s, MlpDev* W, double* x_max, int32_t* chi, double* cutoff,
+                          int* device);
 
 static int64_t fdiv(int64_t a, int64_t b) {
   int64_t q = a / b;
@@ -697,6 +710,10 @@ static void enqueue(marfa_plan* p, int first, int count, void* out, int64_t stri
   a.stride = stride;
   a.stats = p->d.stats;
   a.max_item = tl.max_item;
+  a.surr = (p->surr && !count_mode) ? 1 : 0;
+  a.mlp_xmax = p->mlp_xmax;
+  a.mlp_inv_c = p->mlp_inv_c;
+  a.mlp = p->mlp;
   int64_t items = a.n_tiles * count;
   int grid = (int)std::min<int64_t>(std::max<int64_t>(1, items), (int64_t)(grid_cap > 0 ? grid_cap : p->grid));
   if (stages & 2) {
@@ -733,8 +750,15 @@ static marfa_status check_out(marfa_plan* p, void* out, int64_t stride) {
   return MARFA_OK;
 }
 
+static marfa_status check_eval(const marfa_plan* p) {
+  if (p->req.eval == MARFA_EVAL_SURROGATE && !p->surr)
+    return fail(MARFA_E_UNSUPPORTED, "surrogate evaluation requested but no trained surrogate is set");
+  return MARFA_OK;
+}
+
 extern "C" marfa_status marfa_execute(marfa_plan* p, void* out, int64_t stride, void* stream) {
   if (!p) return fail(MARFA_E_INVALID, "null plan");
+  if (check_eval(p) != MARFA_OK) return MARFA_E_UNSUPPORTED;
   marfa_status st = check_out(p, out, stride);
   if (st != MARFA_OK) return st;
   HIP_TRY(hipSetDevice(p->device));
@@ -750,6 +774,7 @@ extern "C" marfa_status marfa_execute(marfa_plan* p, void* out, int64_t stride, 
 
 extern "C" marfa_status marfa_execute_timed(marfa_plan* p, void* out, int64_t stride, void* stream, marfa_timing* t) {
   if (!p || !t) return fail(MARFA_E_INVALID, "null argument");
+  if (check_eval(p) != MARFA_OK) return MARFA_E_UNSUPPORTED;
   marfa_status st = check_out(p, out, stride);
   if (st != MARFA_OK) return st;
   HIP_TRY(hipSetDevice(p->device));
@@ -779,6 +804,7 @@ extern "C" marfa_status marfa_execute_layers(marfa_plan* p, int32_t first, int32
                                              void* stream) {
   if (!p) return fail(MARFA_E_INVALID, "null plan");
   if (first < 0 || count < 1 || first + count > p->n_layers) return fail(MARFA_E_INVALID, "layer range");
+  if (check_eval(p) != MARFA_OK) return MARFA_E_UNSUPPORTED;
   marfa_status st = check_out(p, out, stride);
   if (st != MARFA_OK) return st;
   HIP_TRY(hipSetDevice(p->device));
@@ -925,6 +951,36 @@ extern "C" marfa_status marfa_plan_tune(marfa_plan* p, void* out, int64_t stride
   HIP_TRY(hipStreamSynchronize(s));
   p->tuned = 1;
   p->tune_ms = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return MARFA_OK;
+}
+
+extern "C" marfa_status marfa_plan_set_surrogate(marfa_plan* p, const marfa_surrogate* s) {
+  if (!p) return fail(MARFA_E_INVALID, "null plan");
+  if (!s) {
+    p->surr = nullptr;
+    drop_graphs(p);
+    return MARFA_OK;
+  }
+  MlpDev W;
+  double x_max = 0.0, cutoff = 0.0;
+  int32_t chi = 0;
+  int dev = -1;
+  if (!marfa_surrogate_view(s, &W, &x_max, &chi, &cutoff, &dev))
+    return fail(MARFA_E_UNSUPPORTED, "the surrogate is not trained");
+  if (dev != p->device) return fail(MARFA_E_INVALID, "surrogate on device %d, plan on %d", dev, p->device);
+  if (p->req.fp64 || p->req.shape != MARFA_SHAPE_VOIGT)
+    return fail(MARFA_E_INVALID, "the surrogate serves single-precision Voigt plans");
+  if (chi != p->req.chi || cutoff != p->req.cutoff)
+    return fail(MARFA_E_INVALID, "surrogate trained for chi %d, cut-off %g; plan has chi %d, cut-off %g", chi, cutoff,
+                p->req.chi, p->req.cutoff);
+  for (const IntervalSet& iv : p->ivs)
+    if (iv.n_jump > 0 && !iv.lc_ok)
+      return fail(MARFA_E_UNSUPPORTED, "cut-off too small for the line-major band pass the surrogate needs");
+  p->surr = s;
+  p->mlp = W;
+  p->mlp_xmax = (float)x_max;
+  p->mlp_inv_c = (float)(1.0 / cutoff);
+  drop_graphs(p);
   return MARFA_OK;
 }
 

@@ -62,6 +62,24 @@ class Tiles(C.Structure):
                 ("wave_nodes", C.c_int32 * 11), ("tune_ms", C.c_float)]
 
 
+class SampleCfg(C.Structure):
+    _fields_ = [("nu_lo", C.c_double), ("nu_hi", C.c_double), ("T_lo", C.c_double), ("T_hi", C.c_double),
+                ("molar_mass_g", C.c_double)]
+
+
+class TrainCfg(C.Structure):
+    _fields_ = [("n_train", C.c_int64), ("n_val", C.c_int64), ("epochs", C.c_int32), ("batch", C.c_int32),
+                ("lr_max", C.c_float), ("lr_min", C.c_float), ("seed", C.c_uint64)]
+
+
+class TrainReport(C.Structure):
+    _fields_ = [("train_loss", C.c_float), ("val_loss", C.c_float), ("val_max_abs", C.c_float),
+                ("val_mean_abs", C.c_float), ("ms", C.c_float), ("steps", C.c_int64), ("x_max", C.c_double)]
+
+
+N_PARAMS = 12801
+MLP_WIDTHS = (3, 64, 64, 64, 64, 1)
+
 _lib = None
 
 
@@ -88,6 +106,21 @@ def lib():
         L.marfa_status_string.restype = C.c_char_p
         L.marfa_last_error.argtypes = [C.c_char_p, C.c_size_t]
         L.marfa_voigt_eval.argtypes = [i32, i64, vp, vp, vp, i32]
+        u64, f32p = C.c_uint64, C.POINTER(C.c_float)
+        L.marfa_surrogate_create.argtypes = [C.POINTER(vp), i32, C.c_double, u64, i32]
+        L.marfa_surrogate_set_params.argtypes = [vp, vp, i64]
+        L.marfa_surrogate_get_params.argtypes = [vp, vp, i64]
+        L.marfa_surrogate_forward.argtypes = [vp, vp, i64, vp, vp]
+        L.marfa_surrogate_loss_grad.argtypes = [vp, vp, vp, i64, f32p, vp]
+        L.marfa_surrogate_make_samples.argtypes = [vp, C.POINTER(SampleCfg), u64, i64, vp, vp, vp]
+        L.marfa_surrogate_train.argtypes = [vp, C.POINTER(SampleCfg), C.POINTER(TrainCfg), C.POINTER(TrainReport)]
+        L.marfa_surrogate_destroy.argtypes = [vp]
+        L.marfa_surrogate_destroy.restype = None
+        L.marfa_plan_set_surrogate.argtypes = [vp, vp]
+        for f in ("marfa_surrogate_create", "marfa_surrogate_set_params", "marfa_surrogate_get_params",
+                  "marfa_surrogate_forward", "marfa_surrogate_loss_grad", "marfa_surrogate_make_samples",
+                  "marfa_surrogate_train", "marfa_plan_set_surrogate"):
+            getattr(L, f).restype = C.c_int32
         for f in ("marfa_plan_create", "marfa_plan_points", "marfa_execute", "marfa_execute_layers",
                   "marfa_plan_count", "marfa_plan_tiles", "marfa_execute_timed", "marfa_plan_tune", "marfa_last_error",
                   "marfa_voigt_eval"):
@@ -211,9 +244,97 @@ class Plan:
                                      _stream_handle(stream, self.device)))
         return self.tiles()
 
+    def set_surrogate(self, surrogate):
+        """Evaluate line shapes with a trained Surrogate (None: plain shapes)."""
+        _check(lib().marfa_plan_set_surrogate(self._h, surrogate._h if surrogate is not None else None))
+        self._surrogate = surrogate
+
     def close(self):
         if getattr(self, "_h", None):
             lib().marfa_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _sample_cfg(nu_lo, nu_hi, T_lo, T_hi, molar_mass=44.0):
+    return SampleCfg(float(nu_lo), float(nu_hi), float(T_lo), float(T_hi), float(molar_mass))
+
+
+class Surrogate:
+    """The learned line shape (see marfa_surrogate_* in include/marfa.h).
+
+    Features and targets are device tensors: X [n, 3] float32, T [n] float32.
+    """
+
+    def __init__(self, chi="tonkov", cutoff=125.0, seed=1, device=0):
+        h = C.c_void_p()
+        _check(lib().marfa_surrogate_create(C.byref(h), CHIS.get(chi, chi), float(cutoff), int(seed), int(device)))
+        self._h = h
+        self.device = int(device)
+        self.chi = chi
+        self.cutoff = float(cutoff)
+        self.report = None
+
+    def get_params(self):
+        p = np.empty(N_PARAMS, np.float32)
+        _check(lib().marfa_surrogate_get_params(self._h, _ptr(p), N_PARAMS))
+        return p
+
+    def set_params(self, params):
+        p = np.ascontiguousarray(params, np.float32)
+        _check(lib().marfa_surrogate_set_params(self._h, _ptr(p), p.size))
+
+    def forward(self, X, stream=None):
+        import torch
+        X = X.contiguous()
+        if X.dtype != torch.float32 or X.dim() != 2 or X.shape[1] != 3:
+            raise ValueError("X must be float32 [n, 3]")
+        out = torch.empty(X.shape[0], dtype=torch.float32, device=X.device)
+        _check(lib().marfa_surrogate_forward(self._h, C.c_void_p(X.data_ptr()), X.shape[0],
+                                             C.c_void_p(out.data_ptr()), _stream_handle(stream, self.device)))
+        return out
+
+    def loss_grad(self, X, T):
+        import torch
+        torch.cuda.synchronize(self.device)
+        X, T = X.contiguous(), T.contiguous()
+        g = np.empty(N_PARAMS, np.float32)
+        loss = C.c_float()
+        _check(lib().marfa_surrogate_loss_grad(self._h, C.c_void_p(X.data_ptr()), C.c_void_p(T.data_ptr()),
+                                               X.shape[0], C.byref(loss), _ptr(g)))
+        return float(loss.value), g
+
+    def make_samples(self, n, seed, nu_lo=375.0, nu_hi=2625.0, T_lo=150.0, T_hi=740.0, molar_mass=44.0,
+                     stream=None):
+        import torch
+        X = torch.empty((n, 3), dtype=torch.float32, device=f"cuda:{self.device}")
+        T = torch.empty(n, dtype=torch.float32, device=f"cuda:{self.device}")
+        cfg = _sample_cfg(nu_lo, nu_hi, T_lo, T_hi, molar_mass)
+        _check(lib().marfa_surrogate_make_samples(self._h, C.byref(cfg), int(seed), int(n),
+                                                  C.c_void_p(X.data_ptr()), C.c_void_p(T.data_ptr()),
+                                                  _stream_handle(stream, self.device)))
+        return X, T
+
+    def train(self, n_train=10_000_000, n_val=1_000_000, epochs=20, batch=8192, lr_max=2e-3, lr_min=1e-6,
+              seed=4, nu_lo=375.0, nu_hi=2625.0, T_lo=150.0, T_hi=740.0, molar_mass=44.0):
+        import torch
+        torch.cuda.synchronize(self.device)
+        sc = _sample_cfg(nu_lo, nu_hi, T_lo, T_hi, molar_mass)
+        tc = TrainCfg(int(n_train), int(n_val), int(epochs), int(batch), float(lr_max), float(lr_min), int(seed))
+        r = TrainReport()
+        _check(lib().marfa_surrogate_train(self._h, C.byref(sc), C.byref(tc), C.byref(r)))
+        self.report = dict(train_loss=r.train_loss, val_loss=r.val_loss, val_max_abs=r.val_max_abs,
+                           val_mean_abs=r.val_mean_abs, ms=r.ms, steps=r.steps, x_max=r.x_max)
+        return self.report
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().marfa_surrogate_destroy(self._h)
             self._h = None
 
     def __del__(self):

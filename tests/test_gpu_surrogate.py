@@ -1,0 +1,133 @@
+"""The learned line shape on the GPU against the FP64 oracle.
+
+* forward pass (BF16 weights, split-BF16 activations, MFMA) vs the oracle's
+  FP64 network evaluated with the same BF16-rounded weights;
+* loss and gradient of the device backward pass vs the oracle's FP64
+  backward pass at the same weights;
+* training samples: the device targets vs the oracle's Voigt function;
+* training lowers the validation error.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+WIDTHS = [3, 64, 64, 64, 64, 1]
+
+
+def M():
+    from paper_2411_03418_amd import marfa
+    return marfa
+
+
+def bf16_round(a):
+    """Round float32 values to the nearest BF16 (ties to even), as float64."""
+    u = np.ascontiguousarray(a, np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
+    return (u.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
+def eval_params(p):
+    """The parameters the device evaluates: weights rounded to BF16, biases FP32."""
+    q = np.asarray(p, np.float64).copy()
+    off = 0
+    for i in range(len(WIDTHS) - 1):
+        nw = WIDTHS[i] * WIDTHS[i + 1]
+        q[off:off + nw] = bf16_round(p[off:off + nw])
+        off += nw + WIDTHS[i + 1]
+    return q
+
+
+def random_params(seed, scale=1.0):
+    rng = np.random.default_rng(seed)
+    parts = []
+    for i in range(len(WIDTHS) - 1):
+        fan = WIDTHS[i] + WIDTHS[i + 1]
+        parts.append(rng.uniform(-1, 1, WIDTHS[i] * WIDTHS[i + 1]) * np.sqrt(6.0 / fan) * scale)
+        parts.append(rng.uniform(-0.3, 0.3, WIDTHS[i + 1]))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def random_features(n, seed):
+    rng = np.random.default_rng(seed)
+    return np.stack([rng.uniform(0, 1.8, n), rng.uniform(-2, 1.5, n), rng.uniform(0, 1, n)], 1).astype(np.float32)
+
+
+def test_forward_matches_oracle_network():
+    S = M().Surrogate(chi="tonkov", cutoff=125.0, seed=3)
+    p = random_params(11, scale=1.5)
+    S.set_params(p)
+    X = random_features(1000, 12)   # not a multiple of 64: ragged last wavefront
+    got = S.forward(torch.tensor(X, device="cuda:0")).cpu().numpy().astype(np.float64)
+    ref = O.mlp_forward(WIDTHS, eval_params(p), X.astype(np.float64))[:, 0]
+    err = np.abs(got - ref) / np.maximum(1.0, np.abs(ref))
+    print(f"forward: max err {err.max():.2e}, output range {ref.min():.3f} .. {ref.max():.3f}")
+    assert err.max() < 5e-5
+    S.close()
+
+
+def test_params_round_trip():
+    S = M().Surrogate(seed=5)
+    p = random_params(13)
+    S.set_params(p)
+    assert np.array_equal(S.get_params(), p)
+    S.close()
+
+
+def test_gradient_matches_oracle():
+    S = M().Surrogate(seed=3)
+    p = random_params(21)
+    S.set_params(p)
+    n = 1000
+    X = random_features(n, 22)
+    rng = np.random.default_rng(23)
+    T = rng.normal(0, 0.5, n).astype(np.float32)
+    loss, g = S.loss_grad(torch.tensor(X, device="cuda:0"), torch.tensor(T, device="cuda:0"))
+    ref_loss, ref_g = O.mlp_loss_grad(WIDTHS, eval_params(p), X.astype(np.float64), T.astype(np.float64))
+    print(f"loss {loss:.6e} vs {ref_loss:.6e}")
+    assert abs(loss - ref_loss) <= 1e-4 * ref_loss
+    # per layer: weight and bias blocks, BF16 activations in the weight-gradient products
+    off = 0
+    for i in range(len(WIDTHS) - 1):
+        for nw in (WIDTHS[i] * WIDTHS[i + 1], WIDTHS[i + 1]):
+            a, b = g[off:off + nw].astype(np.float64), ref_g[off:off + nw]
+            rel = np.linalg.norm(a - b) / np.linalg.norm(b)
+            cos = a @ b / (np.linalg.norm(a) * np.linalg.norm(b))
+            print(f"block at {off} ({nw}): rel {rel:.2e} cos {cos:.8f}")
+            assert rel < 1e-2 and cos > 0.9999
+            off += nw
+    S.close()
+
+
+def test_training_samples_match_oracle_voigt():
+    S = M().Surrogate(chi="tonkov", cutoff=125.0, seed=3)
+    X, T = S.make_samples(20000, seed=99)
+    X = X.cpu().numpy().astype(np.float64)
+    T = T.cpu().numpy().astype(np.float64)
+    x = np.sinh(8.0 * X[:, 0])
+    y = 10.0 ** (2.0 * X[:, 1])
+    ad = 3.0 + 125.0 * X[:, 2]
+    chi = np.where(X[:, 2] > 0, np.array([O.chi(1, a) for a in ad]), 1.0)
+    kb = y / (np.sqrt(np.pi) * (x * x + y * y + 0.5)) + np.exp(-x * x) / (1 + np.sqrt(np.pi) * y) ** 2
+    ref = np.log(O.voigt_K(x, y) * chi) - np.log(kb)
+    # features are single precision: x carries ~1e-6 relative rounding
+    err = np.abs(T - ref)
+    print(f"targets: max |dt| {err.max():.2e}; y {y.min():.2e} .. {y.max():.2e}; x up to {x.max():.2e}")
+    assert err.max() < 3e-5
+    assert y.min() >= 0.99e-4 and y.max() <= 1.01e3
+    S.close()
+
+
+def test_training_reduces_validation_error():
+    S = M().Surrogate(chi="tonkov", cutoff=125.0, seed=3)
+    Xv, Tv = S.make_samples(50000, seed=7)
+    before = (S.forward(Xv) - Tv).abs().max().item()
+    rep = S.train(n_train=200_000, n_val=50_000, epochs=3, batch=4096, lr_max=2e-3, lr_min=1e-4, seed=8)
+    after = (S.forward(Xv) - Tv).abs().max().item()
+    print(f"train report {rep}; max |dt| before {before:.3f}, after {after:.3f}")
+    assert rep["steps"] == 3 * (200_000 // 4096)
+    assert after < 0.5 * before
+    S.close()
