@@ -191,7 +191,8 @@ void marfa_plan_destroy(marfa_plan* plan);
  * line with Voigt parameters x = sqrt(ln2) d / alpha_D, y = sqrt(ln2)
  * gamma_L / alpha_D (Eq.(7)-(8)) it predicts t = log(K chi) - log(Kb), the
  * residual of K(x, y) chi(|d|) (Eq.(10)) against the analytic base
- *   Kb = y / (sqrt(pi) (x^2 + y^2 + 1/2)) + exp(-x^2) / (1 + sqrt(pi) y)^2,
+ *   Kb = y (1 + (3x^2 - y^2) / (2 rho^2 + 1)) / (sqrt(pi) (rho + exp(-rho) / 2))
+ *        + exp(-x^2) / (1 + sqrt(pi) y)^2,   rho = x^2 + y^2,
  * from the inputs f = (asinh|x| / 8, log10(y) / 2, max(|d| - 3, 0) / c)
  * (|d|, c in cm^-1).  A network serves one (chi, cut-off) pair.  Parameters
  * are 12801 FP32 values packed as W0[64][3], b0[64], W1[64][64], b1[64],
@@ -209,14 +210,19 @@ typedef struct {
 } marfa_sample_cfg;
 
 /* Training run: n_train samples drawn once (n_val more for validation),
- * `epochs` passes in mini-batches of `batch` (a multiple of 32), Adam with
- * a cosine learning-rate schedule from lr_max to lr_min after a 2 % warm-up,
- * samples from a counter-based generator seeded by `seed`. */
+ * `epochs` passes in mini-batches of `batch` (a multiple of 32), Adam (state
+ * reset at the start of the run) with a cosine learning-rate schedule from
+ * lr_max to lr_min after a 2 % warm-up, samples from a counter-based
+ * generator seeded by `seed`.  loss_power 2 minimises the mean squared error
+ * of t, 4 the mean fourth power (a fine-tuning stage that weights the
+ * largest errors).  A run continues from the current parameters. */
 typedef struct {
   int64_t n_train, n_val;
   int32_t epochs, batch;
   float lr_max, lr_min;
   uint64_t seed;
+  int32_t loss_power;
+  int32_t reserved;
 } marfa_train_cfg;
 
 /* Outcome: final mini-batch loss, validation mean-squared and mean/max

@@ -1024,9 +1024,31 @@ __device__ void band_lines(const Geometry& G, const LevelArgs& a, int l, int lay
 // item into region tiles, then into band groups of 64 nodes; node sums meet in
 // LDS and are written once.
 template <typename R, bool COUNT, bool SURR>
-__global__ void __launch_bounds__(256) k_level(Geometry G, LevelArgs a) {
+__global__ void __launch_bounds__(256) k_level(Geometry G, LevelArgs a_in) {
   extern __shared__ char smem_raw[];
   R* lds_acc = reinterpret_cast<R*>(smem_raw);
+  LevelArgs a = a_in;
+  if constexpr (SURR) {
+    // the learned line shape's weights, staged once per workgroup
+    __shared__ float4 s_w0b[kMlpHid];
+    __shared__ uint4 s_wp[kMlpHidLayers * 8 * 64];
+    __shared__ float s_bh[kMlpHidLayers * kMlpHid];
+    __shared__ float s_w4[kMlpHid];
+    __shared__ float s_b4[1];
+    for (int i = threadIdx.x; i < kMlpHid; i += 256) {
+      s_w0b[i] = a_in.mlp.w0b[i];
+      s_w4[i] = a_in.mlp.w4[i];
+    }
+    for (int i = threadIdx.x; i < kMlpHidLayers * 8 * 64; i += 256) s_wp[i] = a_in.mlp.wp[i];
+    for (int i = threadIdx.x; i < kMlpHidLayers * kMlpHid; i += 256) s_bh[i] = a_in.mlp.bh[i];
+    if (threadIdx.x == 0) s_b4[0] = a_in.mlp.b4[0];
+    __syncthreads();
+    a.mlp.w0b = s_w0b;
+    a.mlp.wp = s_wp;
+    a.mlp.bh = s_bh;
+    a.mlp.w4 = s_w4;
+    a.mlp.b4 = s_b4;
+  }
   __shared__ int64_t s_item;
   const int wv = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
@@ -1176,7 +1198,8 @@ __device__ __forceinline__ double uniform01(uint64_t seed, uint64_t ctr) {
 // Sample i: a line centre nu0 and temperature T uniform over the configured
 // ranges (alpha_D from Section 2.2's Doppler width), y log-uniform, and the
 // distance |d| from a mixture -- log-uniform over [1e-6, c], uniform over
-// [0, c], and uniform over the Doppler core (x in [0, 8]).  Inputs are the
+// [0, c], uniform over the Doppler core (x in [0, 8]), and the transition
+// from core to wing (x in [0, 4] with y in [0.01, 10]).  Inputs are the
 // network features; the target is log(K chi) - log(Kb) with K from the
 // double-precision device line shape and chi from Eq.(10).
 __global__ void k_mlp_samples(MlpSampleCfg c, uint64_t seed, int64_t n, float* __restrict__ X,
@@ -1187,18 +1210,24 @@ __global__ void k_mlp_samples(MlpSampleCfg c, uint64_t seed, int64_t n, float* _
   const double nu0 = c.nu_lo + (c.nu_hi - c.nu_lo) * uniform01(seed, b + 0);
   const double Tk = c.T_lo + (c.T_hi - c.T_lo) * uniform01(seed, b + 1);
   const double aD = nu0 / kCLight * sqrt(2.0 * kLn2d * kBoltzmann * kNA * Tk / (c.molar_mass * 1e-3));
-  const double y = exp(log(c.y_lo) + (log(c.y_hi) - log(c.y_lo)) * uniform01(seed, b + 2));
+  double y = exp(log(c.y_lo) + (log(c.y_hi) - log(c.y_lo)) * uniform01(seed, b + 2));
   const double u = uniform01(seed, b + 3), v = uniform01(seed, b + 4);
   const double sq = sqrt(kLn2d);
   double ad;
-  if (u < 0.35) ad = exp(log(1e-6) + (log(c.cutoff) - log(1e-6)) * v);
-  else if (u < 0.65) ad = c.cutoff * v;
-  else ad = fmin(c.cutoff, 8.0 * aD / sq * v);
+  if (u < 0.3) ad = exp(log(1e-6) + (log(c.cutoff) - log(1e-6)) * v);
+  else if (u < 0.55) ad = c.cutoff * v;
+  else if (u < 0.8) ad = fmin(c.cutoff, 8.0 * aD / sq * v);
+  else {
+    // where the Doppler core meets the Lorentz wing: x < 4, 0.01 < y < 10
+    ad = fmin(c.cutoff, 4.0 * aD / sq * v);
+    y = exp(log(fmax(c.y_lo, 1e-2)) + (log(fmin(c.y_hi, 10.0)) - log(fmax(c.y_lo, 1e-2))) * uniform01(seed, b + 5));
+  }
   const double x = sq * ad / aD;
   const double K = device_K<double>(x, y);
   const double chi = c.chi == MARFA_CHI_TONKOV ? tonkov<double>(ad) : 1.0;
-  const double x2 = x * x, up = 1.0 + 1.7724538509055160 * y;
-  const double kb = y / (1.7724538509055160 * (x2 + y * y + 0.5)) + exp(-x2) / (up * up);
+  const double x2 = x * x, r = x2 + y * y, up = 1.0 + 1.7724538509055160 * y;
+  const double kb = y * (1.0 + (3.0 * x2 - y * y) / (2.0 * r * r + 1.0)) / (1.7724538509055160 * (r + 0.5 * exp(-r))) +
+                    exp(-x2) / (up * up);
   X[3 * i + 0] = (float)(asinh(x) * 0.125);
   X[3 * i + 1] = (float)(log10(y) * 0.5);
   X[3 * i + 2] = (float)(fmax(ad - 3.0, 0.0) / c.cutoff);

@@ -5,9 +5,12 @@
 // x = sqrt(ln2) d / alpha_D and y = sqrt(ln2) gamma_L / alpha_D, the line
 // shape times the wing factor chi (Eq.(10)) is written
 //     F(d) chi(|d|) = sqrt(ln2 / pi) / alpha_D * Kb(x, y) * exp(t)
-// with the analytic base
-//     Kb(x, y) = y / (sqrt(pi) (x^2 + y^2 + 1/2)) + exp(-x^2) / (1 + sqrt(pi) y)^2,
-// which has the Lorentz wing and the Doppler core of K, and the network
+// with the analytic base (rho = x^2 + y^2)
+//     Kb(x, y) = y (1 + (3x^2 - y^2) / (2 rho^2 + 1)) / (sqrt(pi) (rho + exp(-rho) / 2))
+//              + exp(-x^2) / (1 + sqrt(pi) y)^2,
+// whose first part is the two leading terms of the large-|z| expansion of
+// Re w(z) = K (kept finite at z = 0) and whose second is the Doppler core;
+// the network
 // predicts the bounded residual t = log(K chi) - log(Kb) from the inputs
 //     f1 = asinh(|x|) / 8,  f2 = log10(y) / 2,  f3 = max(|d| - 3, 0) / c
 // (|d| and the cut-off c in cm^-1; f3 is |d|/c measured from the first
@@ -139,9 +142,12 @@ __device__ __forceinline__ void mlp_features(float x, float y, float ad_cm, floa
 // the analytic base Kb(x, y)
 __device__ __forceinline__ float mlp_base(float x, float y) {
   const float kSqrtPi = 1.7724538509055160f;
-  const float x2 = x * x;
+  const float x2 = x * x, y2 = y * y;
+  const float r = x2 + y2;
   const float u = 1.0f + kSqrtPi * y;
-  return y * __builtin_amdgcn_rcpf(kSqrtPi * (x2 + y * y + 0.5f)) + __expf(-x2) * __builtin_amdgcn_rcpf(u * u);
+  const float wing = y * (1.0f + (3.0f * x2 - y2) * __builtin_amdgcn_rcpf(2.0f * r * r + 1.0f)) *
+                     __builtin_amdgcn_rcpf(kSqrtPi * (r + 0.5f * __expf(-r)));
+  return wing + __expf(-x2) * __builtin_amdgcn_rcpf(u * u);
 }
 
 // Wave-collective forward pass: every lane brings one sample (f1, f2, f3)

@@ -97,14 +97,15 @@ __global__ void __launch_bounds__(256) k_mlp_forward(MlpDev W, const float* __re
 // ------------------------------------------------------------------
 // forward + backward of 32 samples per workgroup (one wavefront)
 // ------------------------------------------------------------------
-// Partial gradient of L = gscale/2 * sum_b (y_b - t_b)^2 over this
-// workgroup's samples, in the packed parameter order, followed by the sum
-// of squared errors.  gscale = 2 / batch gives the gradient of the mean.
+// Partial gradient of L = gscale/2 * sum_b (y_b - t_b)^2 (or, with pow4,
+// of 1e6 gscale/2 * sum_b (y_b - t_b)^4) over this workgroup's samples, in
+// the packed parameter order, followed by the sum of squared errors.
+// gscale = 2 / batch gives the gradient of the mean.
 constexpr int kGradSamples = 32;
 
 __global__ void __launch_bounds__(64) k_mlp_grad(MlpDev W, const float* __restrict__ X, const float* __restrict__ Tg,
                                                  int64_t n_all, int64_t first, int64_t count, int64_t perm_a,
-                                                 int64_t perm_b, float gscale, float* __restrict__ partial) {
+                                                 int64_t perm_b, float gscale, int pow4, float* __restrict__ partial) {
   // pre-activations z of layers 0..3 for 2 tiles, later their gradients;
   // index [layer][tile][row tile * 4 + i][lane]
   __shared__ float zs[4][2][16][64];
@@ -164,7 +165,9 @@ __global__ void __launch_bounds__(64) k_mlp_grad(MlpDev W, const float* __restri
     const bool vs = __shfl((int)valid, src) != 0;
     if (q == 0) {
       const float e = vs ? y - ts : 0.f;
-      douts[src] = gscale * e;
+      // mean squared error, or a mean fourth power (scaled by 1e6) that
+      // weights the largest errors
+      douts[src] = pow4 ? gscale * 2e6f * e * e * e : gscale * e;
       errs[src] = e * e;
     }
   }
@@ -391,11 +394,12 @@ uint64_t host_mix(uint64_t z) {
 // gradient over n samples at [first, first + n) of the permutation
 // i -> (a i + b) mod n_all of a sample set of n_all entries
 marfa_status run_grad(marfa_surrogate* s, const float* X, const float* T, int64_t n_all, int64_t first, int64_t n,
-                      int64_t pa, int64_t pb, float gscale, const AdamArgs& ad) {
+                      int64_t pa, int64_t pb, float gscale, const AdamArgs& ad, int pow4 = 0) {
   const int64_t groups = (n + kGradSamples - 1) / kGradSamples;
   marfa_status st = ensure_partial(s, groups);
   if (st != MARFA_OK) return st;
-  k_mlp_grad<<<(unsigned)groups, 64, 0, s->stream>>>(dev_view(s), X, T, n_all, first, n, pa, pb, gscale, s->partial);
+  k_mlp_grad<<<(unsigned)groups, 64, 0, s->stream>>>(dev_view(s), X, T, n_all, first, n, pa, pb, gscale, pow4,
+                                                     s->partial);
   k_mlp_reduce_adam<<<(kMlpParams + 1 + 255) / 256, 256, 0, s->stream>>>(s->partial, (int)groups, s->grad, s->master,
                                                                          s->m, s->v, ad, s->eb);
   SHIP(hipGetLastError());
@@ -536,7 +540,8 @@ extern "C" marfa_status marfa_surrogate_train(marfa_surrogate* s, const marfa_sa
                                               const marfa_train_cfg* cfg, marfa_train_report* rep) {
   if (!s || !c || !cfg || !rep) return sfail(MARFA_E_INVALID, "null argument");
   if (cfg->n_train < kGradSamples || cfg->n_val < 1 || cfg->epochs < 1 || cfg->batch < kGradSamples ||
-      cfg->batch % kGradSamples != 0 || !(cfg->lr_max > 0.f) || !(cfg->lr_min >= 0.f))
+      cfg->batch % kGradSamples != 0 || !(cfg->lr_max > 0.f) || !(cfg->lr_min >= 0.f) ||
+      (cfg->loss_power != 2 && cfg->loss_power != 4))
     return sfail(MARFA_E_INVALID, "training configuration");
   SHIP(hipSetDevice(s->device));
   const auto t0 = std::chrono::steady_clock::now();
@@ -556,6 +561,12 @@ extern "C" marfa_status marfa_surrogate_train(marfa_surrogate* s, const marfa_sa
   st = marfa_surrogate_make_samples(s, c, cfg->seed, N, X, T, s->stream);
   if (st == MARFA_OK) st = marfa_surrogate_make_samples(s, c, cfg->seed ^ 0x5bd1e995ull, V, Xv, Tv, s->stream);
   if (st != MARFA_OK) { cleanup(); return st; }
+  // a fresh optimizer state for every run
+  if (hipMemsetAsync(s->m, 0, kMlpParams * sizeof(float), s->stream) != hipSuccess ||
+      hipMemsetAsync(s->v, 0, kMlpParams * sizeof(float), s->stream) != hipSuccess) {
+    cleanup();
+    return sfail(MARFA_E_DEVICE, "optimizer reset");
+  }
   const int64_t steps_per_epoch = N / cfg->batch;
   const int64_t total = steps_per_epoch * cfg->epochs;
   const int64_t warm = std::max<int64_t>(1, total / 50);
@@ -577,7 +588,8 @@ extern "C" marfa_status marfa_surrogate_train(marfa_surrogate* s, const marfa_sa
       pb1 *= b1;
       pb2 *= b2;
       AdamArgs ad{lr, b1, b2, 1e-8f, (float)(1.0 - pb1), (float)(1.0 - pb2), 1};
-      st = run_grad(s, X, T, N, b * cfg->batch, cfg->batch, pa, pbo, 2.0f / (float)cfg->batch, ad);
+      st = run_grad(s, X, T, N, b * cfg->batch, cfg->batch, pa, pbo, 2.0f / (float)cfg->batch, ad,
+                    cfg->loss_power == 4 ? 1 : 0);
     }
   }
   if (st == MARFA_OK) {

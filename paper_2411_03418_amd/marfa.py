@@ -69,7 +69,8 @@ class SampleCfg(C.Structure):
 
 class TrainCfg(C.Structure):
     _fields_ = [("n_train", C.c_int64), ("n_val", C.c_int64), ("epochs", C.c_int32), ("batch", C.c_int32),
-                ("lr_max", C.c_float), ("lr_min", C.c_float), ("seed", C.c_uint64)]
+                ("lr_max", C.c_float), ("lr_min", C.c_float), ("seed", C.c_uint64), ("loss_power", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class TrainReport(C.Structure):
@@ -321,11 +322,12 @@ class Surrogate:
         return X, T
 
     def train(self, n_train=10_000_000, n_val=1_000_000, epochs=20, batch=8192, lr_max=2e-3, lr_min=1e-6,
-              seed=4, nu_lo=375.0, nu_hi=2625.0, T_lo=150.0, T_hi=740.0, molar_mass=44.0):
+              seed=4, nu_lo=375.0, nu_hi=2625.0, T_lo=150.0, T_hi=740.0, molar_mass=44.0, loss_power=2):
         import torch
         torch.cuda.synchronize(self.device)
         sc = _sample_cfg(nu_lo, nu_hi, T_lo, T_hi, molar_mass)
-        tc = TrainCfg(int(n_train), int(n_val), int(epochs), int(batch), float(lr_max), float(lr_min), int(seed))
+        tc = TrainCfg(int(n_train), int(n_val), int(epochs), int(batch), float(lr_max), float(lr_min), int(seed),
+                      int(loss_power), 0)
         r = TrainReport()
         _check(lib().marfa_surrogate_train(self._h, C.byref(sc), C.byref(tc), C.byref(r)))
         self.report = dict(train_loss=r.train_loss, val_loss=r.val_loss, val_max_abs=r.val_max_abs,

@@ -111,7 +111,9 @@ def test_training_samples_match_oracle_voigt():
     y = 10.0 ** (2.0 * X[:, 1])
     ad = 3.0 + 125.0 * X[:, 2]
     chi = np.where(X[:, 2] > 0, np.array([O.chi(1, a) for a in ad]), 1.0)
-    kb = y / (np.sqrt(np.pi) * (x * x + y * y + 0.5)) + np.exp(-x * x) / (1 + np.sqrt(np.pi) * y) ** 2
+    r = x * x + y * y
+    kb = (y * (1 + (3 * x * x - y * y) / (2 * r * r + 1)) / (np.sqrt(np.pi) * (r + 0.5 * np.exp(-r)))
+          + np.exp(-x * x) / (1 + np.sqrt(np.pi) * y) ** 2)
     ref = np.log(O.voigt_K(x, y) * chi) - np.log(kb)
     # features are single precision: x carries ~1e-6 relative rounding
     err = np.abs(T - ref)
