@@ -1,9 +1,18 @@
 #!/usr/bin/env python3
-"""Benchmark: spectral points per second on one MI355X for an eleven-grid PT table.
+"""Benchmark: spectral points per second on one MI355X for eleven-grid PT tables.
 
 A step is one pass of the whole hot path (line preparation, level
 accumulation, cascade) over every layer of the workload, replayed from the
-plan's HIP graph with all inputs resident in HBM.  Prints one JSON line.
+plan's HIP graph with all inputs resident in HBM.  Prints one JSON line:
+
+* the plain path on the large table (2M lines, 100 layers, 0-10000 cm^-1),
+  tiles autotuned before timing;
+* "surrogate": the learned line shape on the 100-layer 200k-line table
+  (trained on the device first), its throughput, its speed relative to the
+  plain path on the same table, and its deviation from the plain path;
+* "roofline": counted algorithmic FP32 work of the level kernel per launch
+  over its event-timed duration, against the FP32 vector peak;
+* "cpu_baseline": the FP64 oracle's eleven-grid program on a bounded sample.
 """
 from __future__ import annotations
 
@@ -19,25 +28,20 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP32_VALU_TFLOPS = 157.3   # MI355X published FP32 vector peak
-PEAK_HBM_GBS = 8000.0
 
-# Counted flops per evaluated term (static count of the kernel source; FMA = 2,
-# add/mul/compare-free = 1, rcp/exp = 1).  Double-precision flops of the
-# rational core count twice (the FP64 vector peak is half the FP32 one).
-FLOP_PAIR = 3            # d = (X - k0) - frac, |d| band tests excluded, acc += v
-FLOP_WING = 20           # dcm, d^2, x, y, z^2, Q = 1/(d^2+g^2), e, f, chi, S'*f*chi
-FLOP_WING_TERM = 7       # one more term of the asymptotic series
-FLOP_CORE = 2 * 250      # Weideman N = 32 in FP64 (31 complex Horner steps + setup)
-FLOP_BAND_NODE = 2       # stencil weight times the coarse value
-FLOP_CASCADE_NODE = 5    # 3-point interpolation per node
+# Algorithmic flops per unit of work, counted from the kernel source
+# (FMA = 2, add / mul = 1, rcp / exp2 = 1; compares, selects and integer
+# address arithmetic are not counted):
+FLOP_WING = 18        # d, d^2+g^2, 1/., e, U, 1+eU, A Q sum, chi = exp2(c0+c1 d), acc += g chi
+FLOP_TERM = 6         # one more term of the asymptotic wing series
+FLOP_CORE = 2 * 260   # rational core in FP64 (31 complex Horner steps + setup); FP64 counts double
+FLOP_BAND = 6         # three stencil weights times coarse values, per band pair
 
 
 def counted_flops(st):
-    pairs = sum(st["pairs_level"])
-    evals = st["pairs_wing"] + st["pairs_core"]
-    f = (FLOP_PAIR * pairs + FLOP_WING * st["pairs_wing"] + FLOP_WING_TERM * st["wing_terms"]
-         + FLOP_CORE * st["pairs_core"] + FLOP_BAND_NODE * 3 * st["pairs_band"])
-    return float(f), evals
+    """Counted FP32-equivalent flops of one level-kernel launch over all layers."""
+    return float(FLOP_WING * st["pairs_wing"] + FLOP_TERM * st["wing_terms"] + FLOP_CORE * st["pairs_core"]
+                 + FLOP_BAND * st["pairs_band"])
 
 
 def cpu_baseline(lines, layers, req, budget_s):
@@ -62,6 +66,60 @@ def cpu_baseline(lines, layers, req, budget_s):
                        f"{width:g} cm^-1 at {lo:g} cm^-1 = {pts} points, {dt:.2f} s")
 
 
+def timed_steps(plan, out, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        plan.execute(out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.execute(out=out)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps * 1e3
+
+
+def rel_dev(a, b):
+    """max over layers and nodes with a >= 1e-8 of the layer max of |b - a| / a."""
+    worst = 0.0
+    for i in range(a.shape[0]):
+        x, y = a[i].double(), b[i].double()
+        m = x >= 1e-8 * x.max()
+        worst = max(worst, float(((y[m] - x[m]).abs() / x[m]).max()))
+    return worst
+
+
+def surrogate_leg(args):
+    import torch
+    from paper_2411_03418_amd import marfa, synth
+    lines, layers, rq = synth.workload("pt100_200k")
+    req = dict(nu_begin=rq["nu_begin"], nu_end=rq["nu_end"], cutoff=rq["cutoff"], chi="tonkov", prune=rq["prune"])
+    S = marfa.Surrogate(chi="tonkov", cutoff=rq["cutoff"], seed=1)
+    rep = S.fit(nu_lo=float(lines.nu0.min()), nu_hi=float(lines.nu0.max()), T_lo=float(layers[:, 1].min()),
+                T_hi=float(layers[:, 1].max()))
+    print(f"[bench] surrogate trained: {rep}", file=sys.stderr, flush=True)
+    plan = marfa.Plan(lines, layers, device=0, **req)
+    out = torch.empty((plan.n_layers, plan.points), dtype=torch.float32, device="cuda:0")
+    plan.tune(out=out)
+    ms_plain = timed_steps(plan, out, 3, 1)
+    plain = out.clone()
+    plan.set_surrogate(S)
+    ms_surr = timed_steps(plan, out, args.surrogate_steps, 1)
+    dev = rel_dev(plain, out)
+    _, t = plan.execute_timed(out=out)
+    points = plan.points * plan.n_layers
+    print(f"[bench] surrogate {ms_surr:.1f} ms/step vs plain {ms_plain:.1f}; max dev from plain {dev:.2e}",
+          file=sys.stderr, flush=True)
+    plan.close()
+    S.close()
+    return dict(workload="pt100_200k", value=points / (ms_surr * 1e-3), unit="points/s", ms_per_step=ms_surr,
+                steps=args.surrogate_steps, level_ms=t["level_ms"], plain_ms_per_step=ms_plain,
+                speed_vs_plain=ms_plain / ms_surr, max_rel_dev_from_plain=dev,
+                train=dict(ms=rep["ms"], steps=rep["steps"], val_max_abs_t=rep["val_max_abs"],
+                           val_mean_abs_t=rep["val_mean_abs"], samples=10_000_000,
+                           recipe="300 epochs mean-squared + 100 epochs fourth-power, batch 16384"),
+                mfma="v_mfma_f32_16x16x32_bf16, BF16 weights, BF16 hi/lo activations, FP32 accumulate")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -70,8 +128,11 @@ def main():
     ap.add_argument("--workload", default="pt100_2m")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--check-nodes", type=int, default=256)
+    ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--surrogate-steps", type=int, default=2)
     ap.add_argument("--no-tune", action="store_true", help="keep the density-based tiles")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a device-to-device copy of MIB MiB (HBM counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (layers shard across GPUs "
@@ -80,8 +141,17 @@ def main():
 
     import torch
 
-    import oracle as O
     from paper_2411_03418_amd import marfa, synth
+
+    if args.calibrate_copy:
+        n = args.calibrate_copy * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": n * 4}))
+        return
 
     t0 = time.perf_counter()
     lines, layers, rq = synth.workload(args.workload)
@@ -94,21 +164,12 @@ def main():
     tiles = plan.tune(out=out) if not args.no_tune else plan.tiles()
     print(f"[bench] tiles {tiles}", file=sys.stderr, flush=True)
     st = plan.count()
-    flops, evals = counted_flops(st)
-    print(f"[bench] plan ready; pairs {sum(st['pairs_level']):.3e}, core {st['pairs_core']:.3e}, "
-          f"band {st['pairs_band']:.3e}", file=sys.stderr, flush=True)
-    for _ in range(args.warmup):
-        plan.execute(out=out)
-    torch.cuda.synchronize()
-    print("[bench] warmup done", file=sys.stderr, flush=True)
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        plan.execute(out=out)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    ms = dt / args.steps * 1e3
+    flops = counted_flops(st)
+    print(f"[bench] pairs {sum(st['pairs_level']):.3e}, core {st['pairs_core']:.3e}, band {st['pairs_band']:.3e}",
+          file=sys.stderr, flush=True)
+    ms = timed_steps(plan, out, args.steps, args.warmup)
     points = plan.points * plan.n_layers
-    # dominant kernel: level accumulation, timed by HIP events recorded in the graph
+    # dominant kernel: the level stage, timed by HIP events on the launch stream
     lv, tot, prep, cas = [], [], [], []
     for _ in range(args.steps):
         _, t = plan.execute_timed(out=out)
@@ -117,26 +178,12 @@ def main():
     achieved = flops / (level_ms * 1e-3) / 1e12
     print(f"[bench] {ms:.2f} ms/step; level {level_ms:.2f} ms, prep {np.mean(prep):.2f} ms, "
           f"cascade {np.mean(cas):.2f} ms", file=sys.stderr, flush=True)
-
-    # sampled parity against the definition (direct sum) on two layers
-    res = {}
-    if args.check_nodes > 0:
-        rng = np.random.default_rng(1)
-        m0 = int(round(req["nu_begin"] * 2048))
-        nodes = np.sort(rng.integers(m0, int(round(req["nu_end"] * 2048)) + 1, args.check_nodes))
-        worst = 0.0
-        o = dict(nu_begin=req["nu_begin"], nu_end=req["nu_end"], cutoff=req["cutoff"], chi=rq["chi"],
-                 prune=req["prune"])
-        for li in sorted({0, plan.n_layers - 1, plan.n_layers // 2}):
-            ref = O.direct(lines, layers[li], nodes, threads=min(os.cpu_count() or 1, 16), **o)
-            got = out[li, torch.as_tensor(nodes - m0, device="cuda:0")].double().cpu().numpy()
-            msk = ref >= 1e-8 * ref.max()
-            worst = max(worst, float(np.max(np.abs(got[msk] - ref[msk]) / ref[msk])))
-        res = dict(max_rel_err_vs_direct=worst, checked_nodes=int(args.check_nodes), checked_layers=3)
-        print(f"[bench] sampled parity {worst:.2e}", file=sys.stderr, flush=True)
+    plan.close()
+    del out
+    torch.cuda.empty_cache()
 
     line = {
-        "metric": "spectral points/s/GPU (PT table), plain path at 1e-4 rel err",
+        "metric": "spectral points/s/GPU (PT table), plain vs MLP-surrogate at 1e-4/1e-3 rel err",
         "value": points / (ms * 1e-3),
         "unit": "points/s",
         "n_gpus": 1,
@@ -148,10 +195,10 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": args.workload, "lines": lines.n, "layers": plan.n_layers,
-                   "points_per_layer": plan.points, "nu_begin": req["nu_begin"], "nu_end": req["nu_end"],
-                   "cutoff": req["cutoff"], "chi": chi, "prune_rel": req["prune"], "R": 48,
-                   "parallelism": "single GPU"},
+        "config": {"workload": args.workload, "lines": lines.n, "layers": len(layers),
+                   "points_per_layer": int(points // len(layers)), "nu_begin": req["nu_begin"],
+                   "nu_end": req["nu_end"], "cutoff": req["cutoff"], "chi": chi, "prune_rel": req["prune"], "R": 48,
+                   "path": "plain", "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_VALU_TFLOPS, "traffic": None,
                      "kernel": "k_level", "kernel_ms": level_ms, "counted_tflop_per_launch": flops / 1e12},
@@ -165,8 +212,8 @@ def main():
                   "wing_terms": int(st["wing_terms"])},
         "tiles": tiles,
     }
-    line.update(res)
-    plan.close()
+    if not args.no_surrogate:
+        line["surrogate"] = surrogate_leg(args)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(lines, layers, dict(req, chi=rq["chi"]), args.cpu_seconds)
     print(json.dumps(line))

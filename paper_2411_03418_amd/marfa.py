@@ -334,6 +334,21 @@ class Surrogate:
                            val_mean_abs=r.val_mean_abs, ms=r.ms, steps=r.steps, x_max=r.x_max)
         return self.report
 
+    def fit(self, nu_lo, nu_hi, T_lo, T_hi, molar_mass=44.0, n_train=10_000_000, n_val=1_000_000, epochs=300,
+            fine_epochs=100, batch=16384, lr=3e-3, seed=4):
+        """Two-stage training: mean squared error, then a fourth-power stage
+        at a tenth of the learning rate that weights the largest errors."""
+        rng = dict(nu_lo=nu_lo, nu_hi=nu_hi, T_lo=T_lo, T_hi=T_hi, molar_mass=molar_mass)
+        r1 = self.train(n_train=n_train, n_val=n_val, epochs=epochs, batch=batch, lr_max=lr, lr_min=lr * 1e-3,
+                        seed=seed, **rng)
+        if fine_epochs <= 0:
+            return r1
+        r2 = self.train(n_train=n_train, n_val=n_val, epochs=fine_epochs, batch=batch, lr_max=lr / 10,
+                        lr_min=lr * 1e-3, seed=seed, loss_power=4, **rng)
+        r2 = dict(r2, ms=r1["ms"] + r2["ms"], steps=r1["steps"] + r2["steps"])
+        self.report = r2
+        return r2
+
     def close(self):
         if getattr(self, "_h", None):
             lib().marfa_surrogate_destroy(self._h)

@@ -5,7 +5,10 @@
 * loss and gradient of the device backward pass vs the oracle's FP64
   backward pass at the same weights;
 * training samples: the device targets vs the oracle's Voigt function;
-* training lowers the validation error.
+* training lowers the validation error;
+* a PT table evaluated with the trained network stays within 1e-3 of the
+  oracle's direct sum, and the network cuts the error of its analytic base
+  alone (the method without the learned part) by more than tenfold.
 """
 import numpy as np
 import pytest
@@ -132,4 +135,46 @@ def test_training_reduces_validation_error():
     print(f"train report {rep}; max |dt| before {before:.3f}, after {after:.3f}")
     assert rep["steps"] == 3 * (200_000 // 4096)
     assert after < 0.5 * before
+    S.close()
+
+
+def _rel(got, ref):
+    m = ref >= 1e-8 * ref.max()
+    return float(np.max(np.abs(got[m] - ref[m]) / ref[m]))
+
+
+def test_surrogate_pt_table_vs_direct_and_vs_base_alone():
+    from paper_2411_03418_amd import synth
+    mm = M()
+    lines = synth.make_lines(3000, 930.0, 1090.0, 41, shift=True)
+    layers = synth.pt_table(7)
+    req = dict(nu_begin=1000.0, nu_end=1013.5, cutoff=60.0, chi="tonkov", prune=1e-6)
+    S = mm.Surrogate(chi="tonkov", cutoff=60.0, seed=1)
+    rep = S.fit(nu_lo=925.0, nu_hi=1095.0, T_lo=150.0, T_hi=740.0)
+    print(f"fit: {rep}")
+    plan = mm.Plan(lines, layers, device=0, **req)
+    plain = plan.execute().clone()
+    plan.set_surrogate(S)
+    surr = plan.execute().clone()
+    S.set_params(np.zeros(mm.N_PARAMS, np.float32))   # t = 0: the analytic base alone
+    plan.set_surrogate(S)
+    base = plan.execute().clone()
+    torch.cuda.synchronize()
+    plan.close()
+    rng = np.random.default_rng(5)
+    m0 = int(req["nu_begin"] * 2048)
+    nodes = np.unique(np.concatenate([rng.integers(m0, int(req["nu_end"] * 2048) + 1, 1500),
+                                      np.arange(m0 + 6000, m0 + 6400)]))
+    o = dict(nu_begin=req["nu_begin"], nu_end=req["nu_end"], cutoff=req["cutoff"], chi=1, prune=req["prune"])
+    e_s, e_b, e_p = [], [], []
+    for i in range(layers.shape[0]):
+        ref = O.direct(lines, layers[i], nodes, threads=16, **o)
+        e_s.append(_rel(surr[i, nodes - m0].double().cpu().numpy(), ref))
+        e_b.append(_rel(base[i, nodes - m0].double().cpu().numpy(), ref))
+        e_p.append(_rel(plain[i, nodes - m0].double().cpu().numpy(), ref))
+    print(f"vs direct: plain {max(e_p):.2e}, surrogate {max(e_s):.2e}, base alone {max(e_b):.2e}")
+    full = max(_rel(surr[i].double().cpu().numpy(), plain[i].double().cpu().numpy()) for i in range(layers.shape[0]))
+    print(f"surrogate vs plain, every node: {full:.2e}")
+    assert max(e_s) < 1e-3
+    assert max(e_b) > 10 * max(e_s)
     S.close()
