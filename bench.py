@@ -38,6 +38,28 @@ FLOP_CORE = 2 * 260   # rational core in FP64 (31 complex Horner steps + setup);
 FLOP_BAND = 6         # three stencil weights times coarse values, per band pair
 
 
+def profiled_traffic(workload):
+    """HBM bytes per k_level launch measured with rocprofv3 counters for this
+    workload (profiles/k_level_<workload>.md), or None when there is no such
+    profile or the kernel sources changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"k_level_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    for ln in open(path):
+        if ":" in ln and ln.split(":")[0] in ("traffic_bytes_per_launch", "kernel_source_sha256"):
+            k, v = ln.split(":", 1)
+            rec[k] = v.strip()
+    h = hashlib.sha256()
+    for src in ("marfa_kernels.hip", "marfa_internal.h", "marfa_mlp.h"):
+        with open(os.path.join(ROOT, "paper_2411_03418_amd", "csrc", src), "rb") as f:
+            h.update(f.read())
+    if rec.get("kernel_source_sha256") != h.hexdigest():
+        return None
+    return float(rec["traffic_bytes_per_launch"])
+
+
 def counted_flops(st):
     """Counted FP32-equivalent flops of one level-kernel launch over all layers."""
     return float(FLOP_WING * st["pairs_wing"] + FLOP_TERM * st["wing_terms"] + FLOP_CORE * st["pairs_core"]
@@ -57,7 +79,7 @@ def cpu_baseline(lines, layers, req, budget_s):
         t0 = time.perf_counter()
         out = O.grid(lines, L, threads=threads, nu_begin=lo, nu_end=lo + width, **o)
         dt = time.perf_counter() - t0
-        if dt > budget_s / 3 or width >= 64:
+        if dt > budget_s / 3 or width >= 4096:
             break
         width *= 2 if dt > 0.2 * budget_s / 3 else 4
     pts = out.size
@@ -131,6 +153,8 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--surrogate-steps", type=int, default=2)
     ap.add_argument("--no-tune", action="store_true", help="keep the density-based tiles")
+    ap.add_argument("--tiles", default=None, metavar="JSON",
+                    help="tile parameters from an earlier run's \"tiles\" (skips tuning)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -161,7 +185,12 @@ def main():
           file=sys.stderr, flush=True)
     plan = marfa.Plan(lines, layers, device=0, **req)
     out = torch.empty((plan.n_layers, plan.points), dtype=torch.float32, device="cuda:0")
-    tiles = plan.tune(out=out) if not args.no_tune else plan.tiles()
+    if args.tiles:
+        tiles = plan.set_tiles(json.loads(args.tiles))
+    elif not args.no_tune:
+        tiles = plan.tune(out=out)
+    else:
+        tiles = plan.tiles()
     print(f"[bench] tiles {tiles}", file=sys.stderr, flush=True)
     st = plan.count()
     flops = counted_flops(st)
@@ -200,7 +229,7 @@ def main():
                    "nu_end": req["nu_end"], "cutoff": req["cutoff"], "chi": chi, "prune_rel": req["prune"], "R": 48,
                    "path": "plain", "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_VALU_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_FP32_VALU_TFLOPS, "traffic": profiled_traffic(args.workload),
                      "kernel": "k_level", "kernel_ms": level_ms, "counted_tflop_per_launch": flops / 1e12},
         "stages_ms": {"prep": float(np.mean(prep)), "level": level_ms, "cascade": float(np.mean(cas)),
                       "graph_total": float(np.mean(tot))},

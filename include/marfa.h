@@ -157,6 +157,12 @@ typedef struct {
   float tune_ms;
 } marfa_tiles;
 marfa_status marfa_plan_tiles(const marfa_plan* plan, marfa_tiles* tiles);
+/* Use given tile parameters (e.g. from an earlier marfa_plan_tune of a plan
+ * of the same shape) instead of tuning: item_nodes a multiple of 64 in
+ * [64, 8192], blocks_per_cu in [1, 32], wave_nodes[l] a power of two in
+ * [1, 64]; tuned and tune_ms are ignored.  Graphs are rebuilt on the next
+ * execute.  Errors: MARFA_E_INVALID, MARFA_E_NOMEM. */
+marfa_status marfa_plan_set_tiles(marfa_plan* plan, const marfa_tiles* tiles);
 
 /* Autotuner: runs line preparation, then times the level kernel on the
  * device for candidate tile parameters with the plan's own lines and layers

@@ -850,6 +850,16 @@ extern "C" marfa_status marfa_plan_count(marfa_plan* p, marfa_stats* out) {
   return MARFA_OK;
 }
 
+static void drop_graphs(marfa_plan* p) {
+  if (p->exec) { (void)hipGraphExecDestroy(p->exec); p->exec = nullptr; }
+  if (p->graph) { (void)hipGraphDestroy(p->graph); p->graph = nullptr; }
+  for (int i = 0; i < 3; ++i) {
+    if (p->sexec[i]) { (void)hipGraphExecDestroy(p->sexec[i]); p->sexec[i] = nullptr; }
+    if (p->sgraph[i]) { (void)hipGraphDestroy(p->sgraph[i]); p->sgraph[i] = nullptr; }
+  }
+  p->g_out = p->s_out = nullptr;
+}
+
 extern "C" marfa_status marfa_plan_tiles(const marfa_plan* p, marfa_tiles* t) {
   if (!p || !t) return fail(MARFA_E_INVALID, "null argument");
   std::memset(t, 0, sizeof *t);
@@ -861,14 +871,38 @@ extern "C" marfa_status marfa_plan_tiles(const marfa_plan* p, marfa_tiles* t) {
   return MARFA_OK;
 }
 
-static void drop_graphs(marfa_plan* p) {
-  if (p->exec) { (void)hipGraphExecDestroy(p->exec); p->exec = nullptr; }
-  if (p->graph) { (void)hipGraphDestroy(p->graph); p->graph = nullptr; }
-  for (int i = 0; i < 3; ++i) {
-    if (p->sexec[i]) { (void)hipGraphExecDestroy(p->sexec[i]); p->sexec[i] = nullptr; }
-    if (p->sgraph[i]) { (void)hipGraphDestroy(p->sgraph[i]); p->sgraph[i] = nullptr; }
+
+extern "C" marfa_status marfa_plan_set_tiles(marfa_plan* p, const marfa_tiles* t) {
+  if (!p || !t) return fail(MARFA_E_INVALID, "null argument");
+  if (t->item_nodes < 64 || t->item_nodes > 8192 || t->item_nodes % 64 != 0)
+    return fail(MARFA_E_INVALID, "item_nodes must be a multiple of 64 in [64, 8192]");
+  if (t->blocks_per_cu < 1 || t->blocks_per_cu > 32) return fail(MARFA_E_INVALID, "blocks_per_cu in [1, 32]");
+  int lnw[kLevels];
+  for (int l = 0; l < kLevels; ++l) {
+    const int w = t->wave_nodes[l];
+    if (w < 1 || w > 64 || (w & (w - 1)) != 0) return fail(MARFA_E_INVALID, "wave_nodes must be powers of 2 <= 64");
+    lnw[l] = __builtin_ctz((unsigned)w);
   }
-  p->g_out = p->s_out = nullptr;
+  std::vector<Tile> tl;
+  make_tiles(p->G, tl, t->item_nodes);
+  HIP_TRY(hipSetDevice(p->device));
+  if ((int64_t)tl.size() > p->tiles_cap) {
+    Tile* nt = nullptr;
+    marfa_status st = dmalloc(&nt, tl.size());
+    if (st != MARFA_OK) return st;
+    HIP_TRY(hipDeviceSynchronize());
+    (void)hipFree(p->d.tiles);
+    p->d.tiles = nt;
+    p->tiles_cap = (int64_t)tl.size();
+  }
+  HIP_TRY(hipMemcpy(p->d.tiles, tl.data(), tl.size() * sizeof(Tile), hipMemcpyHostToDevice));
+  drop_graphs(p);
+  for (int l = 0; l < kLevels; ++l) p->G.lnw[l] = lnw[l];
+  p->tiles = tl;
+  p->base_nodes = t->item_nodes;
+  p->blocks_per_cu = t->blocks_per_cu;
+  p->grid = p->cu_count * t->blocks_per_cu;
+  return MARFA_OK;
 }
 
 // Level stage alone over every layer with the given tiles and grid; the

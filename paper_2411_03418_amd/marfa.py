@@ -100,6 +100,8 @@ def lib():
         L.marfa_plan_count.argtypes = [vp, C.POINTER(Stats)]
         L.marfa_plan_tiles.argtypes = [vp, C.POINTER(Tiles)]
         L.marfa_plan_tune.argtypes = [vp, vp, i64, vp]
+        L.marfa_plan_set_tiles.argtypes = [vp, C.POINTER(Tiles)]
+        L.marfa_plan_set_tiles.restype = C.c_int32
         L.marfa_execute_timed.argtypes = [vp, vp, i64, vp, C.POINTER(Timing)]
         L.marfa_plan_destroy.argtypes = [vp]
         L.marfa_plan_destroy.restype = None
@@ -236,6 +238,13 @@ class Plan:
         _check(lib().marfa_plan_tiles(self._h, C.byref(t)))
         return dict(item_nodes=t.item_nodes, blocks_per_cu=t.blocks_per_cu, tuned=bool(t.tuned),
                     wave_nodes=list(t.wave_nodes), tune_ms=float(t.tune_ms))
+
+    def set_tiles(self, tiles):
+        """Use tile parameters from an earlier tune (dict as returned by tiles())."""
+        t = Tiles(int(tiles["item_nodes"]), int(tiles["blocks_per_cu"]), 0,
+                  (C.c_int32 * 11)(*[int(w) for w in tiles["wave_nodes"]]), 0.0)
+        _check(lib().marfa_plan_set_tiles(self._h, C.byref(t)))
+        return self.tiles()
 
     def tune(self, out=None, stream=None):
         """Autotune the level kernel's tiles on the device (synchronous);
