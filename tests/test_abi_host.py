@@ -97,3 +97,22 @@ def test_no_device_reports_device_error():
 def test_record_number_example():
     # Appendix A: 7564 cm^-1 is in record 756
     assert marfa.record_number(7564.0) == 756
+
+
+@pytest.mark.parametrize("chi,cutoff", [(7, 125.0), (-1, 125.0), (1, 0.0), (1, -3.0), (1, float("nan"))])
+def test_surrogate_create_rejects_bad_configuration(chi, cutoff):
+    L = marfa.lib()
+    h = C.c_void_p()
+    st = L.marfa_surrogate_create(C.byref(h), chi, cutoff, 1, 0)
+    assert st == marfa.E_INVALID
+    assert not h.value
+
+
+def test_null_handles_are_rejected():
+    L = marfa.lib()
+    t = marfa.Tiles()
+    assert L.marfa_plan_set_tiles(None, C.byref(t)) == marfa.E_INVALID
+    assert L.marfa_plan_set_surrogate(None, None) == marfa.E_INVALID
+    assert L.marfa_surrogate_set_params(None, None, 0) == marfa.E_INVALID
+    assert L.marfa_surrogate_train(None, None, None, None) == marfa.E_INVALID
+    assert L.marfa_plan_tune(None, None, 0, None) == marfa.E_INVALID
