@@ -34,7 +34,7 @@ PEAK_FP32_VALU_TFLOPS = 157.3   # MI355X published FP32 vector peak
 # address arithmetic are not counted):
 FLOP_WING = 18        # d, d^2+g^2, 1/., e, U, 1+eU, A Q sum, chi = exp2(c0+c1 d), acc += g chi
 FLOP_TERM = 6         # one more term of the asymptotic wing series
-FLOP_CORE = 2 * 260   # rational core in FP64 (31 complex Horner steps + setup); FP64 counts double
+FLOP_CORE = 2 * 230   # rational core in FP64 (27 complex Horner steps + setup); FP64 counts double
 FLOP_BAND = 6         # three stencil weights times coarse values, per band pair
 
 

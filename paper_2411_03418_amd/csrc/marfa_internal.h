@@ -14,7 +14,7 @@ constexpr int kGroups = 11;      // lines grouped by start level 0..10
 constexpr int kMaxIntervals = 8; // disjoint |d| windows per (level, start-level classes)
 constexpr int kMaxJumps = 5;     // jump points of T_(l+1) per (level, start level)
 constexpr int kWave = 64;        // CDNA wavefront
-constexpr int kWeidemanN32 = 32; // rational-series length, single-precision path
+constexpr int kWeidemanN32 = 28; // rational-series length, single-precision path (1.5e-7 for |z| < 6)
 constexpr int kWeidemanN64 = 48; // rational-series length, double-precision path
 constexpr int kBucketPerCm = 256; // line-index buckets per cm^-1 (8 finest steps)
 
@@ -58,13 +58,17 @@ struct IntervalSet {
   // chi over the whole window: exp2(c0 + c1 |d|) (fine units), or chi_mixed = 1
   double chi_c0[kMaxIntervals], chi_c1[kMaxIntervals];
   int32_t chi_mixed[kMaxIntervals];
-  // fast region test for layers whose lines all start below l: |d| in
-  // [ra, rbx) (rbx exclusive: min(b_l, next value above the cut-off)), and chi
-  // over that range as exp2(fc0 + fc1 |d|) unless fchi_mixed
+  // fast region test, one window: fast_ok = 1 when the lines of the level all
+  // start below it (annulus |d| in [ra, rbx), two sides), 2 when none starts
+  // below it (own region |d| < rbx, ra = 0, one side); rbx is exclusive:
+  // min(b_l, next value above the cut-off).  fast_need_s: lines starting
+  // above the level are present and are skipped by their start level.  chi
+  // over the window is exp2(fc0 + fc1 |d|) unless fchi_mixed.
   double ra64, rbx64;
   float ra32, rbx32;
   double fc0, fc1;
   int32_t fchi_mixed, fast_ok;
+  int32_t fast_need_s, fast_pad;
   // jumps of T_(l+1), ascending, with the classes of lines they apply to
   // (bit 0: start level <= l, bit 1: start level > l)
   double jq[kMaxJumps];

@@ -639,18 +639,25 @@ template <> struct RecBuf<double> {
   }
 };
 
-// Fast region scan for layers whose lines all start below level l: one side
-// (SGN) of the annulus, |d| in [ra, rbx), chi one exponential piece (or any).
+// Fast region scan over one window: SGN = +1 / -1 one side of the annulus
+// |d| in [ra, rbx); SGN = 0 the own region |d| < rbx, where lanes past the
+// window's last line are masked explicitly (a zero record at d = 0 would be
+// NaN).  Lines with start level above smax are skipped.  chi is one
+// exponential piece over the window (or any).
 template <typename R, bool COUNT, int SGN, bool SURR>
 __device__ __forceinline__ void scan_fast(__amdgpu_buffer_rsrc_t rs, const R* __restrict__ sp, int32_t j0,
-                                          int32_t j1, int S, int slice, int32_t X, R ra, R rbx, bool chi_none,
-                                          bool chi_mixed, R c0, R c1, const Geometry& G, R& acc, Counts& cnt,
-                                          uint32_t& n_used, const LevelArgs& a) {
+                                          int32_t j1, int S, int slice, int32_t X, R ra, R rbx, int smax,
+                                          bool chi_none, bool chi_mixed, R c0, R c1, const Geometry& G, R& acc,
+                                          Counts& cnt, uint32_t& n_used, const LevelArgs& a) {
   using Rec = typename RecOf<R>::T;
-  const R c1s = SGN > 0 ? c1 : -c1;   // chi exponent slope in the signed distance
+  const R c1s = SGN < 0 ? -c1 : c1;   // chi exponent slope in the signed distance
   auto step = [&](const Rec& L, int32_t j) {
     const R d = R(X - L.k0) - R(L.frac);
-    const bool in_reg = SGN > 0 ? (d >= ra && d < rbx) : (d <= -ra && d > -rbx);
+    bool in_reg;
+    if (SGN > 0) in_reg = d >= ra && d < rbx;
+    else if (SGN < 0) in_reg = d <= -ra && d > -rbx;
+    else in_reg = fabs(d) < rbx && j < j1;
+    in_reg = in_reg && L.s <= smax;
     if constexpr (SURR) {
       const float g = g_surr<COUNT>(d, L, sp, j, G, a, in_reg, cnt);
       acc += in_reg ? g : R(0);
@@ -659,7 +666,7 @@ __device__ __forceinline__ void scan_fast(__amdgpu_buffer_rsrc_t rs, const R* __
       const R g = shape_fast<R, COUNT>(d, L, sp, j, G, in_reg, cnt);
       R chi;
       if (chi_none) chi = R(1);
-      else if (!chi_mixed) chi = fast_exp2<R>(fma(c1s, d, c0));
+      else if (!chi_mixed) chi = fast_exp2<R>(fma(c1s, SGN == 0 ? fabs(d) : d, c0));
       else chi = chi_any<R>(fabs(d), G);
       acc += in_reg ? g * chi : R(0);
     }
@@ -757,12 +764,27 @@ __device__ void region_tile(const Geometry& G, const LevelArgs& a, int l, int la
   const int32_t my_j = (lane < 2 * nws) ? bk[my_bucket] : 0;
   R acc = R(0);
   if (iv->fast_ok && G.shape != MARFA_SHAPE_DOPPLER) {
-    // lines all start below l: one annulus window, two sides
-    const R ra = active ? (sizeof(R) == 4 ? R(iv->ra32) : R(iv->ra64)) : R(INFINITY);
-    const R rbx = sizeof(R) == 4 ? R(iv->rbx32) : R(iv->rbx64);
     const bool chi_mixed = iv->fchi_mixed != 0;
     const bool chi_none = !chi_mixed && iv->fc0 == 0.0 && iv->fc1 == 0.0;
     const R c0 = R(iv->fc0), c1 = R(iv->fc1);
+    const int smax = uniform(iv->fast_need_s) ? l : kLevels;
+    if (uniform(iv->fast_ok) == 2) {
+      // no line starts below l: the own region, one window
+      const R rbx = active ? (sizeof(R) == 4 ? R(iv->rbx32) : R(iv->rbx64)) : R(-1);
+      const int32_t j0 = uniform(__shfl(my_j, 0)), j1 = uniform(__shfl(my_j, 1));
+      if (j0 < j1) {
+        const __amdgpu_buffer_rsrc_t rs =
+            __builtin_amdgcn_make_buffer_rsrc((void*)rec, 0, (int)(j1 * (int32_t)sizeof(Rec)), 0x00020000);
+        scan_fast<R, COUNT, 0, SURR>(rs, sp, j0, j1, S, slice, X, R(0), rbx, smax, chi_none, chi_mixed, c0, c1, G,
+                                     acc, cnt, n_used, a);
+      }
+      for (int o = S >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+      if (active && slice == 0) lds_acc[m - G.lo[l] - item_first] = acc;
+      return;
+    }
+    // every line with a region here starts below l: one annulus window, two sides
+    const R ra = active ? (sizeof(R) == 4 ? R(iv->ra32) : R(iv->ra64)) : R(INFINITY);
+    const R rbx = sizeof(R) == 4 ? R(iv->rbx32) : R(iv->rbx64);
     for (int side = 0; side < 2; ++side) {
       const int32_t j0 = uniform(__shfl(my_j, 2 * side)), j1 = uniform(__shfl(my_j, 2 * side + 1));
       if (j0 >= j1) continue;
@@ -770,11 +792,11 @@ __device__ void region_tile(const Geometry& G, const LevelArgs& a, int l, int la
       const __amdgpu_buffer_rsrc_t rs =
           __builtin_amdgcn_make_buffer_rsrc((void*)rec, 0, (int)(j1 * (int32_t)sizeof(Rec)), 0x00020000);
       if (side == 0)
-        scan_fast<R, COUNT, 1, SURR>(rs, sp, j0, j1, S, slice, X, ra, rbx, chi_none, chi_mixed, c0, c1, G, acc,
-                                      cnt, n_used, a);
+        scan_fast<R, COUNT, 1, SURR>(rs, sp, j0, j1, S, slice, X, ra, rbx, smax, chi_none, chi_mixed, c0, c1, G,
+                                     acc, cnt, n_used, a);
       else
-        scan_fast<R, COUNT, -1, SURR>(rs, sp, j0, j1, S, slice, X, ra, rbx, chi_none, chi_mixed, c0, c1, G, acc,
-                                      cnt, n_used, a);
+        scan_fast<R, COUNT, -1, SURR>(rs, sp, j0, j1, S, slice, X, ra, rbx, smax, chi_none, chi_mixed, c0, c1, G,
+                                      acc, cnt, n_used, a);
     }
     for (int o = S >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
     if (active && slice == 0) lds_acc[m - G.lo[l] - item_first] = acc;
@@ -973,6 +995,8 @@ __device__ void band_lines(const Geometry& G, const LevelArgs& a, int l, int lay
         }
         const int32_t un = __shfl_down(u32, 1);
         const bool seg_end = lane == 63 || un != u32;
+        // at fine levels lines are sparse: no two lanes share a centre and the merge is skipped
+        const bool merge = __builtin_amdgcn_ballot_w64(same != 0u) != 0;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           const int64_t kc = u - 1 + c;
@@ -1004,10 +1028,12 @@ __device__ void band_lines(const Geometry& G, const LevelArgs& a, int l, int lay
                          (R(0.5 * tt * (tt - 1.0)) * T1[c] + R(1.0 - tt * tt) * T1[c + 1] +
                           R(0.5 * tt * (tt + 1.0)) * T1[c + 2]);
             R v = use ? v0 : R(0);
+            if (merge) {
 #pragma unroll
-            for (int st = 0; st < 6; ++st) {
-              const R vo = __shfl_up(v, 1 << st);
-              if (same & (1u << st)) v += vo;
+              for (int st = 0; st < 6; ++st) {
+                const R vo = __shfl_up(v, 1 << st);
+                if (same & (1u << st)) v += vo;
+              }
             }
             if (seg_end && own) lds_acc[m - base] += v;
             if (COUNT && use) { n_band++; if (!in_reg) n_used++; }

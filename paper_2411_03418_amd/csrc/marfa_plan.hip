@@ -224,7 +224,7 @@ static void make_geometry(const marfa_request& rq, double nu_max, Geometry& G) {
     }
     out[0] = 0.0;
   };
-  fill(1e-8, 16, G.eterm32);
+  fill(1e-7, 16, G.eterm32);
   fill(1e-17, 64, G.eterm64);
   // Eq.(10): 1.084 e^{-0.027|d|}, 0.208 e^{-0.016|d|}, 0.025 e^{-0.009|d|}
   const double l2e = 1.0 / std::log(2.0);
@@ -280,10 +280,15 @@ static bool make_intervals(const Geometry& G, int chi, std::vector<IntervalSet>&
           }
         }
       }
-      // fast region test when every line starts below l (one annulus window)
+      // fast region test: every line with a region here starts below l (one
+      // annulus window), or none starts below l (the own region); lines that
+      // start above l are skipped by their start level
       S.fast_ok = 0;
-      if (combo == 1 && l > 0 && S.n_iv == 1) {
-        const double ra = G.b[l - 1];
+      S.fast_need_s = 0;
+      const bool annulus = (combo == 1 || combo == 5) && l > 0 && S.n_iv == 1;
+      const bool own = (combo == 2 || combo == 6) && S.n_iv == 1;
+      if (annulus || own) {
+        const double ra = annulus ? G.b[l - 1] : 0.0;
         const double bl = top ? INFINITY : G.b[l];
         double rbx64;
         float rbx32;
@@ -295,7 +300,8 @@ static bool make_intervals(const Geometry& G, int chi, std::vector<IntervalSet>&
           rbx64 = bl;
           rbx32 = (float)bl;
         }
-        S.fast_ok = 1;
+        S.fast_ok = annulus ? 1 : 2;
+        S.fast_need_s = (combo & 4) ? 1 : 0;
         S.ra64 = ra;
         S.rbx64 = rbx64;
         S.ra32 = (float)ra;
