@@ -40,9 +40,6 @@ struct Geometry {
   double bucket_origin;      // wavenumber of bucket 0 [cm^-1] (below every shifted centre)
   int32_t ncoarse;           // 1 cm^-1 buckets of the coarse line index
   int32_t pad2;
-  // wing series: term k is needed while e >= eterm[k] (single, double precision)
-  float eterm32[16];
-  double eterm64[64];
   // Tonkov chi pieces as exp2(chi_c0[i] + chi_c1[i] |d|), |d| in cm (host-computed)
   double chi_c0[3], chi_c1[3];
 };

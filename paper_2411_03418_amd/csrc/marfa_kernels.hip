@@ -54,7 +54,7 @@ template <> struct RecOf<double> { using T = LineRec64; };
 // Wing series cut and the |z|^2 above which it replaces the rational core.
 template <typename R> struct Prec;
 template <> struct Prec<float> {
-  static constexpr float kEps = 1e-8f;
+  static constexpr float kEps = 1e-7f;
   static constexpr float kZ2 = 36.0f;
   static constexpr int kTerms = 12;
 };
@@ -441,15 +441,37 @@ template <typename R> __device__ __forceinline__ R fast_exp2(R x);
 template <> __device__ __forceinline__ float fast_exp2<float>(float x) { return __builtin_amdgcn_exp2f(x); }
 template <> __device__ __forceinline__ double fast_exp2<double>(double x) { return exp2(x); }
 
+// Wing series of the fast path.  Term k (coefficient (2k-1)!! e^k) is kept
+// while some live lane has (2k+1)!! e^k >= eps, i.e. e >= thr(k) with
+// thr(k) = (eps / (2k+1)!!)^(1/k), computed at compile time (Newton's method
+// for the k-th root).  The core takes |z| < 6 (FP32) / 8 (FP64); at |z| = 6
+// the FP32 series needs 8 terms for 1e-7.
+constexpr double ct_pow(double x, int n) {
+  double r = 1.0;
+  for (int i = 0; i < n; ++i) r *= x;
+  return r;
+}
+constexpr double ct_root(double a, int k) {
+  double r = 1.0;
+  for (int i = 0; i < 400; ++i) r -= (ct_pow(r, k) - a) / (k * ct_pow(r, k - 1));
+  return r;
+}
+constexpr double ct_series_thr(double eps, int k) {
+  double df = 1.0;
+  for (int i = 1; i <= k; ++i) df *= 2.0 * i + 1.0;
+  return ct_root(eps / df, k);
+}
 template <typename R> struct Series;
 template <> struct Series<float> {
   static constexpr int kMax = 10;
-  static __device__ __forceinline__ float thr(const Geometry& G, int k) { return G.eterm32[k]; }
+  static constexpr float thr[kMax + 1] = {
+      0.f, (float)ct_series_thr(1e-7, 1), (float)ct_series_thr(1e-7, 2), (float)ct_series_thr(1e-7, 3),
+      (float)ct_series_thr(1e-7, 4), (float)ct_series_thr(1e-7, 5), (float)ct_series_thr(1e-7, 6),
+      (float)ct_series_thr(1e-7, 7), (float)ct_series_thr(1e-7, 8), (float)ct_series_thr(1e-7, 9),
+      (float)ct_series_thr(1e-7, 10)};
 };
-template <> struct Series<double> {
-  static constexpr int kMax = 60;
-  static __device__ __forceinline__ double thr(const Geometry& G, int k) { return G.eterm64[k]; }
-};
+static_assert(Series<float>::thr[2] > 8.1e-5f && Series<float>::thr[2] < 8.2e-5f, "sqrt(1e-7 / 15)");
+template <> struct Series<double> { static constexpr int kMax = 60; };
 
 // chi of Eq.(10) without branches: exp2(c0 + c1 |d|) with the piece chosen by selects
 template <typename R>
@@ -484,10 +506,18 @@ __device__ __forceinline__ R shape_fast(R d, const typename RecOf<R>::T& L, cons
   R U = fma(R(-4) * R(L.gam2), Q, R(3));
   R sum = fma(e, U, R(1));
   const bool wing = live && !core;
-  if (__builtin_amdgcn_ballot_w64(wing && e >= Series<R>::thr(G, 2))) {
+  // term k, with coefficient c_k = (2k-1)!! e^k, is kept while some live
+  // wing lane has (2k+1)!! e^k >= eps: e >= thr(k) (FP32), or from the
+  // running coefficient (2k+1)(2k-1) c_(k-1) e >= eps (FP64)
+  const R eps = Prec<R>::kEps;
+  auto more = [&](int k, R ck_prev) -> bool {
+    if constexpr (sizeof(R) == 4) return e >= Series<float>::thr[k];
+    else return R((2 * k + 1) * (2 * k - 1)) * ck_prev * e >= eps;
+  };
+  if (__builtin_amdgcn_ballot_w64(wing && more(2, e))) {
     const R t = U - R(1);
     R Um = R(1), ck = e;
-#pragma unroll 4
+#pragma unroll
     for (int k = 2; k < Series<R>::kMax; ++k) {
       ck *= R(2 * k - 1) * e;
       const R Un = t * U - Um;
@@ -495,7 +525,7 @@ __device__ __forceinline__ R shape_fast(R d, const typename RecOf<R>::T& L, cons
       U = Un;
       sum += ck * U;
       if (COUNT && wing) cnt.terms++;
-      if (!__builtin_amdgcn_ballot_w64(wing && e >= Series<R>::thr(G, k + 1))) break;
+      if (k + 1 >= Series<R>::kMax || !__builtin_amdgcn_ballot_w64(wing && more(k + 1, ck))) break;
     }
   }
   R f = R(L.A) * Q * sum;

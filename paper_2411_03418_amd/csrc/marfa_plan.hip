@@ -214,18 +214,6 @@ static void make_geometry(const marfa_request& rq, double nu_max, Geometry& G) {
   G.fp64 = rq.fp64;
   G.nbucket = (int32_t)std::ceil((nu_max + 1.0) * kBucketPerCm) + 1;
   G.ncoarse = (int32_t)std::ceil(nu_max + 1.0) + 1;
-  // term k of the wing series, bounded by (2k+1)!! e^k, matters while it is
-  // above the precision's cut: e >= (eps / (2k+1)!!)^(1/k)
-  auto fill = [](double eps, int kmax, auto* out) {
-    double df = 1.0;  // (2k+1)!!
-    for (int k = 1; k < kmax; ++k) {
-      df *= (2.0 * k + 1.0);
-      out[k] = std::pow(eps / df, 1.0 / k);
-    }
-    out[0] = 0.0;
-  };
-  fill(1e-7, 16, G.eterm32);
-  fill(1e-17, 64, G.eterm64);
   // Eq.(10): 1.084 e^{-0.027|d|}, 0.208 e^{-0.016|d|}, 0.025 e^{-0.009|d|}
   const double l2e = 1.0 / std::log(2.0);
   G.chi_c0[0] = std::log2(1.084); G.chi_c1[0] = -0.027 * l2e;
