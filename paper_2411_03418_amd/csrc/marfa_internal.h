@@ -75,6 +75,14 @@ struct IntervalSet {
   // lc_eps widens the centre estimate past single-precision rounding of d
   int32_t lc_ok, pad_lc;
   double lc_eps;
+  // jumps farther apart than two stencil hulls: a hull holds at most one,
+  // so the smallest straddled jump is the one straddled
+  int32_t jumps_isolated, pad_ji;
+  // chi over the evaluation points around jump k (|d| within q +- (3 r1 + 4)):
+  // jchi_mode 0 = 1, 1 = exp2(jchi_c0 + jchi_c1 |d|) (fine units), 2 = any piece
+  int32_t jchi_mode[kMaxJumps];
+  int32_t pad_jc;
+  double jchi_c0[kMaxJumps], jchi_c1[kMaxJumps];
 };
 
 // One work item of the level kernel: `count` consecutive nodes of one level,
@@ -101,10 +109,10 @@ struct LineRec64 {
   int32_t k0;
   int32_t s;
   double frac, A, gam, gam2, ae, xs;
-  double pad;     // 64-byte records: four 16-byte loads
+  double pad;     // 64-byte records
 };
-static_assert(sizeof(LineRec32) == 32, "LineRec32 is loaded as two 16-byte words");
-static_assert(sizeof(LineRec64) == 64, "LineRec64 is loaded as four 16-byte words");
+static_assert(sizeof(LineRec32) == 32, "LineRec32 is two 16-byte words");
+static_assert(sizeof(LineRec64) == 64, "LineRec64 is four 16-byte words");
 
 // Device-side workspace of a plan.
 struct DeviceBuffers {

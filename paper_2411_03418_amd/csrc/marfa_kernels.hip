@@ -579,6 +579,22 @@ __device__ float g_surr(float d, const LineRec32& L, const float* __restrict__ s
   return v;
 }
 
+// g(d) with the cut-off for the band pass, chi given for the jump's
+// neighbourhood (mode 0: 1, 1: one piece exp2(c0 + c1 |d|), 2: any piece)
+template <typename R, bool COUNT, bool SURR>
+__device__ __forceinline__ R g_band(R d, const typename RecOf<R>::T& L, const R* __restrict__ sp, int32_t j,
+                                    const Geometry& G, R cfine, bool live, Counts& cnt, const LevelArgs& a,
+                                    int chi_mode, R c0, R c1) {
+  if (SURR || G.shape == MARFA_SHAPE_DOPPLER) return g_eval<R, COUNT, SURR>(d, L, sp, j, G, cfine, live, cnt, a);
+  const R ad = fabs(d);
+  const R f = shape_fast<R, COUNT>(d, L, sp, j, G, live && ad <= cfine, cnt);
+  R chi;
+  if (chi_mode == 0) chi = R(1);
+  else if (chi_mode == 1) chi = fast_exp2<R>(fma(c1, ad, c0));
+  else chi = chi_any<R>(ad, G);
+  return ad <= cfine ? f * chi : R(0);
+}
+
 // g(d) with the cut-off, plain or learned (wave-collective when SURR)
 template <typename R, bool COUNT, bool SURR>
 __device__ __forceinline__ R g_eval(R d, const typename RecOf<R>::T& L, const R* __restrict__ sp, int32_t j,
@@ -644,38 +660,14 @@ __device__ __forceinline__ void scan_region(const typename RecOf<R>::T* __restri
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// Line record through a raw buffer resource: 32-bit offsets, and lines past
-// the resource's end read as zero (zero intensity), so no clamping is needed.
-template <typename R> struct RecBuf;
-template <> struct RecBuf<float> {
-  static __device__ __forceinline__ LineRec32 load(__amdgpu_buffer_rsrc_t r, int32_t j) {
-    LineRec32 L;
-    auto a = __builtin_amdgcn_raw_buffer_load_b128(r, j * (int32_t)sizeof(LineRec32), 0, 0);
-    auto b = __builtin_amdgcn_raw_buffer_load_b128(r, j * (int32_t)sizeof(LineRec32) + 16, 0, 0);
-    __builtin_memcpy(&L, &a, 16);
-    __builtin_memcpy(reinterpret_cast<char*>(&L) + 16, &b, 16);
-    return L;
-  }
-};
-template <> struct RecBuf<double> {
-  static __device__ __forceinline__ LineRec64 load(__amdgpu_buffer_rsrc_t r, int32_t j) {
-    LineRec64 L;
-    char* o = reinterpret_cast<char*>(&L);
-    for (int k = 0; k < 4; ++k) {
-      auto a = __builtin_amdgcn_raw_buffer_load_b128(r, j * (int32_t)sizeof(LineRec64) + 16 * k, 0, 0);
-      __builtin_memcpy(o + 16 * k, &a, 16);
-    }
-    return L;
-  }
-};
-
 // Fast region scan over one window: SGN = +1 / -1 one side of the annulus
-// |d| in [ra, rbx); SGN = 0 the own region |d| < rbx, where lanes past the
-// window's last line are masked explicitly (a zero record at d = 0 would be
-// NaN).  Lines with start level above smax are skipped.  chi is one
-// exponential piece over the window (or any).
+// |d| in [ra, rbx); SGN = 0 the own region |d| < rbx.  Lanes past the
+// window's last line read that line again and are masked.  Lines with start
+// level above smax are skipped.  chi is one exponential piece over the
+// window (or any).
 template <typename R, bool COUNT, int SGN, bool SURR>
-__device__ __forceinline__ void scan_fast(__amdgpu_buffer_rsrc_t rs, const R* __restrict__ sp, int32_t j0,
+__device__ __forceinline__ void scan_fast(const typename RecOf<R>::T* __restrict__ rec, const R* __restrict__ sp,
+                                          int32_t j0,
                                           int32_t j1, int S, int slice, int32_t X, R ra, R rbx, int smax,
                                           bool chi_none, bool chi_mixed, R c0, R c1, const Geometry& G, R& acc,
                                           Counts& cnt, uint32_t& n_used, const LevelArgs& a) {
@@ -686,8 +678,8 @@ __device__ __forceinline__ void scan_fast(__amdgpu_buffer_rsrc_t rs, const R* __
     bool in_reg;
     if (SGN > 0) in_reg = d >= ra && d < rbx;
     else if (SGN < 0) in_reg = d <= -ra && d > -rbx;
-    else in_reg = fabs(d) < rbx && j < j1;
-    in_reg = in_reg && L.s <= smax;
+    else in_reg = fabs(d) < rbx;
+    in_reg = in_reg && L.s <= smax && j < j1;
     if constexpr (SURR) {
       const float g = g_surr<COUNT>(d, L, sp, j, G, a, in_reg, cnt);
       acc += in_reg ? g : R(0);
@@ -703,11 +695,11 @@ __device__ __forceinline__ void scan_fast(__amdgpu_buffer_rsrc_t rs, const R* __
     if (COUNT && in_reg) n_used++;
   };
   int32_t j = j0 + slice;
-  Rec La = RecBuf<R>::load(rs, j);
+  Rec La = rec[j < j1 ? j : j1 - 1];
   for (int32_t J = j0; J < j1; J += 2 * S) {
-    const Rec Lb = RecBuf<R>::load(rs, J + S + slice);
+    const Rec Lb = rec[J + S + slice < j1 ? J + S + slice : j1 - 1];
     step(La, J + slice);
-    La = RecBuf<R>::load(rs, J + 2 * S + slice);
+    La = rec[J + 2 * S + slice < j1 ? J + 2 * S + slice : j1 - 1];
     if (COUNT && (threadIdx.x & 63) == 0) cnt.iters++;
     if (J + S < j1) {
       step(Lb, J + S + slice);
@@ -803,9 +795,7 @@ __device__ void region_tile(const Geometry& G, const LevelArgs& a, int l, int la
       const R rbx = active ? (sizeof(R) == 4 ? R(iv->rbx32) : R(iv->rbx64)) : R(-1);
       const int32_t j0 = uniform(__shfl(my_j, 0)), j1 = uniform(__shfl(my_j, 1));
       if (j0 < j1) {
-        const __amdgpu_buffer_rsrc_t rs =
-            __builtin_amdgcn_make_buffer_rsrc((void*)rec, 0, (int)(j1 * (int32_t)sizeof(Rec)), 0x00020000);
-        scan_fast<R, COUNT, 0, SURR>(rs, sp, j0, j1, S, slice, X, R(0), rbx, smax, chi_none, chi_mixed, c0, c1, G,
+        scan_fast<R, COUNT, 0, SURR>(rec, sp, j0, j1, S, slice, X, R(0), rbx, smax, chi_none, chi_mixed, c0, c1, G,
                                      acc, cnt, n_used, a);
       }
       for (int o = S >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
@@ -818,14 +808,11 @@ __device__ void region_tile(const Geometry& G, const LevelArgs& a, int l, int la
     for (int side = 0; side < 2; ++side) {
       const int32_t j0 = uniform(__shfl(my_j, 2 * side)), j1 = uniform(__shfl(my_j, 2 * side + 1));
       if (j0 >= j1) continue;
-      // the resource ends at line j1: loads past the window read zero-intensity lines
-      const __amdgpu_buffer_rsrc_t rs =
-          __builtin_amdgcn_make_buffer_rsrc((void*)rec, 0, (int)(j1 * (int32_t)sizeof(Rec)), 0x00020000);
       if (side == 0)
-        scan_fast<R, COUNT, 1, SURR>(rs, sp, j0, j1, S, slice, X, ra, rbx, smax, chi_none, chi_mixed, c0, c1, G,
+        scan_fast<R, COUNT, 1, SURR>(rec, sp, j0, j1, S, slice, X, ra, rbx, smax, chi_none, chi_mixed, c0, c1, G,
                                      acc, cnt, n_used, a);
       else
-        scan_fast<R, COUNT, -1, SURR>(rs, sp, j0, j1, S, slice, X, ra, rbx, smax, chi_none, chi_mixed, c0, c1, G,
+        scan_fast<R, COUNT, -1, SURR>(rec, sp, j0, j1, S, slice, X, ra, rbx, smax, chi_none, chi_mixed, c0, c1, G,
                                       acc, cnt, n_used, a);
     }
     for (int o = S >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
@@ -984,10 +971,13 @@ __device__ void band_lines(const Geometry& G, const LevelArgs& a, int l, int lay
   }
   const int64_t base = G.lo[l] + item_first;   // absolute index of the item's first node
   const int64_t m_a = base + own_lo, m_b = base + own_hi - 1;
+  const bool iso = uniform(iv->jumps_isolated) != 0;
   for (int k = 0; k < nj; ++k) {
     const double q = iv->jq[k];
     const R rq = R(q);
     const int mask = iv->jmask[k];
+    const int chi_mode = uniform(iv->jchi_mode[k]);
+    const R cc0 = R(iv->jchi_c0[k]), cc1 = R(iv->jchi_c1[k]);
     for (int side = 0; side < 2; ++side) {
       const double sq = side == 0 ? q : -q;
       // lines whose candidate nodes can reach [m_a, m_b]
@@ -1012,7 +1002,7 @@ __device__ void band_lines(const Geometry& G, const LevelArgs& a, int l, int lay
           dd[i] = R((int32_t)((u - 2 + i) * r1) - L.k0) - R(L.frac);
           const R adi = fabs(dd[i]);
           const bool act = ok && adi <= cfine && !(l + 1 > ls && adi < b_cur);
-          const R g = g_eval<R, COUNT, SURR>(dd[i], L, sp, jl, G, cfine, act, cnt, a);
+          const R g = g_band<R, COUNT, SURR>(dd[i], L, sp, jl, G, cfine, act, cnt, a, chi_mode, cc0, cc1);
           T1[i] = act ? g : R(0);
         }
         // segments of lanes with equal u (u is non-decreasing over lanes)
@@ -1033,11 +1023,16 @@ __device__ void band_lines(const Geometry& G, const LevelArgs& a, int l, int lay
           const R d0 = dd[c], d2 = dd[c + 2];
           const R lo = (d0 * d2 <= R(0)) ? R(0) : fmin(fabs(d0), fabs(d2));
           const R hi = fmax(fabs(d0), fabs(d2));
-          R qmin = R(INFINITY);
+          bool strad;
+          if (iso) {
+            strad = ok && rq >= lo && rq <= hi;
+          } else {
+            R qmin = R(INFINITY);
 #pragma unroll
-          for (int i = 0; i < kMaxJumps; ++i)
-            if ((jm[i] & cls) && jq[i] >= lo && jq[i] <= hi) qmin = fmin(qmin, jq[i]);
-          const bool strad = ok && qmin == rq;
+            for (int i = 0; i < kMaxJumps; ++i)
+              if ((jm[i] & cls) && jq[i] >= lo && jq[i] <= hi) qmin = fmin(qmin, jq[i]);
+            strad = ok && qmin == rq;
+          }
 #pragma unroll
           for (int jj = -RHO / 2 + 1; jj <= RHO / 2; ++jj) {
             if (jj == 0) continue;
@@ -1052,7 +1047,8 @@ __device__ void band_lines(const Geometry& G, const LevelArgs& a, int l, int lay
             const bool tl = ad <= cfine && !(l > ls && ad < b_prev);
             const bool need = use && tl && !in_reg;
             R gl = R(0);
-            if (__builtin_amdgcn_ballot_w64(need)) gl = g_eval<R, COUNT, SURR>(d, L, sp, jl, G, cfine, need, cnt, a);
+            if (__builtin_amdgcn_ballot_w64(need))
+              gl = g_band<R, COUNT, SURR>(d, L, sp, jl, G, cfine, need, cnt, a, chi_mode, cc0, cc1);
             const double tt = (double)jj / (double)RHO;
             const R v0 = (need ? gl : R(0)) -
                          (R(0.5 * tt * (tt - 1.0)) * T1[c] + R(1.0 - tt * tt) * T1[c + 1] +

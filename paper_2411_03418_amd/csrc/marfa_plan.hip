@@ -330,6 +330,26 @@ static bool make_intervals(const Geometry& G, int chi, std::vector<IntervalSet>&
         S.jq[k] = qs[k].first;
         S.jmask[k] = qs[k].second;
       }
+      S.jumps_isolated = 1;
+      for (size_t k = 1; k < qs.size(); ++k)
+        if (qs[k].first - qs[k - 1].first <= 4.0 * G.r[l + (top ? 0 : 1)] + 4.0) S.jumps_isolated = 0;
+      for (size_t k = 0; k < qs.size(); ++k) {
+        S.jchi_mode[k] = 0;
+        S.jchi_c0[k] = 0.0;
+        S.jchi_c1[k] = 0.0;
+        if (chi != MARFA_CHI_TONKOV || top) continue;
+        const double reach = 3.0 * G.r[l + 1] + 4.0;
+        const double lo = std::max(0.0, qs[k].first - reach) / 2048.0, hi = (qs[k].first + reach) / 2048.0;
+        auto piece = [](double x) { return x < 3.0 ? 0 : (x <= 150.0 ? 1 : (x <= 300.0 ? 2 : 3)); };
+        const int pa = piece(lo), pb = piece(hi);
+        if (pa != pb) {
+          S.jchi_mode[k] = 2;
+        } else if (pa > 0) {
+          S.jchi_mode[k] = 1;
+          S.jchi_c0[k] = G.chi_c0[pa - 1];
+          S.jchi_c1[k] = G.chi_c1[pa - 1] / 2048.0;
+        }
+      }
       S.lc_ok = 0;
       S.lc_eps = 0.0;
       if (!top && !qs.empty()) {
@@ -399,8 +419,8 @@ static marfa_status validate(const marfa_lines* L, const marfa_layer* lay, int32
   if (L->n > 0 && (!L->nu0 || !L->S296 || !L->gamma_air || !L->gamma_self || !L->E_lower || !L->n_air ||
                    !L->delta_air))
     return fail(MARFA_E_INVALID, "null line array");
-  // line records are addressed with 32-bit byte offsets (64-byte records)
-  if (L->n > ((int64_t)1 << 25) - 1) return fail(MARFA_E_INVALID, "too many lines (at most 2^25 - 1)");
+  // line indices within a layer are 32-bit
+  if (L->n > ((int64_t)1 << 31) - 1) return fail(MARFA_E_INVALID, "too many lines (at most 2^31 - 1)");
   if (!(L->molar_mass_g > 0.0) || !std::isfinite(L->molar_mass_g)) return fail(MARFA_E_INVALID, "molar mass");
   for (int64_t j = 0; j < L->n; ++j)
     if (!std::isfinite(L->nu0[j]) || L->nu0[j] < 0.0) return fail(MARFA_E_INVALID, "line %lld: bad nu0", (long long)j);
