@@ -72,19 +72,40 @@ template <> struct Prec<double> {
 // series in Z = (L+iz)/(L-iz):  w = 1/(sqrt(pi)(L-iz)) + 2/(L-iz)^2 sum_n a_n Z^(n-1).
 // Evaluated in double precision in both paths (the real part is small next to
 // |w| near the real axis, so single precision would lose it).
-template <int N>
+// P(Z) = sum_{n=1..N} a_n Z^(n-1) has real coefficients.  QUAD evaluates it
+// by synthetic division by (X - Z)(X - conj Z) = X^2 - 2 Re Z X + |Z|^2:
+// b_m = a_(m+1) + 2 Re Z b_(m+1) - |Z|^2 b_(m+2), P(Z) = b_0 - b_1 conj(Z),
+// two real FMAs per degree instead of a complex multiply-add (its rounding
+// grows like 1/|arg Z| near the real axis: 1e-9 relative here, used by the
+// single-precision path); otherwise complex Horner.
+template <int N, bool QUAD = false>
 __device__ __forceinline__ double voigt_core(double x, double y, const double* a, double L) {
   double Ar = L + y, Ai = -x;
   double inv = 1.0 / (Ar * Ar + Ai * Ai);
   double iAr = Ar * inv, iAi = -Ai * inv;
   double Br = L - y, Bi = x;
   double Zr = Br * iAr - Bi * iAi, Zi = Br * iAi + Bi * iAr;
-  double pr = a[N], pim = 0.0;
+  double pr, pim;
+  if constexpr (QUAD) {
+    const double r = 2.0 * Zr, s = -(Zr * Zr + Zi * Zi);
+    double b1 = a[N], b2 = 0.0;
 #pragma unroll
-  for (int n = N - 1; n >= 1; --n) {
-    double tr = fma(pr, Zr, fma(-pim, Zi, a[n]));
-    pim = fma(pr, Zi, pim * Zr);
-    pr = tr;
+    for (int m = N - 2; m >= 0; --m) {
+      const double b0 = fma(r, b1, fma(s, b2, a[m + 1]));
+      b2 = b1;
+      b1 = b0;
+    }
+    pr = fma(-b2, Zr, b1);
+    pim = b2 * Zi;
+  } else {
+    pr = a[N];
+    pim = 0.0;
+#pragma unroll
+    for (int n = N - 1; n >= 1; --n) {
+      double tr = fma(pr, Zr, fma(-pim, Zi, a[n]));
+      pim = fma(pr, Zi, pim * Zr);
+      pr = tr;
+    }
   }
   double i2r = iAr * iAr - iAi * iAi, i2i = 2.0 * iAr * iAi;
   return iAr * kInvSqrtPi + 2.0 * (pr * i2r - pim * i2i);
@@ -158,7 +179,7 @@ __device__ __forceinline__ R line_value(R d, const typename RecOf<R>::T& L, R Sp
     } else {
       double K;
       if (sizeof(R) == 4)
-        K = voigt_core<kWeidemanN32>(fabs((double)x), (double)y, c_weid32, c_weidL[0]);
+        K = voigt_core<kWeidemanN32, true>(fabs((double)x), (double)y, c_weid32, c_weidL[0]);
       else
         K = voigt_core<kWeidemanN64>(fabs((double)x), (double)y, c_weid64, c_weidL[1]);
       f = R((double)L.xs * kInvSqrtPi * K);
@@ -535,7 +556,7 @@ __device__ __forceinline__ R shape_fast(R d, const typename RecOf<R>::T& L, cons
       const R y = R(L.xs) * R(L.gam);
       double K;
       if (sizeof(R) == 4)
-        K = voigt_core<kWeidemanN32>(fabs((double)x), (double)y, c_weid32, c_weidL[0]);
+        K = voigt_core<kWeidemanN32, true>(fabs((double)x), (double)y, c_weid32, c_weidL[0]);
       else
         K = voigt_core<kWeidemanN64>(fabs((double)x), (double)y, c_weid64, c_weidL[1]);
       f = sp[j] * R((double)L.xs * kInvSqrtPi * K);
