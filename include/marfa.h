@@ -48,7 +48,7 @@ typedef enum { MARFA_EVAL_PLAIN = 0, MARFA_EVAL_SURROGATE = 1 } marfa_eval;
 
 /* Line list, structure of arrays in HOST memory, n entries each (fields of the
  * 36-byte record of Appendix B).  Any order; the plan sorts by nu0.
- * Rules: 0 <= n <= 2^31 - 1; every value finite; nu0 >= 0; S296, gamma_* >= 0;
+ * Rules: 0 <= n <= 2^26 - 1; every value finite; nu0 >= 0; S296, gamma_* >= 0;
  * molar_mass_g > 0.  mol_iso may be NULL (it is carried, not used). */
 typedef struct {
   int64_t n;

@@ -27,6 +27,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "marfa_internal.h"
 
 namespace marfa {
@@ -642,12 +644,12 @@ __device__ __forceinline__ void scan_region(const typename RecOf<R>::T* __restri
   using Rec = typename RecOf<R>::T;
   const bool generic_shape = G.shape == MARFA_SHAPE_DOPPLER;
   int32_t jn = j0 + slice;
-  Rec Lnext = rec[jn < j1 ? jn : j1 - 1];
+  Rec Lnext = load_rec(rec, jn < j1 ? jn : j1 - 1);
   for (int32_t J = j0; J < j1; J += S) {
     const int32_t j = J + slice;
     const Rec L = Lnext;
     jn = j + S;
-    if (J + S < j1) Lnext = rec[jn < j1 ? jn : j1 - 1];
+    if (J + S < j1) Lnext = load_rec(rec, jn < j1 ? jn : j1 - 1);
     const R d = R(X - L.k0) - R(L.frac);
     const R ad = fabs(d);
     bool in_win = active && j < j1 && ad >= ra && ad <= rb;
@@ -680,6 +682,14 @@ __device__ __forceinline__ void scan_region(const typename RecOf<R>::T* __restri
 }
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Line record j of a layer through a 32-bit byte offset from the layer's
+// base (plans keep a layer's records under 4 GiB), so the load takes the
+// scalar-base + vector-offset form.
+template <typename Rec>
+__device__ __forceinline__ Rec load_rec(const Rec* __restrict__ rec, int32_t j) {
+  return rec[j];
+}
 
 // Fast region scan over one window: SGN = +1 / -1 one side of the annulus
 // |d| in [ra, rbx); SGN = 0 the own region |d| < rbx.  Lanes past the
@@ -716,11 +726,11 @@ __device__ __forceinline__ void scan_fast(const typename RecOf<R>::T* __restrict
     if (COUNT && in_reg) n_used++;
   };
   int32_t j = j0 + slice;
-  Rec La = rec[j < j1 ? j : j1 - 1];
+  Rec La = load_rec(rec, j < j1 ? j : j1 - 1);
   for (int32_t J = j0; J < j1; J += 2 * S) {
-    const Rec Lb = rec[J + S + slice < j1 ? J + S + slice : j1 - 1];
+    const Rec Lb = load_rec(rec, J + S + slice < j1 ? J + S + slice : j1 - 1);
     step(La, J + slice);
-    La = rec[J + 2 * S + slice < j1 ? J + 2 * S + slice : j1 - 1];
+    La = load_rec(rec, J + 2 * S + slice < j1 ? J + 2 * S + slice : j1 - 1);
     if (COUNT && (threadIdx.x & 63) == 0) cnt.iters++;
     if (J + S < j1) {
       step(Lb, J + S + slice);
@@ -764,7 +774,7 @@ __device__ __forceinline__ int stencil_of(const Geometry& G, int l, int64_t m, i
 // walks the union of its nodes' line ranges, S consecutive lines per step
 // (coalesced loads); node sums are reduced over slices and stored to LDS.
 template <typename R, bool COUNT, bool SURR>
-__device__ void region_tile(const Geometry& G, const LevelArgs& a, int l, int layer, int lnw, int64_t rel0,
+__device__ __forceinline__ void region_tile(const Geometry& G, const LevelArgs& a, int l, int layer, int lnw, int64_t rel0,
                             int tile_left, const IntervalSet* iv, R* lds_acc, int64_t item_first, Counts& cnt,
                             uint32_t& n_used) {
   using Rec = typename RecOf<R>::T;
@@ -877,7 +887,7 @@ __device__ void region_tile(const Geometry& G, const LevelArgs& a, int l, int la
 // adds D_l = T_l(d) - sum_i w_i T_(l+1)(d_i) minus the region value already
 // added.
 template <typename R, bool COUNT>
-__device__ void band_group(const Geometry& G, const LevelArgs& a, int l, int layer, int64_t rel0, int group_left,
+__device__ __forceinline__ void band_group(const Geometry& G, const LevelArgs& a, int l, int layer, int64_t rel0, int group_left,
                            const IntervalSet* iv, R* lds_acc, int64_t item_first, Counts& cnt, uint32_t& n_used,
                            uint32_t& n_band) {
   using Rec = typename RecOf<R>::T;
@@ -952,21 +962,106 @@ __device__ void band_group(const Geometry& G, const LevelArgs& a, int l, int lay
   if (active) lds_acc[m - G.lo[l] - item_first] += acc;
 }
 
+// One chunk of 64 lines of the line-major band pass for one jump and side:
+// NC candidate centres from kc0 (see band_lines).
+template <typename R, bool COUNT, int RHO, bool SURR, int NC>
+__device__ __forceinline__ void band_chunk(const typename RecOf<R>::T& L, int32_t jl, int ls, int cls, bool ok,
+                                           int64_t kc0, int side, R rq, bool iso, const IntervalSet* iv,
+                                           int chi_mode, R cc0, R cc1, int l, int32_t rl, int32_t r1, R cfine,
+                                           R b_prev, R b_cur, int64_t m_a, int64_t m_b, int64_t base,
+                                           const R* __restrict__ sp, const Geometry& G, const LevelArgs& a,
+                                           R* lds_acc, Counts& cnt, uint32_t& n_used, uint32_t& n_band) {
+  const int lane = threadIdx.x & 63;
+  // T_(l+1) at level-(l+1) nodes kc0-1 .. kc0+NC
+  R dd[NC + 2], T1[NC + 2];
+#pragma unroll
+  for (int i = 0; i < NC + 2; ++i) {
+    dd[i] = R((int32_t)((kc0 - 1 + i) * r1) - L.k0) - R(L.frac);
+    const R adi = fabs(dd[i]);
+    const bool act = ok && adi <= cfine && !(l + 1 > ls && adi < b_cur);
+    const R g = g_band<R, COUNT, SURR>(dd[i], L, sp, jl, G, cfine, act, cnt, a, chi_mode, cc0, cc1);
+    T1[i] = act ? g : R(0);
+  }
+  // segments of lanes with equal kc0 (non-decreasing over lanes)
+  const int32_t u32 = (int32_t)kc0;
+  uint32_t same = 0;
+#pragma unroll
+  for (int st = 0; st < 6; ++st) {
+    const int32_t uo = __shfl_up(u32, 1 << st);
+    if (lane >= (1 << st) && uo == u32) same |= 1u << st;
+  }
+  const int32_t un = __shfl_down(u32, 1);
+  const bool seg_end = lane == 63 || un != u32;
+  // at fine levels lines are sparse: no two lanes share a centre and the merge is skipped
+  const bool merge = __builtin_amdgcn_ballot_w64(same != 0u) != 0;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const int64_t kc = kc0 + c;
+    const R d0 = dd[c], d2 = dd[c + 2];
+    const R lo = (d0 * d2 <= R(0)) ? R(0) : fmin(fabs(d0), fabs(d2));
+    const R hi = fmax(fabs(d0), fabs(d2));
+    bool strad;
+    if (iso) {
+      strad = ok && rq >= lo && rq <= hi;
+    } else {
+      R qmin = R(INFINITY);
+      const int nj = uniform(iv->n_jump);
+      for (int i = 0; i < nj; ++i) {
+        const R qi = R(iv->jq[i]);
+        if ((iv->jmask[i] & cls) && qi >= lo && qi <= hi) qmin = fmin(qmin, qi);
+      }
+      strad = ok && qmin == rq;
+    }
+#pragma unroll
+    for (int jj = -RHO / 2 + 1; jj <= RHO / 2; ++jj) {
+      if (jj == 0) continue;
+      const int64_t m = kc * RHO + jj;
+      const R d = R((int32_t)(m * rl) - L.k0) - R(L.frac);
+      const bool side_ok = side == 0 ? d > R(0) : !(d > R(0));
+      const bool own = m >= m_a && m <= m_b;
+      const bool use = strad && own && side_ok;
+      const R ad = fabs(d);
+      const R rlo = (l == ls) ? R(0) : b_prev;
+      const bool in_reg = ls <= l && ad >= rlo && ad < b_cur && ad <= cfine;
+      const bool tl = ad <= cfine && !(l > ls && ad < b_prev);
+      const bool need = use && tl && !in_reg;
+      R gl = R(0);
+      if (__builtin_amdgcn_ballot_w64(need))
+        gl = g_band<R, COUNT, SURR>(d, L, sp, jl, G, cfine, need, cnt, a, chi_mode, cc0, cc1);
+      const double tt = (double)jj / (double)RHO;
+      const R v0 = (need ? gl : R(0)) -
+                   (R(0.5 * tt * (tt - 1.0)) * T1[c] + R(1.0 - tt * tt) * T1[c + 1] +
+                    R(0.5 * tt * (tt + 1.0)) * T1[c + 2]);
+      R v = use ? v0 : R(0);
+      if (merge) {
+#pragma unroll
+        for (int st = 0; st < 6; ++st) {
+          const R vo = __shfl_up(v, 1 << st);
+          if (same & (1u << st)) v += vo;
+        }
+      }
+      if (seg_end && own) lds_acc[m - base] += v;
+      if (COUNT && use) { n_band++; if (!in_reg) n_used++; }
+    }
+  }
+
+}
+
 // Residual-band pass, line-major form, for one wavefront owning the item's
 // nodes [own_lo, own_hi).  For a jump q of T_(l+1) and a side, put the
 // line's jump point at P = nu~0 + q (nodes above the line) or nu~0 - q (nodes
 // below).  A level-l node's stencil hull [(kc-1) r1, (kc+1) r1] holds P only
 // if its nearest level-(l+1) centre kc is within one step of P / r1, so the
-// nodes to correct are the (RHO - 1) three-point nodes around each of three
-// centres.  Lane = line: T_(l+1) is evaluated once at the five level-(l+1)
-// nodes around P, every candidate node gets D_l = T_l(d) - sum w_i T_(l+1)(d_i)
+// nodes to correct are the (RHO - 1) three-point nodes around each of two
+// (three at coarse nodes) centres.  Lane = line: T_(l+1) is evaluated once at
+// the level-(l+1) nodes around P, every candidate node gets D_l = T_l(d) - sum w_i T_(l+1)(d_i)
 // minus the region value (zero unless its hull straddles q and q is the
 // smallest straddled jump), and a segmented sum over lanes with the same
 // centre estimate -- non-decreasing in line order -- merges corrections of a
 // node before one lane adds them to its LDS slot.  Per slot there is one
 // writer and a fixed summation order, so results are reproducible.
 template <typename R, bool COUNT, int RHO, bool SURR>
-__device__ void band_lines(const Geometry& G, const LevelArgs& a, int l, int layer, int64_t item_first, int own_lo,
+__device__ __forceinline__ void band_lines(const Geometry& G, const LevelArgs& a, int l, int layer, int64_t item_first, int own_lo,
                            int own_hi, const IntervalSet* iv, R* lds_acc, Counts& cnt, uint32_t& n_used,
                            uint32_t& n_band) {
   using Rec = typename RecOf<R>::T;
@@ -983,13 +1078,6 @@ __device__ void band_lines(const Geometry& G, const LevelArgs& a, int l, int lay
   const double eps = iv->lc_eps;
   const double inv_r1 = 1.0 / (double)r1;
   const int nj = uniform(iv->n_jump);
-  R jq[kMaxJumps];
-  int jm[kMaxJumps];
-#pragma unroll
-  for (int i = 0; i < kMaxJumps; ++i) {
-    jq[i] = i < nj ? R(iv->jq[i]) : R(INFINITY);
-    jm[i] = i < nj ? iv->jmask[i] : 0;
-  }
   const int64_t base = G.lo[l] + item_first;   // absolute index of the item's first node
   const int64_t m_a = base + own_lo, m_b = base + own_hi - 1;
   const bool iso = uniform(iv->jumps_isolated) != 0;
@@ -1010,82 +1098,27 @@ __device__ void band_lines(const Geometry& G, const LevelArgs& a, int l, int lay
       const int32_t j0 = uniform(bk[b0]), j1 = uniform(bk[b1]);
       for (int32_t J = j0; J < j1; J += kWave) {
         const int32_t jl = (J + lane < j1) ? J + lane : j1 - 1;
-        const Rec L = rec[jl];
+        const Rec L = load_rec(rec, jl);
         const int ls = L.s;
         const int cls = (l >= ls) ? 1 : 2;
         const bool ok = (J + lane < j1) && (mask & cls);
         const double P = (double)L.k0 + (double)L.frac + sq;
-        const int64_t u = (int64_t)floor(P * inv_r1 + eps);
-        // T_(l+1) at level-(l+1) nodes u-2 .. u+2
-        R dd[5], T1[5];
-#pragma unroll
-        for (int i = 0; i < 5; ++i) {
-          dd[i] = R((int32_t)((u - 2 + i) * r1) - L.k0) - R(L.frac);
-          const R adi = fabs(dd[i]);
-          const bool act = ok && adi <= cfine && !(l + 1 > ls && adi < b_cur);
-          const R g = g_band<R, COUNT, SURR>(dd[i], L, sp, jl, G, cfine, act, cnt, a, chi_mode, cc0, cc1);
-          T1[i] = act ? g : R(0);
-        }
-        // segments of lanes with equal u (u is non-decreasing over lanes)
-        const int32_t u32 = (int32_t)u;
-        uint32_t same = 0;
-#pragma unroll
-        for (int st = 0; st < 6; ++st) {
-          const int32_t uo = __shfl_up(u32, 1 << st);
-          if (lane >= (1 << st) && uo == u32) same |= 1u << st;
-        }
-        const int32_t un = __shfl_down(u32, 1);
-        const bool seg_end = lane == 63 || un != u32;
-        // at fine levels lines are sparse: no two lanes share a centre and the merge is skipped
-        const bool merge = __builtin_amdgcn_ballot_w64(same != 0u) != 0;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          const int64_t kc = u - 1 + c;
-          const R d0 = dd[c], d2 = dd[c + 2];
-          const R lo = (d0 * d2 <= R(0)) ? R(0) : fmin(fabs(d0), fabs(d2));
-          const R hi = fmax(fabs(d0), fabs(d2));
-          bool strad;
-          if (iso) {
-            strad = ok && rq >= lo && rq <= hi;
-          } else {
-            R qmin = R(INFINITY);
-#pragma unroll
-            for (int i = 0; i < kMaxJumps; ++i)
-              if ((jm[i] & cls) && jq[i] >= lo && jq[i] <= hi) qmin = fmin(qmin, jq[i]);
-            strad = ok && qmin == rq;
-          }
-#pragma unroll
-          for (int jj = -RHO / 2 + 1; jj <= RHO / 2; ++jj) {
-            if (jj == 0) continue;
-            const int64_t m = kc * RHO + jj;
-            const R d = R((int32_t)(m * rl) - L.k0) - R(L.frac);
-            const bool side_ok = side == 0 ? d > R(0) : !(d > R(0));
-            const bool own = m >= m_a && m <= m_b;
-            const bool use = strad && own && side_ok;
-            const R ad = fabs(d);
-            const R rlo = (l == ls) ? R(0) : b_prev;
-            const bool in_reg = ls <= l && ad >= rlo && ad < b_cur && ad <= cfine;
-            const bool tl = ad <= cfine && !(l > ls && ad < b_prev);
-            const bool need = use && tl && !in_reg;
-            R gl = R(0);
-            if (__builtin_amdgcn_ballot_w64(need))
-              gl = g_band<R, COUNT, SURR>(d, L, sp, jl, G, cfine, need, cnt, a, chi_mode, cc0, cc1);
-            const double tt = (double)jj / (double)RHO;
-            const R v0 = (need ? gl : R(0)) -
-                         (R(0.5 * tt * (tt - 1.0)) * T1[c] + R(1.0 - tt * tt) * T1[c + 1] +
-                          R(0.5 * tt * (tt + 1.0)) * T1[c + 2]);
-            R v = use ? v0 : R(0);
-            if (merge) {
-#pragma unroll
-              for (int st = 0; st < 6; ++st) {
-                const R vo = __shfl_up(v, 1 << st);
-                if (same & (1u << st)) v += vo;
-              }
-            }
-            if (seg_end && own) lds_acc[m - base] += v;
-            if (COUNT && use) { n_band++; if (!in_reg) n_used++; }
-          }
-        }
+        // Candidate centres: kc in [P/r1 - 1, P/r1 + 1].  Unless P/r1 lies
+        // within single-precision rounding of an integer (eps), these are the
+        // two centres floor(P/r1) and floor(P/r1) + 1; otherwise three, from
+        // floor(P/r1 + eps) - 1.  The wavefront takes the wider set when any
+        // of its used lanes needs it.
+        const double Pr = P * inv_r1;
+        const double fl = floor(Pr);
+        const bool edge = (Pr - fl) < eps || (Pr - fl) > 1.0 - eps;
+        if (__builtin_amdgcn_ballot_w64(ok && edge))
+          band_chunk<R, COUNT, RHO, SURR, 3>(L, jl, ls, cls, ok, (int64_t)floor(Pr + eps) - 1, side, rq, iso, iv,
+                                             chi_mode, cc0, cc1, l, rl, r1, cfine, b_prev, b_cur, m_a, m_b, base, sp,
+                                             G, a, lds_acc, cnt, n_used, n_band);
+        else
+          band_chunk<R, COUNT, RHO, SURR, 2>(L, jl, ls, cls, ok, (int64_t)fl, side, rq, iso, iv, chi_mode, cc0,
+                                             cc1, l, rl, r1, cfine, b_prev, b_cur, m_a, m_b, base, sp, G, a, lds_acc,
+                                             cnt, n_used, n_band);
         if (COUNT && lane == 0) cnt.band_iters++;
       }
     }

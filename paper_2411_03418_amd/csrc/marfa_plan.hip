@@ -419,8 +419,9 @@ static marfa_status validate(const marfa_lines* L, const marfa_layer* lay, int32
   if (L->n > 0 && (!L->nu0 || !L->S296 || !L->gamma_air || !L->gamma_self || !L->E_lower || !L->n_air ||
                    !L->delta_air))
     return fail(MARFA_E_INVALID, "null line array");
-  // line indices within a layer are 32-bit
-  if (L->n > ((int64_t)1 << 31) - 1) return fail(MARFA_E_INVALID, "too many lines (at most 2^31 - 1)");
+  // a layer's line records (64 bytes in double precision) stay under 4 GiB:
+  // kernels address them with 32-bit byte offsets
+  if (L->n > ((int64_t)1 << 26) - 1) return fail(MARFA_E_INVALID, "too many lines (at most 2^26 - 1)");
   if (!(L->molar_mass_g > 0.0) || !std::isfinite(L->molar_mass_g)) return fail(MARFA_E_INVALID, "molar mass");
   for (int64_t j = 0; j < L->n; ++j)
     if (!std::isfinite(L->nu0[j]) || L->nu0[j] < 0.0) return fail(MARFA_E_INVALID, "line %lld: bad nu0", (long long)j);
