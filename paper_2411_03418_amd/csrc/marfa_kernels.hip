@@ -684,11 +684,18 @@ __device__ __forceinline__ void scan_region(const typename RecOf<R>::T* __restri
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 // Line record j of a layer through a 32-bit byte offset from the layer's
-// base (plans keep a layer's records under 4 GiB), so the load takes the
-// scalar-base + vector-offset form.
+// base in the global address space (plans keep a layer's records under
+// 4 GiB), so the load can take the scalar-base + vector-offset form.
 template <typename Rec>
 __device__ __forceinline__ Rec load_rec(const Rec* __restrict__ rec, int32_t j) {
-  return rec[j];
+#if __HIP_DEVICE_COMPILE__
+  typedef const __attribute__((address_space(1))) char gchar;
+  typedef const __attribute__((address_space(1))) Rec grec;
+  gchar* base = (gchar*)rec;
+  return *(grec*)(base + (uint32_t)j * (uint32_t)sizeof(Rec));
+#else
+  return rec[j];   // host pass: parsed, never run
+#endif
 }
 
 // Fast region scan over one window: SGN = +1 / -1 one side of the annulus
