@@ -28,6 +28,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP32_VALU_TFLOPS = 157.3   # MI355X published FP32 vector peak
+PEAK_BF16_MFMA_TFLOPS = 2500.0  # MI355X published dense BF16 matrix peak
+# algorithmic flops of one network evaluation: 3->64 (2*3*64 + 64), three
+# 64->64 layers (2*64*64 each), 64->1 (2*64); the split-BF16 activations run
+# the hidden layers twice on the matrix cores, which is not counted here
+FLOP_MLP = 2 * 3 * 64 + 64 + 3 * 2 * 64 * 64 + 2 * 64
 
 # Algorithmic flops per unit of work, counted from the kernel source
 # (FMA = 2, add / mul = 1, rcp / exp2 = 1; compares, selects and integer
@@ -122,6 +127,8 @@ def surrogate_leg(args):
     plan = marfa.Plan(lines, layers, device=0, **req)
     out = torch.empty((plan.n_layers, plan.points), dtype=torch.float32, device="cuda:0")
     plan.tune(out=out)
+    st = plan.count()
+    evals = st["pairs_wing"] + st["pairs_core"]   # shape evaluations, region and band passes
     ms_plain = timed_steps(plan, out, 3, 1)
     plain = out.clone()
     plan.set_surrogate(S)
@@ -133,7 +140,12 @@ def surrogate_leg(args):
           file=sys.stderr, flush=True)
     plan.close()
     S.close()
+    mfma_tflops = evals * FLOP_MLP / (t["level_ms"] * 1e-3) / 1e12
     return dict(workload="pt100_200k", value=points / (ms_surr * 1e-3), unit="points/s", ms_per_step=ms_surr,
+                roofline={"bound": "mfma", "achieved": mfma_tflops, "peak": PEAK_BF16_MFMA_TFLOPS, "unit": "TFLOP/s",
+                          "frac": mfma_tflops / PEAK_BF16_MFMA_TFLOPS, "kernel": "k_level (learned shape)",
+                          "evaluations": int(evals), "flop_per_evaluation": FLOP_MLP,
+                          "note": "VALU-bound in practice: SiLU costs two quarter-rate transcendentals per activation"},
                 steps=args.surrogate_steps, level_ms=t["level_ms"], plain_ms_per_step=ms_plain,
                 speed_vs_plain=ms_plain / ms_surr, max_rel_dev_from_plain=dev,
                 train=dict(ms=rep["ms"], steps=rep["steps"], val_max_abs_t=rep["val_max_abs"],

@@ -188,6 +188,40 @@ def test_small_cutoff_node_major_band(fp64):
     assert eg < (1e-12 if fp64 else FP32_VS_GRID)
 
 
+@pytest.mark.parametrize("fp64", [False, True])
+def test_long_cutoff_all_tonkov_pieces(fp64):
+    # cut-off 400 cm^-1: the 150 and 300 cm^-1 breaks of chi are jumps of the
+    # coarse levels and windows span several chi pieces
+    lines = synth.make_lines(1500, 600.0, 1400.0, 37, shift=True)
+    lay = [2.0, 300.0, 2.0, 0.0]
+    req = dict(nu_begin=995.0, nu_end=1005.0, cutoff=400.0, chi="tonkov")
+    got = run(lines, [lay], fp64=fp64, **req)[0]
+    o = _oreq(req)
+    ref_d = O.direct(lines, lay, all_nodes(req), threads=THREADS, **o)
+    ref_g = O.grid(lines, lay, threads=THREADS, **o)
+    eg, ed = rel_err(got, ref_g), rel_err(got, ref_d)
+    print(f"cut-off 400 fp64={fp64}: vs grid {eg:.2e} vs direct {ed:.2e}")
+    assert ed < 1e-4
+    assert eg < (1e-12 if fp64 else FP32_VS_GRID)
+
+
+@pytest.mark.parametrize("fp64", [False, True])
+def test_region_edge_next_to_chi_break(fp64):
+    # R = 47 puts b_5 = 2.94 cm^-1 within one stencil hull of the 3 cm^-1 chi
+    # break: a hull can straddle both jumps and only the smaller one corrects
+    lines = synth.make_lines(800, 960.0, 1050.0, 38, shift=True)
+    lay = [0.05, 220.0, 0.05, 0.0]
+    req = dict(nu_begin=1000.0, nu_end=1010.0, cutoff=40.0, chi="tonkov", R=47)
+    got = run(lines, [lay], fp64=fp64, **req)[0]
+    o = _oreq(req)
+    ref_d = O.direct(lines, lay, all_nodes(req), threads=THREADS, **o)
+    ref_g = O.grid(lines, lay, threads=THREADS, **o)
+    eg, ed = rel_err(got, ref_g), rel_err(got, ref_d)
+    print(f"R=47 fp64={fp64}: vs grid {eg:.2e} vs direct {ed:.2e}")
+    assert ed < 1e-4
+    assert eg < (1e-12 if fp64 else FP32_VS_GRID)
+
+
 def test_absorption_coefficient_output():
     lines = synth.make_lines(300, 980.0, 1030.0, 32)
     lay = [0.8, 280.0, 0.2, 0.0]
