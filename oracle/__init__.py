@@ -38,7 +38,8 @@ class _Layer(C.Structure):
 class _Request(C.Structure):
     _fields_ = [("nu_begin", C.c_double), ("nu_end", C.c_double), ("cutoff", C.c_double),
                 ("shape", C.c_int32), ("chi", C.c_int32), ("out_kind", C.c_int32),
-                ("level_table", C.c_int32), ("prune_rel", C.c_double), ("R", C.c_double)]
+                ("level_table", C.c_int32), ("prune_rel", C.c_double), ("R", C.c_double),
+                ("stencil", C.c_int32)]
 
 
 class _State(C.Structure):
@@ -102,9 +103,9 @@ def _layer(lay):
 
 
 def _request(nu_begin, nu_end, cutoff, shape=0, chi=0, out_kind=0, level_table=0, prune=0.0,
-             R=48.0):
+             R=48.0, stencil=3):
     return _Request(float(nu_begin), float(nu_end), float(cutoff), int(shape), int(chi),
-                    int(out_kind), int(level_table), float(prune), float(R))
+                    int(out_kind), int(level_table), float(prune), float(R), int(stencil))
 
 
 def dawson(x: float) -> float:

@@ -215,6 +215,7 @@ static int validate(const orc_lines* L, const orc_layer* lay, const orc_request*
   if (floor(rq->nu_end * 2048.0) != rq->nu_end * 2048.0) return -1;
   if (!(rq->cutoff > 0.0) || !finite_d(rq->cutoff)) return -1;
   if (!(rq->R >= 4.0) || !finite_d(rq->R)) return -1;
+  if (rq->stencil != 0 && rq->stencil != 3 && rq->stencil != 5) return -1;
   if (!(lay->T_K > 0.0) || !(lay->p_atm >= 0.0) || !(lay->p_self_atm >= 0.0) ||
       lay->p_self_atm > lay->p_atm || !finite_d(lay->T_K) || !finite_d(lay->p_atm))
     return -1;
@@ -365,16 +366,18 @@ int orc_direct(const orc_lines* L, const orc_layer* lay, const orc_request* rq,
 /* (its inner edge, the cut-off, chi breakpoints); elsewhere D_l is the  */
 /* interpolation error of a smooth function and is dropped.              */
 /* Cascade: A_10 = sum D_10, A_l = sum D_l + P(A_(l+1)), sigma = A_0.   */
-/* P is the 3-point Lagrange interpolation on the nearest coarse node    */
-/* (ties to the lower one), injection at coinciding nodes.              */
+/* P is the 3-point (or 5-point) Lagrange interpolation centred on the  */
+/* nearest coarse node (ties to the lower one), injection at coinciding  */
+/* nodes; Section 2.4 names both orders.                                 */
 /* ------------------------------------------------------------------ */
 #define NLEV 11
 
 typedef struct {
+  int ns;                   /* stencil points, 3 or 5 */
   int64_t r[NLEV];          /* level step in finest steps */
   double h[NLEV];           /* level step [cm^-1] */
   double b[NLEV];           /* b_l = R h_(l+1), l = 0..9 */
-  double B[NLEV];           /* band half-width 2 h_(l+1) */
+  double B[NLEV];           /* band half-width (ns+1)/2 h_(l+1): hull reach from a node */
   int64_t lo[NLEV], hi[NLEV];
   double* A[NLEV];
   double c;
@@ -388,6 +391,8 @@ static int64_t floor_div(int64_t a, int64_t b) {
 }
 
 static void make_geom(const orc_request* rq, grid_geom* G) {
+  G->ns = rq->stencil == 5 ? 5 : 3;
+  const int half = G->ns / 2;
   for (int l = 0; l < NLEV; ++l) {
     if (rq->level_table == 1) G->r[l] = (int64_t)1 << l;
     else G->r[l] = l == 0 ? 1 : ((int64_t)1 << (l + 1));
@@ -395,7 +400,7 @@ static void make_geom(const orc_request* rq, grid_geom* G) {
   }
   for (int l = 0; l < NLEV - 1; ++l) {
     G->b[l] = rq->R * G->h[l + 1];
-    G->B[l] = 2.0 * G->h[l + 1];
+    G->B[l] = (double)(half + 1) * G->h[l + 1];
   }
   G->b[NLEV - 1] = INFINITY;
   G->B[NLEV - 1] = 0.0;
@@ -403,8 +408,8 @@ static void make_geom(const orc_request* rq, grid_geom* G) {
   G->hi[0] = (int64_t)llround(rq->nu_end * 2048.0);
   for (int l = 0; l < NLEV - 1; ++l) {
     int64_t rho = G->r[l + 1] / G->r[l];
-    G->lo[l + 1] = floor_div(G->lo[l], rho) - 1;
-    G->hi[l + 1] = -floor_div(-G->hi[l], rho) + 1;
+    G->lo[l + 1] = floor_div(G->lo[l], rho) - half;
+    G->hi[l + 1] = -floor_div(-G->hi[l], rho) + half;
   }
   G->c = rq->cutoff;
   G->shape = rq->shape;
@@ -461,7 +466,11 @@ static int jumps_of(const grid_geom* G, const gline* ln, int l, double* q) {
   return n;
 }
 
-/* 3-point stencil of level-l node m on level l+1: nodes k[0..2], weights w */
+/* Stencil of level-l node m on level l+1: the ns coarse nodes centred on
+ * the nearest one kc (a tie goes to the lower), k[i] = kc - ns/2 + i, with
+ * Lagrange weights w_i(t) = prod_{j != i} (t - j') / (i' - j') over the
+ * offsets i', j' in -ns/2 .. ns/2, t = u - kc; one node with weight 1 where
+ * m coincides with a coarse node. */
 static int stencil(const grid_geom* G, int l, int64_t m, int64_t* k, double* w) {
   int64_t rho = G->r[l + 1] / G->r[l];
   int64_t q = floor_div(m, rho);
@@ -473,21 +482,26 @@ static int stencil(const grid_geom* G, int l, int64_t m, int64_t* k, double* w) 
   double f = (double)rem / (double)rho, t;
   int64_t kc;
   if (f <= 0.5) { kc = q; t = f; } else { kc = q + 1; t = f - 1.0; }
-  k[0] = kc - 1; w[0] = 0.5 * t * (t - 1.0);
-  k[1] = kc;     w[1] = 1.0 - t * t;
-  k[2] = kc + 1; w[2] = 0.5 * t * (t + 1.0);
-  return 3;
+  const int half = G->ns / 2;
+  for (int i = -half; i <= half; ++i) {
+    double v = 1.0;
+    for (int j = -half; j <= half; ++j)
+      if (j != i) v *= (t - j) / (double)(i - j);
+    k[i + half] = kc + i;
+    w[i + half] = v;
+  }
+  return G->ns;
 }
 
-/* Does the 3-point stencil of node m (level l) straddle a jump of T_(l+1)?
+/* Does the stencil of node m (level l) straddle a jump of T_(l+1)?
  * True when some jump point q lies in the closed |d| hull of the stencil's
  * coarse nodes; only there does interpolating T_(l+1) smear a jump. */
 static int straddles(const grid_geom* G, const gline* ln, int l, int64_t m, const double* q, int nq) {
-  int64_t k[3];
-  double w[3];
-  if (stencil(G, l, m, k, w) != 3) return 0;
+  int64_t k[5];
+  double w[5];
+  if (stencil(G, l, m, k, w) == 1) return 0;
   double d0 = (double)k[0] * G->h[l + 1] - ln->nu;
-  double d2 = (double)k[2] * G->h[l + 1] - ln->nu;
+  double d2 = (double)k[G->ns - 1] * G->h[l + 1] - ln->nu;
   double lo = (d0 * d2 <= 0.0) ? 0.0 : fmin(fabs(d0), fabs(d2));
   double hi = fmax(fabs(d0), fabs(d2));
   for (int i = 0; i < nq; ++i)
@@ -500,8 +514,8 @@ static double D_at(const grid_geom* G, const gline* ln, int l, int64_t m) {
   double d = (double)m * G->h[l] - ln->nu;
   double v = T_of(G, ln, l, d);
   if (l < NLEV - 1) {
-    int64_t k[3];
-    double w[3];
+    int64_t k[5];
+    double w[5];
     int ns = stencil(G, l, m, k, w);
     for (int i = 0; i < ns; ++i)
       v -= w[i] * T_of(G, ln, l + 1, (double)k[i] * G->h[l + 1] - ln->nu);
@@ -621,8 +635,8 @@ int orc_grid(const orc_lines* L, const orc_layer* lay, const orc_request* rq,
     /* cascade, coarse to fine */
     for (int l = NLEV - 2; l >= 0; --l) {
       for (int64_t m = G.lo[l]; m <= G.hi[l]; ++m) {
-        int64_t k[3];
-        double w[3];
+        int64_t k[5];
+        double w[5];
         int ns = stencil(&G, l, m, k, w);
         double v = 0.0;
         for (int i = 0; i < ns; ++i) v += w[i] * G.A[l + 1][k[i] - G.lo[l + 1]];

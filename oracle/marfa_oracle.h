@@ -57,6 +57,7 @@ typedef struct {
   int32_t level_table;      /* 0: steps 2^-11, 2^-9 .. 1; 1: 2^-11 .. 2^-1 */
   double prune_rel;         /* keep S >= prune_rel * max S; 0 keeps all */
   double R;                 /* region multiple of the level step */
+  int32_t stencil;          /* interpolation points between levels: 3 (default, 0 = 3) or 5 */
 } orc_request;
 
 typedef struct {

@@ -424,3 +424,43 @@ def test_mlp_forward_hand_network():
     X = np.array([[0.7]])
     z = 2.0 * 0.7 - 0.5
     assert abs(O.mlp_forward(widths, P, X)[0, 0] - (3.0 * z / (1 + math.exp(-z)) + 0.25)) < 1e-15
+
+
+@pytest.mark.parametrize("case", [
+    dict(nu0=1005.0, gamma=0.075),
+    dict(nu0=1005.00013, gamma=0.075),
+    dict(nu0=1005.3, gamma=0.075, chi=1, c=125.0),
+    dict(nu0=1002.1234, gamma=0.3, c=4.0, chi=1),
+    dict(nu0=1007.7, gamma=0.09, p=10.0),
+    dict(nu0=1010.0, gamma=0.06, p=0.2),
+    dict(nu0=1005.0, gamma=0.06, p=0.2, shape=2),
+    dict(nu0=1004.2, gamma=0.06, p=0.4, lt=1),
+])
+def test_grid_5point_matches_definition_one_line(case):
+    """Section 2.4 names 3- and 5-point interpolation; with 5 points the
+    smooth-part error falls like R^-5, so R = 12 suffices for 3e-5."""
+    c = case.get("c", 25.0)
+    L, lay = _one_line(case["nu0"], case["gamma"], p=case.get("p", 1.0))
+    err = _grid_vs_direct(L, lay, nu_begin=1000.0, nu_end=1010.0, cutoff=c, chi=case.get("chi", 0),
+                          shape=case.get("shape", 0), level_table=case.get("lt", 0), R=12.0, stencil=5)
+    assert err < 3e-5, err
+
+
+def test_grid_5point_error_falls_faster_than_3point():
+    # brute force on a 100-line list: at equal R the 5-point scheme is far
+    # closer to the definition, and its error falls ~R^-5 (R 12 -> 24: > 16x)
+    L = synth.make_lines(100, 990.0, 1020.0, 13, shift=True)
+    lay = (0.1, 250.0, 0.1, 0.0)
+    kw = dict(nu_begin=1000.0, nu_end=1010.0, cutoff=25.0, chi=1)
+    e3 = _grid_vs_direct(L, lay, R=12.0, stencil=3, **kw)
+    e5 = _grid_vs_direct(L, lay, R=12.0, stencil=5, **kw)
+    e5b = _grid_vs_direct(L, lay, R=24.0, stencil=5, **kw)
+    assert e5 < 3e-5 and e5 < e3 / 10, (e3, e5)
+    assert e5b < e5 / 16, (e5, e5b)
+
+
+def test_grid_5point_exact_on_a_line_pair_symmetric():
+    # an unshifted line centred on a node gives a spectrum symmetric about it
+    L, lay = _one_line(1005.0, 0.07, p=0.3)
+    g = O.grid(L, lay, nu_begin=1000.0, nu_end=1010.0, cutoff=25.0, R=12.0, stencil=5)
+    assert np.allclose(g, g[::-1], rtol=5e-5, atol=0)
