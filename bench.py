@@ -41,6 +41,7 @@ FLOP_WING = 18        # d, d^2+g^2, 1/., e, U, 1+eU, A Q sum, chi = exp2(c0+c1 d
 FLOP_TERM = 6         # one more term of the asymptotic wing series
 FLOP_CORE = 2 * 230   # rational core in FP64 (27 complex Horner steps + setup); FP64 counts double
 FLOP_BAND = 6         # three stencil weights times coarse values, per band pair
+STENCIL5_R = 12      # R for the 5-point stencil: about 1.6e-5 from the direct sum in one-line sweeps
 
 
 def profiled_traffic(workload):
@@ -115,6 +116,31 @@ def rel_dev(a, b):
     return worst
 
 
+def stencil5_leg(lines, layers, req, plain, steps):
+    """The same table with the 5-point interpolation stencil at a smaller R."""
+    import torch
+    from paper_2411_03418_amd import marfa
+    plan = marfa.Plan(lines, layers, device=0, stencil=5, R=STENCIL5_R, **req)
+    out = torch.empty((plan.n_layers, plan.points), dtype=torch.float32, device="cuda:0")
+    tiles = plan.tune(out=out)
+    st = plan.count()
+    ms = timed_steps(plan, out, steps, 1)
+    lv = []
+    for _ in range(steps):
+        _, t = plan.execute_timed(out=out)
+        lv.append(t["level_ms"])
+    dev = rel_dev(plain, out)
+    points = plan.points * plan.n_layers
+    print(f"[bench] 5-point R={STENCIL5_R}: {ms:.1f} ms/step, level {np.mean(lv):.1f} ms; max dev from 3-point "
+          f"{dev:.2e}", file=sys.stderr, flush=True)
+    plan.close()
+    del out
+    torch.cuda.empty_cache()
+    return dict(value=points / (ms * 1e-3), unit="points/s", ms_per_step=ms, level_ms=float(np.mean(lv)),
+                steps=steps, stencil=5, R=STENCIL5_R, pairs=int(sum(st["pairs_level"])),
+                band_pairs=int(st["pairs_band"]), max_rel_dev_from_3point=dev, tiles=tiles)
+
+
 def surrogate_leg(args):
     import torch
     from paper_2411_03418_amd import marfa, synth
@@ -163,6 +189,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--no-stencil5", action="store_true", help="skip the 5-point stencil leg")
     ap.add_argument("--surrogate-steps", type=int, default=2)
     ap.add_argument("--no-tune", action="store_true", help="keep the density-based tiles")
     ap.add_argument("--tiles", default=None, metavar="JSON",
@@ -220,6 +247,9 @@ def main():
     print(f"[bench] {ms:.2f} ms/step; level {level_ms:.2f} ms, prep {np.mean(prep):.2f} ms, "
           f"cascade {np.mean(cas):.2f} ms", file=sys.stderr, flush=True)
     plan.close()
+    s5 = None
+    if not args.no_stencil5:
+        s5 = stencil5_leg(lines, layers, req, out, args.steps)
     del out
     torch.cuda.empty_cache()
 
@@ -253,6 +283,8 @@ def main():
                   "wing_terms": int(st["wing_terms"])},
         "tiles": tiles,
     }
+    if s5 is not None:
+        line["stencil5"] = s5
     if not args.no_surrogate:
         line["surrogate"] = surrogate_leg(args)
     if not args.no_cpu_baseline:

@@ -38,7 +38,8 @@ typedef enum {
   MARFA_E_NOMEM = -2,        /* host or device allocation failed */
   MARFA_E_DEVICE = -3,       /* HIP error, or no usable gfx950 device */
   MARFA_E_UNSUPPORTED = -4,  /* valid but not available (e.g. untrained surrogate) */
-  MARFA_E_STATE = -5         /* call out of order */
+  MARFA_E_STATE = -5,        /* call out of order */
+  MARFA_E_IO = -6            /* a file could not be opened or written */
 } marfa_status;
 
 typedef enum { MARFA_SHAPE_VOIGT = 0, MARFA_SHAPE_LORENTZ = 1, MARFA_SHAPE_DOPPLER = 2 } marfa_shape;
@@ -75,7 +76,8 @@ typedef struct {
  * level_table 0 (steps 2^-11, 2^-9, ..., 1 cm^-1) or 1 (2^-11, ..., 2^-1);
  * prune_rel in [0, 1): lines with S(T) < prune_rel * max_j S_j(T) are dropped
  * per layer (max over the whole list); fp64 = 1 runs the device path in double
- * precision (output then FP64).  Zero-initialise reserved fields. */
+ * precision (output then FP64); stencil 0, 3 or 5.  Zero-initialise reserved
+ * fields. */
 typedef struct {
   double nu_begin, nu_end;
   double cutoff;
@@ -89,7 +91,10 @@ typedef struct {
   double R;
   int32_t level_table;
   int32_t fp64;
-  int32_t reserved[4];
+  int32_t stencil;            /* interpolation points between levels, 3 (0 = 3) or 5
+                                 (Section 2.4 names both; 5 points reach the 3-point
+                                 accuracy of R = 48 at R = 10-12) */
+  int32_t reserved[3];
 } marfa_request;
 
 typedef struct marfa_plan marfa_plan;
@@ -278,6 +283,31 @@ void marfa_surrogate_destroy(marfa_surrogate* s);
  * MARFA_E_INVALID (mismatch), MARFA_E_UNSUPPORTED (untrained network, a
  * cut-off under two coarsest steps). */
 marfa_status marfa_plan_set_surrogate(marfa_plan* plan, const marfa_surrogate* s);
+
+/* PT-table record file (Appendix A).  One binary direct-access file per layer
+ * holds records of MARFA_PTBIN_NT = 20481 single-precision values: record r
+ * (r >= 1; r = int(nu / 10) for a wavenumber nu inside it) holds the spectrum
+ * at nu = 10 r + i / 2048 cm^-1, i = 0 .. 20480 (both interval ends; the last
+ * value of record r is the first of record r + 1), at byte offset
+ * (r - 1) * 20481 * 4, little-endian.
+ *
+ * marfa_ptbin_write writes every record whose whole interval [10 r, 10 r + 10]
+ * lies inside the n_points lattice values starting at nu_begin (values[i] is the
+ * spectrum at nu_begin + i / 2048); other records of the file are left as they
+ * are (zero-filled where the file grows past them).  values may be host memory
+ * (values_on_device = 0) or device memory on the current device, e.g. a row of
+ * marfa_execute's output (values_on_device = 1: copied to the host on
+ * hip_stream, which the call then synchronizes).  flags: MARFA_PTBIN_TRUNCATE
+ * empties an existing file first.  *records_written (may be NULL) receives the
+ * number of records written; zero when no whole interval is covered.
+ * Errors: MARFA_E_INVALID (NULL path or values with n_points > 0, n_points < 0,
+ * nu_begin negative or not on the 2^-11 cm^-1 lattice, unknown flags),
+ * MARFA_E_IO (open or write failed), MARFA_E_DEVICE (copy failed). */
+#define MARFA_PTBIN_NT 20481
+#define MARFA_PTBIN_TRUNCATE 1
+marfa_status marfa_ptbin_write(const char* path, const float* values, int64_t n_points, double nu_begin,
+                               int32_t values_on_device, void* hip_stream, int32_t flags,
+                               int32_t* records_written);
 
 const char* marfa_status_string(int32_t status);
 /* Copy the calling thread's last error text into buf (NUL-terminated). */

@@ -6,7 +6,7 @@ import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = ["csrc/marfa_kernels.hip", "csrc/marfa_plan.hip", "csrc/marfa_surrogate.hip"]
+SOURCES = ["csrc/marfa_kernels.hip", "csrc/marfa_plan.hip", "csrc/marfa_surrogate.hip", "csrc/marfa_io.hip"]
 OUT = os.path.join(HERE, "libmarfa.so")
 
 FLAGS = [

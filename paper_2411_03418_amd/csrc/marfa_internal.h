@@ -29,12 +29,13 @@ struct Geometry {
   int64_t aoff[kLevels];     // offset of level l >= 1 in a layer's level array
   int64_t a_total;           // level-array length per layer (levels 1..10)
   double b[kLevels];         // region boundary b_l = R r_(l+1), fine units (l < 10)
-  double hb[kLevels];        // band reach 1.5 r_(l+1) + 1, fine units (l < 10)
+  double hb[kLevels];        // band reach (ns/2 + 1/2) r_(l+1) + 1, fine units (l < 10)
   double c_fine;             // cut-off in fine units
   // jump points of T_(l+1) for lines starting at or below l (q1) and above l (q2)
   double q1[kLevels][kMaxJumps], q2[kLevels][kMaxJumps];
   int32_t nq1[kLevels], nq2[kLevels];
   int32_t shape, chi, out_kind, fp64;
+  int32_t ns, pad_ns;        // stencil points between levels (3 or 5)
   int32_t nbucket;           // buckets of the per-layer line index (kBucketPerCm per cm^-1)
   int32_t pad;
   double bucket_origin;      // wavenumber of bucket 0 [cm^-1] (below every shifted centre)
@@ -70,7 +71,7 @@ struct IntervalSet {
   // (bit 0: start level <= l, bit 1: start level > l)
   double jq[kMaxJumps];
   int32_t jmask[kMaxJumps];
-  // line-major band pass: usable when every jump exceeds 2 r_(l+1) + 2 (no
+  // line-major band pass: usable when every jump exceeds (ns - 1) r_(l+1) + 2 (no
   // stencil hull around a line centre can hold one) and rho is 2 or 4;
   // lc_eps widens the centre estimate past single-precision rounding of d
   int32_t lc_ok, pad_lc;

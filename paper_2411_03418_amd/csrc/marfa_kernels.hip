@@ -753,7 +753,25 @@ __device__ __forceinline__ int64_t bucket_of(double nu, const Geometry& G) {
   return b < 0 ? 0 : (b > G.nbucket ? G.nbucket : b);
 }
 
-// 3-point stencil of level-l node m on level l+1 (positions in fine units)
+// Lagrange weight of offset i (in -H..H) at t for the 2H+1 nodes -H..H
+template <int H>
+__host__ __device__ constexpr double lagrange_den(int i) {
+  double v = 1.0;
+  for (int j = -H; j <= H; ++j)
+    if (j != i) v *= (double)(i - j);
+  return v;
+}
+template <int H>
+__host__ __device__ __forceinline__ constexpr double lagrange_w(int i, double t) {
+  double v = 1.0;
+  for (int j = -H; j <= H; ++j)
+    if (j != i) v *= (t - j);
+  return v * (1.0 / lagrange_den<H>(i));
+}
+
+// Stencil of level-l node m on level l+1 (positions in fine units): G.ns
+// coarse nodes centred on the nearest one (a tie goes to the lower); one
+// node where m coincides with a coarse node
 template <typename R>
 __device__ __forceinline__ int stencil_of(const Geometry& G, int l, int64_t m, int32_t* Xs, R* ws) {
   const int64_t rl = G.r[l];
@@ -761,19 +779,21 @@ __device__ __forceinline__ int stencil_of(const Geometry& G, int l, int64_t m, i
   const int64_t q = floor_div(m, rho);
   const int64_t rem = m - q * rho;
   const int64_t r1 = G.r[l + 1];
-  if (rem == 0) {
-    Xs[0] = Xs[1] = Xs[2] = (int32_t)(q * r1);
-    ws[0] = R(1); ws[1] = ws[2] = R(0);
-    return 1;
-  }
+  // at rem == 0 the stencil at t = 0 has weights (.., 0, 1, 0, ..) exactly
   const double f = (double)rem / (double)rho;
   double tt;
   int64_t kc;
   if (f <= 0.5) { kc = q; tt = f; } else { kc = q + 1; tt = f - 1.0; }
-  Xs[0] = (int32_t)((kc - 1) * r1); ws[0] = R(0.5 * tt * (tt - 1.0));
-  Xs[1] = (int32_t)(kc * r1);       ws[1] = R(1.0 - tt * tt);
-  Xs[2] = (int32_t)((kc + 1) * r1); ws[2] = R(0.5 * tt * (tt + 1.0));
-  return 3;
+  // both stencils, selected per slot (the 3-point one padded with zero weights)
+  const bool five = G.ns == 5;
+  const int64_t k0 = five ? kc - 2 : kc - 1;
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    Xs[i] = (int32_t)((k0 + (i < 3 || five ? i : 2)) * r1);
+    const double w3 = i < 3 ? lagrange_w<1>(i - 1, tt) : 0.0;
+    ws[i] = R(five ? lagrange_w<2>(i - 2, tt) : w3);
+  }
+  return rem == 0 ? 1 : G.ns;
 }
 
 // Region pass of one wavefront tile: nw = 2^lnw consecutive nodes of level l;
@@ -803,7 +823,11 @@ __device__ __forceinline__ void region_tile(const Geometry& G, const LevelArgs& 
   const int32_t X = (int32_t)(m * rl);
   const int64_t Xf = (G.lo[l] + rel0) * rl;
   const int64_t Xl = Xf + (int64_t)(nw - 1) * rl;
-  // line ranges of every (window, side), fetched in one round
+  // line ranges of every (window, side), fetched in one round.  Region
+  // membership is decided on the single-precision distance, which can round
+  // onto a window edge from outside; one fine unit of margin keeps such
+  // lines in the scan, where the membership test decides.
+  constexpr double kEdge = 1.0;
   const int n_iv = uniform(iv->n_iv);
   int nws = 0;
   int my_bucket = 0;
@@ -812,9 +836,9 @@ __device__ __forceinline__ void region_tile(const Geometry& G, const LevelArgs& 
     const int nside = (ia == 0.0) ? 1 : 2;
     for (int side = 0; side < nside; ++side, ++nws) {
       double plo, phi;
-      if (nside == 1) { plo = (double)Xf - ib; phi = (double)Xl + ib; }
-      else if (side == 0) { plo = (double)Xf - ib; phi = (double)Xl - ia; }
-      else { plo = (double)Xf + ia; phi = (double)Xl + ib; }
+      if (nside == 1) { plo = (double)Xf - ib - kEdge; phi = (double)Xl + ib + kEdge; }
+      else if (side == 0) { plo = (double)Xf - ib - kEdge; phi = (double)Xl - ia + kEdge; }
+      else { plo = (double)Xf + ia - kEdge; phi = (double)Xl + ib + kEdge; }
       const int64_t blo = bucket_of(plo * kH0, G);
       const int64_t bhi = bucket_of(phi * kH0, G) + 1 > G.nbucket ? G.nbucket : bucket_of(phi * kH0, G) + 1;
       if (lane == 2 * nws) my_bucket = (int)blo;
@@ -908,10 +932,12 @@ __device__ __forceinline__ void band_group(const Geometry& G, const LevelArgs& a
   const R b_cur = R(G.b[l]);
   const double hb = G.hb[l];
   const int64_t m = G.lo[l] + rel0 + lane;
-  int32_t Xs[3];
-  R ws[3];
+  int32_t Xs[5];
+  R ws[5];
   const int ns = stencil_of<R>(G, l, m, Xs, ws);
-  const bool active = (rel0 + lane < G.n[l]) && (lane < group_left) && ns == 3;
+  const bool active = (rel0 + lane < G.n[l]) && (lane < group_left) && ns > 1;
+  const int nsg = G.ns;
+  const int32_t x_last = Xs[0] + (nsg - 1) * G.r[l + 1];   // stencil nodes are r_(l+1) apart
   if (!__any(active)) return;
   const int32_t X = (int32_t)(m * rl);
   const int nj = uniform(iv->n_jump);
@@ -936,7 +962,7 @@ __device__ __forceinline__ void band_group(const Geometry& G, const LevelArgs& a
           const int ls = L.s;
           const int cls = (l >= ls) ? 1 : 2;
           const R d0 = R(Xs[0] - L.k0) - R(L.frac);
-          const R d2 = R(Xs[2] - L.k0) - R(L.frac);
+          const R d2 = R(x_last - L.k0) - R(L.frac);
           const R lo = (d0 * d2 <= R(0)) ? R(0) : fmin(fabs(d0), fabs(d2));
           const R hi = fmax(fabs(d0), fabs(d2));
           // the smallest straddled jump of this line's class
@@ -952,11 +978,12 @@ __device__ __forceinline__ void band_group(const Geometry& G, const LevelArgs& a
             const bool tl = ad <= cfine && !(l > ls && ad < b_prev);
             R v = R(0);
             if (tl && !in_reg) v = g_any<R, COUNT>(d, L, sp, j, G, cfine, true, cnt);
-            const R d1 = R(Xs[1] - L.k0) - R(L.frac);
-            const R dv[3] = {d0, d1, d2};
-            for (int i = 0; i < 3; ++i) {
-              const R adi = fabs(dv[i]);
-              if (adi <= cfine && !(l + 1 > ls && adi < b_cur)) v -= ws[i] * g_any<R, COUNT>(dv[i], L, sp, j, G, cfine, true, cnt);
+#pragma unroll
+            for (int i = 0; i < 5; ++i) {
+              if (i >= nsg) break;
+              const R di = R(Xs[i] - L.k0) - R(L.frac);
+              const R adi = fabs(di);
+              if (adi <= cfine && !(l + 1 > ls && adi < b_cur)) v -= ws[i] * g_any<R, COUNT>(di, L, sp, j, G, cfine, true, cnt);
             }
             acc += v;
             if (COUNT) { n_band++; if (!in_reg) n_used++; }
@@ -970,8 +997,8 @@ __device__ __forceinline__ void band_group(const Geometry& G, const LevelArgs& a
 }
 
 // One chunk of 64 lines of the line-major band pass for one jump and side:
-// NC candidate centres from kc0 (see band_lines).
-template <typename R, bool COUNT, int RHO, bool SURR, int NC>
+// NC candidate centres from kc0 with NSP-point stencils (see band_lines).
+template <typename R, bool COUNT, int RHO, bool SURR, int NSP, int NC>
 __device__ __forceinline__ void band_chunk(const typename RecOf<R>::T& L, int32_t jl, int ls, int cls, bool ok,
                                            int64_t kc0, int side, R rq, bool iso, const IntervalSet* iv,
                                            int chi_mode, R cc0, R cc1, int l, int32_t rl, int32_t r1, R cfine,
@@ -979,11 +1006,12 @@ __device__ __forceinline__ void band_chunk(const typename RecOf<R>::T& L, int32_
                                            const R* __restrict__ sp, const Geometry& G, const LevelArgs& a,
                                            R* lds_acc, Counts& cnt, uint32_t& n_used, uint32_t& n_band) {
   const int lane = threadIdx.x & 63;
-  // T_(l+1) at level-(l+1) nodes kc0-1 .. kc0+NC
-  R dd[NC + 2], T1[NC + 2];
+  constexpr int H = NSP / 2;
+  // T_(l+1) at level-(l+1) nodes kc0-H .. kc0+NC-1+H
+  R dd[NC + 2 * H], T1[NC + 2 * H];
 #pragma unroll
-  for (int i = 0; i < NC + 2; ++i) {
-    dd[i] = R((int32_t)((kc0 - 1 + i) * r1) - L.k0) - R(L.frac);
+  for (int i = 0; i < NC + 2 * H; ++i) {
+    dd[i] = R((int32_t)((kc0 - H + i) * r1) - L.k0) - R(L.frac);
     const R adi = fabs(dd[i]);
     const bool act = ok && adi <= cfine && !(l + 1 > ls && adi < b_cur);
     const R g = g_band<R, COUNT, SURR>(dd[i], L, sp, jl, G, cfine, act, cnt, a, chi_mode, cc0, cc1);
@@ -1004,7 +1032,7 @@ __device__ __forceinline__ void band_chunk(const typename RecOf<R>::T& L, int32_
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
     const int64_t kc = kc0 + c;
-    const R d0 = dd[c], d2 = dd[c + 2];
+    const R d0 = dd[c], d2 = dd[c + 2 * H];
     const R lo = (d0 * d2 <= R(0)) ? R(0) : fmin(fabs(d0), fabs(d2));
     const R hi = fmax(fabs(d0), fabs(d2));
     bool strad;
@@ -1036,9 +1064,10 @@ __device__ __forceinline__ void band_chunk(const typename RecOf<R>::T& L, int32_
       if (__builtin_amdgcn_ballot_w64(need))
         gl = g_band<R, COUNT, SURR>(d, L, sp, jl, G, cfine, need, cnt, a, chi_mode, cc0, cc1);
       const double tt = (double)jj / (double)RHO;
-      const R v0 = (need ? gl : R(0)) -
-                   (R(0.5 * tt * (tt - 1.0)) * T1[c] + R(1.0 - tt * tt) * T1[c + 1] +
-                    R(0.5 * tt * (tt + 1.0)) * T1[c + 2]);
+      R interp = R(0);
+#pragma unroll
+      for (int i = 0; i < NSP; ++i) interp += R(lagrange_w<H>(i - H, tt)) * T1[c + i];
+      const R v0 = (need ? gl : R(0)) - interp;
       R v = use ? v0 : R(0);
       if (merge) {
 #pragma unroll
@@ -1057,17 +1086,18 @@ __device__ __forceinline__ void band_chunk(const typename RecOf<R>::T& L, int32_
 // Residual-band pass, line-major form, for one wavefront owning the item's
 // nodes [own_lo, own_hi).  For a jump q of T_(l+1) and a side, put the
 // line's jump point at P = nu~0 + q (nodes above the line) or nu~0 - q (nodes
-// below).  A level-l node's stencil hull [(kc-1) r1, (kc+1) r1] holds P only
-// if its nearest level-(l+1) centre kc is within one step of P / r1, so the
-// nodes to correct are the (RHO - 1) three-point nodes around each of two
-// (three at coarse nodes) centres.  Lane = line: T_(l+1) is evaluated once at
+// below).  A level-l node's stencil hull [(kc-H) r1, (kc+H) r1] (H = 1 for the
+// 3-point stencil, 2 for the 5-point one) holds P only if its nearest
+// level-(l+1) centre kc is within H steps of P / r1, so the nodes to correct
+// are the (RHO - 1) interpolated nodes around each of 2H (2H + 1 when P / r1
+// is an integer) centres.  Lane = line: T_(l+1) is evaluated once at
 // the level-(l+1) nodes around P, every candidate node gets D_l = T_l(d) - sum w_i T_(l+1)(d_i)
 // minus the region value (zero unless its hull straddles q and q is the
 // smallest straddled jump), and a segmented sum over lanes with the same
 // centre estimate -- non-decreasing in line order -- merges corrections of a
 // node before one lane adds them to its LDS slot.  Per slot there is one
 // writer and a fixed summation order, so results are reproducible.
-template <typename R, bool COUNT, int RHO, bool SURR>
+template <typename R, bool COUNT, int RHO, bool SURR, int NSP>
 __device__ __forceinline__ void band_lines(const Geometry& G, const LevelArgs& a, int l, int layer, int64_t item_first, int own_lo,
                            int own_hi, const IntervalSet* iv, R* lds_acc, Counts& cnt, uint32_t& n_used,
                            uint32_t& n_band) {
@@ -1097,8 +1127,9 @@ __device__ __forceinline__ void band_lines(const Geometry& G, const LevelArgs& a
     for (int side = 0; side < 2; ++side) {
       const double sq = side == 0 ? q : -q;
       // lines whose candidate nodes can reach [m_a, m_b]
-      const double plo = (double)(m_a * rl) - 2.5 * r1 - 2.0 - sq;
-      const double phi = (double)(m_b * rl) + 2.5 * r1 + 2.0 - sq;
+      const double marg = (NSP / 2 + 1.5) * r1 + 2.0;
+      const double plo = (double)(m_a * rl) - marg - sq;
+      const double phi = (double)(m_b * rl) + marg - sq;
       const int64_t b0 = bucket_of(plo * kH0, G);
       int64_t b1 = bucket_of(phi * kH0, G) + 1;
       b1 = b1 > G.nbucket ? G.nbucket : b1;
@@ -1110,22 +1141,24 @@ __device__ __forceinline__ void band_lines(const Geometry& G, const LevelArgs& a
         const int cls = (l >= ls) ? 1 : 2;
         const bool ok = (J + lane < j1) && (mask & cls);
         const double P = (double)L.k0 + (double)L.frac + sq;
-        // Candidate centres: kc in [P/r1 - 1, P/r1 + 1].  Unless P/r1 lies
+        // Candidate centres: kc in [P/r1 - H, P/r1 + H].  Unless P/r1 lies
         // within single-precision rounding of an integer (eps), these are the
-        // two centres floor(P/r1) and floor(P/r1) + 1; otherwise three, from
-        // floor(P/r1 + eps) - 1.  The wavefront takes the wider set when any
+        // 2H centres from floor(P/r1) - H + 1; otherwise 2H + 1, from
+        // floor(P/r1 + eps) - H.  The wavefront takes the wider set when any
         // of its used lanes needs it.
+        constexpr int H = NSP / 2;
         const double Pr = P * inv_r1;
         const double fl = floor(Pr);
         const bool edge = (Pr - fl) < eps || (Pr - fl) > 1.0 - eps;
         if (__builtin_amdgcn_ballot_w64(ok && edge))
-          band_chunk<R, COUNT, RHO, SURR, 3>(L, jl, ls, cls, ok, (int64_t)floor(Pr + eps) - 1, side, rq, iso, iv,
-                                             chi_mode, cc0, cc1, l, rl, r1, cfine, b_prev, b_cur, m_a, m_b, base, sp,
-                                             G, a, lds_acc, cnt, n_used, n_band);
+          band_chunk<R, COUNT, RHO, SURR, NSP, 2 * H + 1>(L, jl, ls, cls, ok, (int64_t)floor(Pr + eps) - H, side, rq,
+                                                          iso, iv, chi_mode, cc0, cc1, l, rl, r1, cfine, b_prev,
+                                                          b_cur, m_a, m_b, base, sp, G, a, lds_acc, cnt, n_used,
+                                                          n_band);
         else
-          band_chunk<R, COUNT, RHO, SURR, 2>(L, jl, ls, cls, ok, (int64_t)fl, side, rq, iso, iv, chi_mode, cc0,
-                                             cc1, l, rl, r1, cfine, b_prev, b_cur, m_a, m_b, base, sp, G, a, lds_acc,
-                                             cnt, n_used, n_band);
+          band_chunk<R, COUNT, RHO, SURR, NSP, 2 * H>(L, jl, ls, cls, ok, (int64_t)fl - H + 1, side, rq, iso, iv,
+                                                      chi_mode, cc0, cc1, l, rl, r1, cfine, b_prev, b_cur, m_a, m_b,
+                                                      base, sp, G, a, lds_acc, cnt, n_used, n_band);
         if (COUNT && lane == 0) cnt.band_iters++;
       }
     }
@@ -1200,10 +1233,18 @@ __global__ void __launch_bounds__(256) k_level(Geometry G, LevelArgs a_in) {
         // each wavefront owns a contiguous quarter of the item's nodes
         const int own_lo = (int)(((int64_t)count * wv) >> 2);
         const int own_hi = (int)(((int64_t)count * (wv + 1)) >> 2);
-        if (G.r[l + 1] == 2 * G.r[l])
-          band_lines<R, COUNT, 2, SURR>(G, a, l, layer, first, own_lo, own_hi, iv, lds_acc, cnt, n_used, n_band);
-        else
-          band_lines<R, COUNT, 4, SURR>(G, a, l, layer, first, own_lo, own_hi, iv, lds_acc, cnt, n_used, n_band);
+        const bool two = G.r[l + 1] == 2 * G.r[l];
+        if (G.ns == 5) {
+          if (two)
+            band_lines<R, COUNT, 2, SURR, 5>(G, a, l, layer, first, own_lo, own_hi, iv, lds_acc, cnt, n_used, n_band);
+          else
+            band_lines<R, COUNT, 4, SURR, 5>(G, a, l, layer, first, own_lo, own_hi, iv, lds_acc, cnt, n_used, n_band);
+        } else {
+          if (two)
+            band_lines<R, COUNT, 2, SURR, 3>(G, a, l, layer, first, own_lo, own_hi, iv, lds_acc, cnt, n_used, n_band);
+          else
+            band_lines<R, COUNT, 4, SURR, 3>(G, a, l, layer, first, own_lo, own_hi, iv, lds_acc, cnt, n_used, n_band);
+        }
       } else {
         const int ngroup = (count + 63) >> 6;
         for (int g = wv; g < ngroup; g += 4)
@@ -1260,7 +1301,13 @@ __global__ void k_cascade(Geometry G, int l, R* A, R* out, int64_t stride, const
     double f = (double)rem / (double)rho, t;
     int64_t kc;
     if (f <= 0.5) { kc = q; t = f; } else { kc = q + 1; t = f - 1.0; }
-    v = R(0.5 * t * (t - 1.0)) * Ac[kc - 1] + R(1.0 - t * t) * Ac[kc] + R(0.5 * t * (t + 1.0)) * Ac[kc + 1];
+    if (G.ns == 5) {
+      v = R(0);
+#pragma unroll
+      for (int k = -2; k <= 2; ++k) v += R(lagrange_w<2>(k, t)) * Ac[kc + k];
+    } else {
+      v = R(lagrange_w<1>(-1, t)) * Ac[kc - 1] + R(lagrange_w<1>(0, t)) * Ac[kc] + R(lagrange_w<1>(1, t)) * Ac[kc + 1];
+    }
   }
   if (l > 0) {
     A[(int64_t)layer * G.a_total + G.aoff[l] + i] += v;

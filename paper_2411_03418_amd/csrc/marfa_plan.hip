@@ -151,6 +151,8 @@ static int64_t fdiv(int64_t a, int64_t b) {
 static int default_lnw(int l) { return l == 0 ? 6 : 4; }
 
 static void make_geometry(const marfa_request& rq, double nu_max, Geometry& G) {
+  G.ns = rq.stencil == 5 ? 5 : 3;
+  const int half = G.ns / 2;
   for (int l = 0; l < kLevels; ++l) {
     if (rq.level_table == 1) G.r[l] = 1 << l;
     else G.r[l] = l == 0 ? 1 : (1 << (l + 1));
@@ -161,8 +163,8 @@ static void make_geometry(const marfa_request& rq, double nu_max, Geometry& G) {
   hi[0] = (int64_t)std::llround(rq.nu_end * 2048.0);
   for (int l = 0; l < kLevels - 1; ++l) {
     int64_t rho = G.r[l + 1] / G.r[l];
-    G.lo[l + 1] = fdiv(G.lo[l], rho) - 1;
-    hi[l + 1] = -fdiv(-hi[l], rho) + 1;
+    G.lo[l + 1] = fdiv(G.lo[l], rho) - half;
+    hi[l + 1] = -fdiv(-hi[l], rho) + half;
   }
   int64_t off = 0;
   for (int l = 0; l < kLevels; ++l) {
@@ -178,7 +180,7 @@ static void make_geometry(const marfa_request& rq, double nu_max, Geometry& G) {
   const double c = rq.cutoff * 2048.0;
   for (int l = 0; l < kLevels - 1; ++l) {
     G.b[l] = rq.R * G.r[l + 1];
-    G.hb[l] = 1.5 * G.r[l + 1] + 1.0;
+    G.hb[l] = (half + 0.5) * G.r[l + 1] + 1.0;
   }
   G.b[kLevels - 1] = INFINITY;
   G.hb[kLevels - 1] = 0.0;
@@ -332,13 +334,13 @@ static bool make_intervals(const Geometry& G, int chi, std::vector<IntervalSet>&
       }
       S.jumps_isolated = 1;
       for (size_t k = 1; k < qs.size(); ++k)
-        if (qs[k].first - qs[k - 1].first <= 4.0 * G.r[l + (top ? 0 : 1)] + 4.0) S.jumps_isolated = 0;
+        if (qs[k].first - qs[k - 1].first <= 2.0 * (G.ns - 1) * G.r[l + (top ? 0 : 1)] + 4.0) S.jumps_isolated = 0;
       for (size_t k = 0; k < qs.size(); ++k) {
         S.jchi_mode[k] = 0;
         S.jchi_c0[k] = 0.0;
         S.jchi_c1[k] = 0.0;
         if (chi != MARFA_CHI_TONKOV || top) continue;
-        const double reach = 3.0 * G.r[l + 1] + 4.0;
+        const double reach = G.ns * G.r[l + 1] + 4.0;
         const double lo = std::max(0.0, qs[k].first - reach) / 2048.0, hi = (qs[k].first + reach) / 2048.0;
         auto piece = [](double x) { return x < 3.0 ? 0 : (x <= 150.0 ? 1 : (x <= 300.0 ? 2 : 3)); };
         const int pa = piece(lo), pb = piece(hi);
@@ -356,9 +358,9 @@ static bool make_intervals(const Geometry& G, int chi, std::vector<IntervalSet>&
         const double r1 = G.r[l + 1];
         const int rho = G.r[l + 1] / G.r[l];
         const double qlo = qs.front().first, qhi = qs.back().first;
-        // single-precision d carries at most half an ulp of |d| <= qhi + 3 r1
-        const double eps = 4.0 * std::ldexp(qhi + 3.0 * r1, -24) / r1 + 1e-9;
-        if ((rho == 2 || rho == 4) && qlo > 2.0 * r1 + 2.0 && eps < 0.4 && qhi + 3.0 * r1 < 16777216.0) {
+        // single-precision d carries at most half an ulp of |d| <= qhi + ns r1
+        const double eps = 4.0 * std::ldexp(qhi + G.ns * r1, -24) / r1 + 1e-9;
+        if ((rho == 2 || rho == 4) && qlo > (G.ns - 1) * r1 + 2.0 && eps < 0.4 && qhi + G.ns * r1 < 16777216.0) {
           S.lc_ok = 1;
           S.lc_eps = eps;
         }
@@ -453,6 +455,7 @@ static marfa_status validate(const marfa_lines* L, const marfa_layer* lay, int32
   if (rq->out_kind < 0 || rq->out_kind > 1) return fail(MARFA_E_INVALID, "out_kind");
   if (rq->eval < 0 || rq->eval > 1) return fail(MARFA_E_INVALID, "eval");
   if (rq->level_table < 0 || rq->level_table > 1) return fail(MARFA_E_INVALID, "level_table");
+  if (rq->stencil != 0 && rq->stencil != 3 && rq->stencil != 5) return fail(MARFA_E_INVALID, "stencil must be 3 or 5");
   if (rq->fp64 < 0 || rq->fp64 > 1) return fail(MARFA_E_INVALID, "fp64");
   if (!(rq->prune_rel >= 0.0) || !(rq->prune_rel < 1.0)) return fail(MARFA_E_INVALID, "prune_rel in [0,1)");
   if (rq->eval == MARFA_EVAL_SURROGATE) return fail(MARFA_E_UNSUPPORTED, "surrogate evaluation needs a trained network");
@@ -1048,6 +1051,7 @@ extern "C" const char* marfa_status_string(int32_t s) {
     case MARFA_E_DEVICE: return "device error";
     case MARFA_E_UNSUPPORTED: return "unsupported";
     case MARFA_E_STATE: return "bad state";
+    case MARFA_E_IO: return "file error";
     default: return "unknown status";
   }
 }

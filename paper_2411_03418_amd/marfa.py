@@ -15,7 +15,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmarfa.so")
 
-OK, E_INVALID, E_NOMEM, E_DEVICE, E_UNSUPPORTED, E_STATE = 0, -1, -2, -3, -4, -5
+OK, E_INVALID, E_NOMEM, E_DEVICE, E_UNSUPPORTED, E_STATE, E_IO = 0, -1, -2, -3, -4, -5, -6
+PTBIN_NT = 20481          # values per PT-table record (Appendix A)
+PTBIN_TRUNCATE = 1
 SHAPES = {"voigt": 0, "lorentz": 1, "doppler": 2}
 CHIS = {"none": 0, "tonkov": 1}
 OUTS = {"sigma": 0, "k": 1}
@@ -41,7 +43,7 @@ class Request(C.Structure):
     _fields_ = [("nu_begin", C.c_double), ("nu_end", C.c_double), ("cutoff", C.c_double),
                 ("shape", C.c_int32), ("chi", C.c_int32), ("out_kind", C.c_int32), ("eval", C.c_int32),
                 ("prune_rel", C.c_double), ("R", C.c_double), ("level_table", C.c_int32),
-                ("fp64", C.c_int32), ("reserved", C.c_int32 * 4)]
+                ("fp64", C.c_int32), ("stencil", C.c_int32), ("reserved", C.c_int32 * 3)]
 
 
 class Stats(C.Structure):
@@ -120,13 +122,14 @@ def lib():
         L.marfa_surrogate_destroy.argtypes = [vp]
         L.marfa_surrogate_destroy.restype = None
         L.marfa_plan_set_surrogate.argtypes = [vp, vp]
+        L.marfa_ptbin_write.argtypes = [C.c_char_p, vp, i64, C.c_double, i32, vp, i32, C.POINTER(i32)]
         for f in ("marfa_surrogate_create", "marfa_surrogate_set_params", "marfa_surrogate_get_params",
                   "marfa_surrogate_forward", "marfa_surrogate_loss_grad", "marfa_surrogate_make_samples",
                   "marfa_surrogate_train", "marfa_plan_set_surrogate"):
             getattr(L, f).restype = C.c_int32
         for f in ("marfa_plan_create", "marfa_plan_points", "marfa_execute", "marfa_execute_layers",
                   "marfa_plan_count", "marfa_plan_tiles", "marfa_execute_timed", "marfa_plan_tune", "marfa_last_error",
-                  "marfa_voigt_eval"):
+                  "marfa_voigt_eval", "marfa_ptbin_write"):
             getattr(L, f).restype = C.c_int32
         _lib = L
     return _lib
@@ -159,7 +162,7 @@ class Plan:
     """
 
     def __init__(self, lines, layers, *, nu_begin, nu_end, cutoff, shape="voigt", chi="none", out="sigma",
-                 prune=0.0, R=48, level_table=0, fp64=False, device=0):
+                 prune=0.0, R=48, level_table=0, fp64=False, stencil=3, device=0):
         L = lib()
         self._arrs = [np.ascontiguousarray(lines.nu0, np.float64),
                       np.ascontiguousarray(lines.S296, np.float32),
@@ -179,7 +182,7 @@ class Plan:
         lays = (Layer * lay.shape[0])(*[Layer(*row) for row in lay])
         rq = Request(float(nu_begin), float(nu_end), float(cutoff), SHAPES.get(shape, shape),
                      CHIS.get(chi, chi), OUTS.get(out, out), 0, float(prune), float(R), int(level_table),
-                     1 if fp64 else 0, (C.c_int32 * 4)(0, 0, 0, 0))
+                     1 if fp64 else 0, int(stencil), (C.c_int32 * 3)(0, 0, 0))
         h = C.c_void_p()
         _check(L.marfa_plan_create(C.byref(h), C.byref(ls), lays, lay.shape[0], C.byref(rq), int(device)))
         self._h = h
@@ -382,3 +385,43 @@ def voigt_eval(x, y, fp64=False, device=0):
 def record_number(nu: float) -> int:
     """Appendix A: the record holding wavenumber nu is int(nu/10)."""
     return int(nu / 10.0)
+
+
+def write_ptbin(path, values, nu_begin, truncate=True, stream=None) -> int:
+    """Write the PT-table records (Appendix A) covered by one layer's spectrum.
+
+    values: a 1-D float32 torch tensor on a GPU (e.g. a row of Plan.execute's
+    output) or a numpy float32 array, holding the spectrum at
+    nu_begin + i / 2048 cm^-1.  Returns the number of records written.
+    """
+    n = C.c_int32(0)
+    flags = PTBIN_TRUNCATE if truncate else 0
+    if isinstance(values, np.ndarray):
+        v = np.ascontiguousarray(values, np.float32).ravel()
+        _check(lib().marfa_ptbin_write(os.fsencode(path), _ptr(v), v.shape[0], float(nu_begin), 0, None, flags,
+                                       C.byref(n)))
+    else:
+        import torch
+        if values.dtype != torch.float32 or not values.is_cuda or values.dim() != 1 or values.stride(0) != 1:
+            raise ValueError("values must be a contiguous 1-D float32 GPU tensor or a numpy array")
+        dev = values.device.index
+        with torch.cuda.device(dev):
+            _check(lib().marfa_ptbin_write(os.fsencode(path), C.c_void_p(values.data_ptr()), values.shape[0],
+                                           float(nu_begin), 1, _stream_handle(stream, dev), flags, C.byref(n)))
+    return n.value
+
+
+def ptbin_name(layer_number: int) -> str:
+    """Appendix A file name: the 1-based layer number padded with '_' to three characters."""
+    return f"{layer_number:_<3d}.ptbin"
+
+
+def write_pt_table(out, directory, nu_begin, stream=None) -> list:
+    """One .ptbin file per layer (rows of out), named by 1-based layer number."""
+    os.makedirs(directory, exist_ok=True)
+    paths = []
+    for i in range(out.shape[0]):
+        p = os.path.join(directory, ptbin_name(i + 1))
+        write_ptbin(p, out[i], nu_begin, truncate=True, stream=stream)
+        paths.append(p)
+    return paths

@@ -3,7 +3,7 @@
 Gates (relative, on nodes where the direct sum is >= 1e-8 of the layer max):
 GPU single precision vs the definition <= 1e-4; vs the oracle's eleven-grid
 result <= FP32_VS_GRID (implementation error only); GPU double precision vs
-the oracle's eleven-grid result <= 1e-12.
+the oracle's eleven-grid result <= FP64_VS_GRID.
 
 FP32_VS_GRID = 3e-5: the eleven-grid result at a weak node next to a strong
 line's cut-off is a coarse-level sum holding that line's wing minus a band
@@ -11,6 +11,13 @@ correction of the same size, so single-precision rounding of the coarse sums
 (about 1e-7 of their value) is amplified by their ratio to the node value;
 with summation orders from other tile shapes this reaches 1.5e-5 at nodes
 near 1e-8 of the layer max.
+
+FP64_VS_GRID = 2e-10: the double-precision device Voigt function takes
+K = Re w(z) from a rational approximation of the Faddeeva function w; for
+y << 1 and |x| of 5 to 8, Re w is smaller than |w| by about y / |x|, so
+double rounding of w leaves K a relative error near |x| eps / y (7.8e-11 at
+y = 1e-5 on the device-K grid below).  Lines of a layer at 1e-5 atm reach it
+at nodes a few Doppler widths from their centres.
 """
 import os
 
@@ -25,6 +32,7 @@ pytestmark = pytest.mark.gpu
 
 THREADS = min(16, os.cpu_count() or 1)
 FP32_VS_GRID = 3e-5
+FP64_VS_GRID = 2e-10
 
 
 def marfa():
@@ -52,6 +60,7 @@ def _oreq(req):
     o["level_table"] = req.get("level_table", 0)
     o["out_kind"] = {"sigma": 0, "k": 1}[req.get("out", "sigma")]
     o["R"] = float(req.get("R", 48))
+    o["stencil"] = int(req.get("stencil", 3))
     return o
 
 
@@ -136,7 +145,7 @@ def test_one_line_parity(case, fp64):
     eg, ed = rel_err(got, ref_g), rel_err(got, ref_d)
     print(f"vs grid {eg:.2e}  vs direct {ed:.2e}")
     assert ed < 1e-4
-    assert eg < (1e-12 if fp64 else FP32_VS_GRID)
+    assert eg < (FP64_VS_GRID if fp64 else FP32_VS_GRID)
 
 
 # ------------------------------------------------------------------ workloads
@@ -152,7 +161,7 @@ def test_single_1k_workload(fp64):
     eg, ed = rel_err(got, ref_g), rel_err(got, ref_d)
     print(f"single_1k fp64={fp64}: vs grid {eg:.2e} vs direct {ed:.2e}")
     assert ed < 1e-4
-    assert eg < (1e-12 if fp64 else FP32_VS_GRID)
+    assert eg < (FP64_VS_GRID if fp64 else FP32_VS_GRID)
 
 
 def test_multi_layer_pruned_ragged():
@@ -185,7 +194,7 @@ def test_small_cutoff_node_major_band(fp64):
     eg, ed = rel_err(got, ref_g), rel_err(got, ref_d)
     print(f"small cut-off fp64={fp64}: vs grid {eg:.2e} vs direct {ed:.2e}")
     assert ed < 1e-4
-    assert eg < (1e-12 if fp64 else FP32_VS_GRID)
+    assert eg < (FP64_VS_GRID if fp64 else FP32_VS_GRID)
 
 
 @pytest.mark.parametrize("fp64", [False, True])
@@ -202,7 +211,7 @@ def test_long_cutoff_all_tonkov_pieces(fp64):
     eg, ed = rel_err(got, ref_g), rel_err(got, ref_d)
     print(f"cut-off 400 fp64={fp64}: vs grid {eg:.2e} vs direct {ed:.2e}")
     assert ed < 1e-4
-    assert eg < (1e-12 if fp64 else FP32_VS_GRID)
+    assert eg < (FP64_VS_GRID if fp64 else FP32_VS_GRID)
 
 
 @pytest.mark.parametrize("fp64", [False, True])
@@ -219,7 +228,114 @@ def test_region_edge_next_to_chi_break(fp64):
     eg, ed = rel_err(got, ref_g), rel_err(got, ref_d)
     print(f"R=47 fp64={fp64}: vs grid {eg:.2e} vs direct {ed:.2e}")
     assert ed < 1e-4
-    assert eg < (1e-12 if fp64 else FP32_VS_GRID)
+    assert eg < (FP64_VS_GRID if fp64 else FP32_VS_GRID)
+
+
+# ------------------------------------------------------------------ rounding at region edges
+
+@pytest.mark.parametrize("tiles", [None, {"item_nodes": 512, "blocks_per_cu": 8,
+                                           "wave_nodes": [32, 32, 16, 8, 4, 2, 2, 2, 2, 2, 2]}])
+def test_centres_within_rounding_of_a_node(tiles):
+    # shifted centres 5.4e-5 of a fine step below / above a lattice node: the
+    # single-precision distance to nodes one region radius away rounds onto
+    # the region edge, so the region scan must take lines whose exact distance
+    # is just outside its window (narrow wavefront tiles put a window edge
+    # exactly there)
+    L = synth.make_lines(2, 0, 1, 7)
+    L.nu0[:] = [(19844672 - 5.4e-5) / 2048.0, (19834880 + 5.4e-5) / 2048.0]
+    L.gamma_air[:] = 0.075
+    L.gamma_self[:] = 0.075
+    L.S296[:] = [1e-20, 3e-21]
+    L.E_lower[:] = 0.0
+    L.delta_air[:] = 0.0
+    lay = [6.77, 645.0, 6.77, 0.0]
+    req = dict(nu_begin=9679.0, nu_end=9699.0, cutoff=125.0)
+    M = marfa()
+    plan = M.Plan(L, np.array([lay]), device=0, **req)
+    if tiles:
+        plan.set_tiles(tiles)
+    got = plan.execute()
+    torch.cuda.synchronize()
+    got = got[0].double().cpu().numpy()
+    plan.close()
+    o = _oreq(req)
+    ref_g = O.grid(L, lay, threads=THREADS, **o)
+    ref_d = O.direct(L, lay, all_nodes(req), threads=THREADS, **o)
+    eg, ed = rel_err(got, ref_g), rel_err(got, ref_d)
+    print(f"tiles {tiles}: vs grid {eg:.2e} vs direct {ed:.2e}")
+    assert ed < 1e-4
+    assert eg < FP32_VS_GRID
+
+
+# ------------------------------------------------------------------ 5-point stencil
+
+# R = 12 with the 5-point stencil: b_7 = 12 r_8 is exactly the 3 cm^-1 break of
+# chi, so one merged jump carries both classes
+FIVE = dict(stencil=5, R=12)
+
+
+@pytest.mark.parametrize("case", [ONE_LINE[i] for i in (0, 1, 2, 3, 5, 6, 8, 10)])
+@pytest.mark.parametrize("fp64", [False, True])
+def test_one_line_parity_5pt(case, fp64):
+    L, lay = _one(case["nu0"], case["gamma"], p=case.get("p", 1.0), T=case.get("T", 296.0))
+    req = dict(nu_begin=case.get("nb", 1000.0), nu_end=case.get("ne", 1010.0), cutoff=case.get("c", 25.0),
+               chi=case.get("chi", "none"), shape=case.get("shape", "voigt"), level_table=case.get("lt", 0), **FIVE)
+    got = run(L, [lay], fp64=fp64, **req)[0]
+    o = _oreq(req)
+    ref_g = O.grid(L, lay, threads=THREADS, **o)
+    ref_d = O.direct(L, lay, all_nodes(req), threads=THREADS, **o)
+    eg, ed = rel_err(got, ref_g), rel_err(got, ref_d)
+    print(f"5-point: vs grid {eg:.2e}  vs direct {ed:.2e}")
+    assert ed < 1e-4
+    assert eg < (FP64_VS_GRID if fp64 else FP32_VS_GRID)
+
+
+@pytest.mark.parametrize("fp64", [False, True])
+def test_multi_layer_5pt(fp64):
+    lines = synth.make_lines(3000, 930.0, 1090.0, 31, shift=True)
+    layers = synth.pt_table(5)
+    req = dict(nu_begin=1000.0, nu_end=1013.5, cutoff=60.0, chi="tonkov", prune=1e-6, **FIVE)
+    got = run(lines, layers, fp64=fp64, **req)
+    o = _oreq(req)
+    for i in range(layers.shape[0]):
+        ref_g = O.grid(lines, layers[i], threads=THREADS, **o)
+        ref_d = O.direct(lines, layers[i], all_nodes(req), threads=THREADS, **o)
+        eg, ed = rel_err(got[i], ref_g), rel_err(got[i], ref_d)
+        print(f"5-point layer {i} fp64={fp64}: vs grid {eg:.2e} vs direct {ed:.2e}")
+        assert ed < 1e-4
+        assert eg < (FP64_VS_GRID if fp64 else FP32_VS_GRID)
+
+
+@pytest.mark.parametrize("fp64", [False, True])
+def test_small_cutoff_node_major_band_5pt(fp64):
+    # 5-point hulls span 4 r_(l+1): the cut-off jump falls inside hulls around
+    # line centres from level 8 up, which take the node-major band pass
+    lines = synth.make_lines(500, 995.0, 1015.0, 35, shift=True)
+    lay = [0.3, 260.0, 0.05, 0.0]
+    req = dict(nu_begin=1000.0, nu_end=1010.0, cutoff=1.5, **FIVE)
+    got = run(lines, [lay], fp64=fp64, **req)[0]
+    o = _oreq(req)
+    ref_d = O.direct(lines, lay, all_nodes(req), threads=THREADS, **o)
+    ref_g = O.grid(lines, lay, threads=THREADS, **o)
+    eg, ed = rel_err(got, ref_g), rel_err(got, ref_d)
+    print(f"5-point small cut-off fp64={fp64}: vs grid {eg:.2e} vs direct {ed:.2e}")
+    assert ed < 1e-4
+    assert eg < (FP64_VS_GRID if fp64 else FP32_VS_GRID)
+
+
+@pytest.mark.parametrize("fp64", [False, True])
+def test_long_cutoff_5pt(fp64):
+    lines = synth.make_lines(1500, 600.0, 1400.0, 37, shift=True)
+    lay = [2.0, 300.0, 2.0, 0.0]
+    req = dict(nu_begin=995.0, nu_end=1005.0, cutoff=400.0, chi="tonkov", **FIVE)
+    got = run(lines, [lay], fp64=fp64, **req)[0]
+    o = _oreq(req)
+    ref_d = O.direct(lines, lay, all_nodes(req), threads=THREADS, **o)
+    ref_g = O.grid(lines, lay, threads=THREADS, **o)
+    eg, ed = rel_err(got, ref_g), rel_err(got, ref_d)
+    print(f"5-point cut-off 400 fp64={fp64}: vs grid {eg:.2e} vs direct {ed:.2e}")
+    assert ed < 1e-4
+    assert eg < (FP64_VS_GRID if fp64 else FP32_VS_GRID)
 
 
 def test_absorption_coefficient_output():
