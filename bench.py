@@ -41,7 +41,7 @@ FLOP_WING = 18        # d, d^2+g^2, 1/., e, U, 1+eU, A Q sum, chi = exp2(c0+c1 d
 FLOP_TERM = 6         # one more term of the asymptotic wing series
 FLOP_CORE = 2 * 230   # rational core in FP64 (27 complex Horner steps + setup); FP64 counts double
 FLOP_BAND = 6         # three stencil weights times coarse values, per band pair
-STENCIL5_R = 12      # R for the 5-point stencil: about 1.6e-5 from the direct sum in one-line sweeps
+STENCIL5_R = 24      # 5-point R with the cost of the 3-point R = 48 table and ~40x lower interpolation error
 
 
 def profiled_traffic(workload):

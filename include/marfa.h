@@ -92,8 +92,8 @@ typedef struct {
   int32_t level_table;
   int32_t fp64;
   int32_t stencil;            /* interpolation points between levels, 3 (0 = 3) or 5
-                                 (Section 2.4 names both; 5 points reach the 3-point
-                                 accuracy of R = 48 at R = 10-12) */
+                                 (Section 2.4 names both; 5 points lower the
+                                 interpolation error tens of times at equal R) */
   int32_t reserved[3];
 } marfa_request;
 
@@ -283,6 +283,28 @@ void marfa_surrogate_destroy(marfa_surrogate* s);
  * MARFA_E_INVALID (mismatch), MARFA_E_UNSUPPORTED (untrained network, a
  * cut-off under two coarsest steps). */
 marfa_status marfa_plan_set_surrogate(marfa_plan* plan, const marfa_surrogate* s);
+
+/* Spectral line database file (Appendix B): packed little-endian records of
+ * 36 bytes, one per line, in this order: nu0 (float64), S296, gamma_air,
+ * gamma_self, E_lower, n_air (float32 each), mol_iso (int32), delta_air
+ * (float32).  No header and no record markers.
+ *
+ * marfa_linedb_count: *n = file size / 36.  MARFA_E_INVALID for NULL
+ * arguments or a size that is not a multiple of 36; MARFA_E_IO if the file
+ * cannot be opened.
+ * marfa_linedb_read: copies records [first, first + count) into the caller's
+ * host arrays (each of count elements; mol_iso may be NULL).  MARFA_E_INVALID
+ * for NULL arrays, negative first/count or a range past the end; MARFA_E_IO on
+ * a read failure.
+ * marfa_linedb_write: writes lines->n records (creating or truncating path);
+ * mol_iso NULL writes zeros.  MARFA_E_INVALID for NULL arguments or n < 0,
+ * MARFA_E_IO on failure. */
+#define MARFA_LINEDB_RECORD 36
+marfa_status marfa_linedb_count(const char* path, int64_t* n);
+marfa_status marfa_linedb_read(const char* path, int64_t first, int64_t count, double* nu0, float* S296,
+                               float* gamma_air, float* gamma_self, float* E_lower, float* n_air,
+                               int32_t* mol_iso, float* delta_air);
+marfa_status marfa_linedb_write(const char* path, const marfa_lines* lines);
 
 /* PT-table record file (Appendix A).  One binary direct-access file per layer
  * holds records of MARFA_PTBIN_NT = 20481 single-precision values: record r

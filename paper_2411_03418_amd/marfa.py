@@ -123,13 +123,17 @@ def lib():
         L.marfa_surrogate_destroy.restype = None
         L.marfa_plan_set_surrogate.argtypes = [vp, vp]
         L.marfa_ptbin_write.argtypes = [C.c_char_p, vp, i64, C.c_double, i32, vp, i32, C.POINTER(i32)]
+        L.marfa_linedb_count.argtypes = [C.c_char_p, C.POINTER(i64)]
+        L.marfa_linedb_read.argtypes = [C.c_char_p, i64, i64, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.marfa_linedb_write.argtypes = [C.c_char_p, C.POINTER(Lines)]
         for f in ("marfa_surrogate_create", "marfa_surrogate_set_params", "marfa_surrogate_get_params",
                   "marfa_surrogate_forward", "marfa_surrogate_loss_grad", "marfa_surrogate_make_samples",
                   "marfa_surrogate_train", "marfa_plan_set_surrogate"):
             getattr(L, f).restype = C.c_int32
         for f in ("marfa_plan_create", "marfa_plan_points", "marfa_execute", "marfa_execute_layers",
                   "marfa_plan_count", "marfa_plan_tiles", "marfa_execute_timed", "marfa_plan_tune", "marfa_last_error",
-                  "marfa_voigt_eval", "marfa_ptbin_write"):
+                  "marfa_voigt_eval", "marfa_ptbin_write", "marfa_linedb_count", "marfa_linedb_read",
+                  "marfa_linedb_write"):
             getattr(L, f).restype = C.c_int32
         _lib = L
     return _lib
@@ -425,3 +429,27 @@ def write_pt_table(out, directory, nu_begin, stream=None) -> list:
         write_ptbin(p, out[i], nu_begin, truncate=True, stream=stream)
         paths.append(p)
     return paths
+
+
+def read_line_db(path, first=0, count=None, molar_mass=44.0):
+    """Line records of an Appendix B database file, as a synth.LineList."""
+    from .synth import LineList
+    L = lib()
+    n = C.c_int64(0)
+    _check(L.marfa_linedb_count(os.fsencode(path), C.byref(n)))
+    if count is None:
+        count = n.value - first
+    arrs = [np.empty(count, np.float64)] + [np.empty(count, np.float32) for _ in range(5)] + \
+           [np.empty(count, np.int32), np.empty(count, np.float32)]
+    _check(L.marfa_linedb_read(os.fsencode(path), int(first), int(count), *[_ptr(a) for a in arrs]))
+    return LineList(*arrs, molar_mass=molar_mass)
+
+
+def write_line_db(path, lines):
+    """Write lines (any object with the LineList arrays) as Appendix B records."""
+    a = [np.ascontiguousarray(lines.nu0, np.float64), np.ascontiguousarray(lines.S296, np.float32),
+         np.ascontiguousarray(lines.gamma_air, np.float32), np.ascontiguousarray(lines.gamma_self, np.float32),
+         np.ascontiguousarray(lines.E_lower, np.float32), np.ascontiguousarray(lines.n_air, np.float32),
+         np.ascontiguousarray(lines.mol_iso, np.int32), np.ascontiguousarray(lines.delta_air, np.float32)]
+    ls = Lines(int(a[0].shape[0]), *[_ptr(x) for x in a], float(getattr(lines, "molar_mass", 44.0)))
+    _check(lib().marfa_linedb_write(os.fsencode(path), C.byref(ls)))

@@ -31,6 +31,7 @@ def test_status_strings():
     assert L.marfa_status_string(0) == b"ok"
     assert L.marfa_status_string(-1) == b"invalid argument"
     assert L.marfa_status_string(-3) == b"device error"
+    assert L.marfa_status_string(-6) == b"file error"
 
 
 def _plan(**kw):

@@ -130,3 +130,43 @@ def test_device_output_written_per_layer(tmp_path):
         assert os.path.getsize(p) == 102 * NT * 4
         for r in (100, 101, 102):
             assert np.array_equal(read_record(p, r), host[i, r * STEP - m0:r * STEP - m0 + NT])
+
+
+# ------------------------------------------------------------------ line database (Appendix B)
+
+def test_linedb_round_trip_and_layout(tmp_path):
+    from paper_2411_03418_amd import synth
+    lines = synth.make_lines(5000, 500.0, 600.0, 17, shift=True)
+    lines.mol_iso[:] = np.arange(lines.n, dtype=np.int32) % 97 + 21
+    p = str(tmp_path / "CO2.db")
+    M.write_line_db(p, lines)
+    assert os.path.getsize(p) == 36 * lines.n
+    # layout read back with the independent struct codec
+    ref = synth.unpack_records(open(p, "rb").read())
+    back = M.read_line_db(p)
+    for f in ("nu0", "S296", "gamma_air", "gamma_self", "E_lower", "n_air", "mol_iso", "delta_air"):
+        assert np.array_equal(getattr(ref, f), getattr(lines, f)), f
+        assert np.array_equal(getattr(back, f), getattr(lines, f)), f
+    # and the writer's bytes equal the struct codec's for the first records
+    assert open(p, "rb").read(36 * 50) == synth.pack_records(lines.subset(np.arange(50)))
+    part = M.read_line_db(p, first=1234, count=100)
+    assert np.array_equal(part.nu0, lines.nu0[1234:1334])
+
+
+def test_linedb_errors(tmp_path):
+    p = tmp_path / "bad.db"
+    p.write_bytes(b"\0" * 35)
+    with pytest.raises(M.MarfaError) as e:
+        M.read_line_db(str(p))
+    assert e.value.status == M.E_INVALID
+    q = tmp_path / "empty.db"
+    q.write_bytes(b"")
+    assert M.read_line_db(str(q)).n == 0
+    with pytest.raises(M.MarfaError) as e:
+        M.read_line_db(str(tmp_path / "missing.db"))
+    assert e.value.status == M.E_IO
+    r = tmp_path / "two.db"
+    r.write_bytes(b"\0" * 72)
+    with pytest.raises(M.MarfaError) as e:
+        M.read_line_db(str(r), first=1, count=2)
+    assert e.value.status == M.E_INVALID
