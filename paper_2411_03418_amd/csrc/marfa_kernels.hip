@@ -700,24 +700,25 @@ __device__ __forceinline__ Rec load_rec(const Rec* __restrict__ rec, int32_t j) 
 
 // Fast region scan over one window: SGN = +1 / -1 one side of the annulus
 // |d| in [ra, rbx); SGN = 0 the own region |d| < rbx.  Lanes past the
-// window's last line read that line again and are masked.  Lines with start
-// level above smax are skipped.  chi is one exponential piece over the
-// window (or any).
-template <typename R, bool COUNT, int SGN, bool SURR>
+// window's last line read that line again and are masked (only the last
+// chunk tests for that).  Lines with start level above smax are skipped.
+// CHIM: 0 no chi, 1 one exponential piece over the window, 2 any piece.
+template <typename R, bool COUNT, int SGN, bool SURR, int CHIM>
 __device__ __forceinline__ void scan_fast(const typename RecOf<R>::T* __restrict__ rec, const R* __restrict__ sp,
                                           int32_t j0,
                                           int32_t j1, int S, int slice, int32_t X, R ra, R rbx, int smax,
-                                          bool chi_none, bool chi_mixed, R c0, R c1, const Geometry& G, R& acc,
+                                          R c0, R c1, const Geometry& G, R& acc,
                                           Counts& cnt, uint32_t& n_used, const LevelArgs& a) {
   using Rec = typename RecOf<R>::T;
   const R c1s = SGN < 0 ? -c1 : c1;   // chi exponent slope in the signed distance
-  auto step = [&](const Rec& L, int32_t j) {
+  auto step = [&](const Rec& L, int32_t j, bool tail) {
     const R d = R(X - L.k0) - R(L.frac);
     bool in_reg;
     if (SGN > 0) in_reg = d >= ra && d < rbx;
     else if (SGN < 0) in_reg = d <= -ra && d > -rbx;
     else in_reg = fabs(d) < rbx;
-    in_reg = in_reg && L.s <= smax && j < j1;
+    in_reg = in_reg && L.s <= smax;
+    if (tail) in_reg = in_reg && j < j1;
     if constexpr (SURR) {
       const float g = g_surr<COUNT>(d, L, sp, j, G, a, in_reg, cnt);
       acc += in_reg ? g : R(0);
@@ -725,8 +726,8 @@ __device__ __forceinline__ void scan_fast(const typename RecOf<R>::T* __restrict
       (void)a;
       const R g = shape_fast<R, COUNT>(d, L, sp, j, G, in_reg, cnt);
       R chi;
-      if (chi_none) chi = R(1);
-      else if (!chi_mixed) chi = fast_exp2<R>(fma(c1s, SGN == 0 ? fabs(d) : d, c0));
+      if constexpr (CHIM == 0) chi = R(1);
+      else if constexpr (CHIM == 1) chi = fast_exp2<R>(fma(c1s, SGN == 0 ? fabs(d) : d, c0));
       else chi = chi_any<R>(fabs(d), G);
       acc += in_reg ? g * chi : R(0);
     }
@@ -734,16 +735,38 @@ __device__ __forceinline__ void scan_fast(const typename RecOf<R>::T* __restrict
   };
   int32_t j = j0 + slice;
   Rec La = load_rec(rec, j < j1 ? j : j1 - 1);
-  for (int32_t J = j0; J < j1; J += 2 * S) {
-    const Rec Lb = load_rec(rec, J + S + slice < j1 ? J + S + slice : j1 - 1);
-    step(La, J + slice);
+  int32_t J = j0;
+  // full chunks of 2S lines: every lane's line exists
+  for (; J + 2 * S <= j1; J += 2 * S) {
+    const Rec Lb = load_rec(rec, J + S + slice);
+    step(La, J + slice, false);
     La = load_rec(rec, J + 2 * S + slice < j1 ? J + 2 * S + slice : j1 - 1);
+    step(Lb, J + S + slice, false);
+    if (COUNT && (threadIdx.x & 63) == 0) cnt.iters += 2;
+  }
+  if (J < j1) {
+    const Rec Lb = load_rec(rec, J + S + slice < j1 ? J + S + slice : j1 - 1);
+    step(La, J + slice, true);
     if (COUNT && (threadIdx.x & 63) == 0) cnt.iters++;
     if (J + S < j1) {
-      step(Lb, J + S + slice);
+      step(Lb, J + S + slice, true);
       if (COUNT && (threadIdx.x & 63) == 0) cnt.iters++;
     }
   }
+}
+
+// scan_fast with the window's chi mode as a template argument
+template <typename R, bool COUNT, int SGN, bool SURR>
+__device__ __forceinline__ void scan_fast_chi(const typename RecOf<R>::T* __restrict__ rec, const R* __restrict__ sp,
+                                              int32_t j0, int32_t j1, int S, int slice, int32_t X, R ra, R rbx,
+                                              int smax, bool chi_none, bool chi_mixed, R c0, R c1, const Geometry& G,
+                                              R& acc, Counts& cnt, uint32_t& n_used, const LevelArgs& a) {
+  if (chi_mixed)
+    scan_fast<R, COUNT, SGN, SURR, 2>(rec, sp, j0, j1, S, slice, X, ra, rbx, smax, c0, c1, G, acc, cnt, n_used, a);
+  else if (chi_none)
+    scan_fast<R, COUNT, SGN, SURR, 0>(rec, sp, j0, j1, S, slice, X, ra, rbx, smax, c0, c1, G, acc, cnt, n_used, a);
+  else
+    scan_fast<R, COUNT, SGN, SURR, 1>(rec, sp, j0, j1, S, slice, X, ra, rbx, smax, c0, c1, G, acc, cnt, n_used, a);
 }
 
 
@@ -857,7 +880,7 @@ __device__ __forceinline__ void region_tile(const Geometry& G, const LevelArgs& 
       const R rbx = active ? (sizeof(R) == 4 ? R(iv->rbx32) : R(iv->rbx64)) : R(-1);
       const int32_t j0 = uniform(__shfl(my_j, 0)), j1 = uniform(__shfl(my_j, 1));
       if (j0 < j1) {
-        scan_fast<R, COUNT, 0, SURR>(rec, sp, j0, j1, S, slice, X, R(0), rbx, smax, chi_none, chi_mixed, c0, c1, G,
+        scan_fast_chi<R, COUNT, 0, SURR>(rec, sp, j0, j1, S, slice, X, R(0), rbx, smax, chi_none, chi_mixed, c0, c1, G,
                                      acc, cnt, n_used, a);
       }
       for (int o = S >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
@@ -871,10 +894,10 @@ __device__ __forceinline__ void region_tile(const Geometry& G, const LevelArgs& 
       const int32_t j0 = uniform(__shfl(my_j, 2 * side)), j1 = uniform(__shfl(my_j, 2 * side + 1));
       if (j0 >= j1) continue;
       if (side == 0)
-        scan_fast<R, COUNT, 1, SURR>(rec, sp, j0, j1, S, slice, X, ra, rbx, smax, chi_none, chi_mixed, c0, c1, G,
+        scan_fast_chi<R, COUNT, 1, SURR>(rec, sp, j0, j1, S, slice, X, ra, rbx, smax, chi_none, chi_mixed, c0, c1, G,
                                      acc, cnt, n_used, a);
       else
-        scan_fast<R, COUNT, -1, SURR>(rec, sp, j0, j1, S, slice, X, ra, rbx, smax, chi_none, chi_mixed, c0, c1, G,
+        scan_fast_chi<R, COUNT, -1, SURR>(rec, sp, j0, j1, S, slice, X, ra, rbx, smax, chi_none, chi_mixed, c0, c1, G,
                                       acc, cnt, n_used, a);
     }
     for (int o = S >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
