@@ -511,6 +511,20 @@ __device__ __forceinline__ R chi_any(R ad_fine, const Geometry& G) {
   return fast_exp2<R>(c0 + c1 * a);
 }
 
+// S' F(d) of the rational core, kept out of line: the region scans inline
+// the wing many times over and take the core for few pairs
+template <typename R>
+__device__ __attribute__((noinline)) R core_value(R dcm, R xs, R gam, R sp) {
+  const R x = xs * dcm;
+  const R y = xs * gam;
+  double K;
+  if (sizeof(R) == 4)
+    K = voigt_core<kWeidemanN32, true>(fabs((double)x), (double)y, c_weid32, c_weidL[0]);
+  else
+    K = voigt_core<kWeidemanN64>(fabs((double)x), (double)y, c_weid64, c_weidL[1]);
+  return sp * R((double)xs * kInvSqrtPi * K);
+}
+
 // S' F(d) (without chi and the cut-off) for the Voigt shape (Lorentz: ae = 0):
 // the asymptotic wing series with a wave-uniform number of terms, and the
 // rational core for lanes with |z| < sqrt(kZ2).  `live` marks lanes whose
@@ -553,16 +567,7 @@ __device__ __forceinline__ R shape_fast(R d, const typename RecOf<R>::T& L, cons
   }
   R f = R(L.A) * Q * sum;
   if (__builtin_amdgcn_ballot_w64(live && core)) {
-    if (live && core) {
-      const R x = R(L.xs) * dcm;
-      const R y = R(L.xs) * R(L.gam);
-      double K;
-      if (sizeof(R) == 4)
-        K = voigt_core<kWeidemanN32, true>(fabs((double)x), (double)y, c_weid32, c_weidL[0]);
-      else
-        K = voigt_core<kWeidemanN64>(fabs((double)x), (double)y, c_weid64, c_weidL[1]);
-      f = sp[j] * R((double)L.xs * kInvSqrtPi * K);
-    }
+    if (live && core) f = core_value<R>(dcm, L.xs, L.gam, sp[j]);
   }
   if (COUNT && live) { if (core) cnt.core++; else cnt.wing++; }
   return f;
@@ -699,74 +704,146 @@ __device__ __forceinline__ Rec load_rec(const Rec* __restrict__ rec, int32_t j) 
 }
 
 // Fast region scan over one window: SGN = +1 / -1 one side of the annulus
-// |d| in [ra, rbx); SGN = 0 the own region |d| < rbx.  Lanes past the
-// window's last line read that line again and are masked (only the last
-// chunk tests for that).  Lines with start level above smax are skipped.
-// CHIM: 0 no chi, 1 one exponential piece over the window, 2 any piece.
-template <typename R, bool COUNT, int SGN, bool SURR, int CHIM>
+// |d| in [ra, rbx); SGN = 0 the own region |d| < rbx.  Each lane takes K
+// consecutive level nodes (X0, X0 + rl, ...) against one line per step, so a
+// line record is loaded and unpacked once per K pairs.  Lanes past the
+// window's last line read that line again and are masked; act masks nodes
+// outside the tile.  Lines with start level
+// above smax are skipped.  CHIM: 0 no chi, 1 one exponential piece over the
+// window, 2 any piece.  With one piece and a signed distance, chi of node k is
+// chi of node k-1 times the constant exp2(c1 rl).
+template <typename R, bool COUNT, int SGN, bool SURR, int CHIM, int K>
 __device__ __forceinline__ void scan_fast(const typename RecOf<R>::T* __restrict__ rec, const R* __restrict__ sp,
-                                          int32_t j0,
-                                          int32_t j1, int S, int slice, int32_t X, R ra, R rbx, int smax,
-                                          R c0, R c1, const Geometry& G, R& acc,
-                                          Counts& cnt, uint32_t& n_used, const LevelArgs& a) {
+                                          int32_t j0, int32_t j1, int S, int slice, int32_t X0, int32_t rl,
+                                          uint32_t act, R ra, R rbx, int smax, R c0, R c1, const Geometry& G,
+                                          R* acc, Counts& cnt, uint32_t& n_used, const LevelArgs& a) {
   using Rec = typename RecOf<R>::T;
   const R c1s = SGN < 0 ? -c1 : c1;   // chi exponent slope in the signed distance
-  auto step = [&](const Rec& L, int32_t j, bool tail) {
-    const R d = R(X - L.k0) - R(L.frac);
-    bool in_reg;
-    if (SGN > 0) in_reg = d >= ra && d < rbx;
-    else if (SGN < 0) in_reg = d <= -ra && d > -rbx;
-    else in_reg = fabs(d) < rbx;
-    in_reg = in_reg && L.s <= smax;
-    if (tail) in_reg = in_reg && j < j1;
-    if constexpr (SURR) {
-      const float g = g_surr<COUNT>(d, L, sp, j, G, a, in_reg, cnt);
-      acc += in_reg ? g : R(0);
-    } else {
-      (void)a;
-      const R g = shape_fast<R, COUNT>(d, L, sp, j, G, in_reg, cnt);
-      R chi;
-      if constexpr (CHIM == 0) chi = R(1);
-      else if constexpr (CHIM == 1) chi = fast_exp2<R>(fma(c1s, SGN == 0 ? fabs(d) : d, c0));
-      else chi = chi_any<R>(fabs(d), G);
-      acc += in_reg ? g * chi : R(0);
+  const R chi_step = (CHIM == 1 && SGN != 0) ? fast_exp2<R>(c1s * R(rl)) : R(1);
+  auto step = [&](const Rec& L, int32_t j) {
+    const int32_t n0 = X0 - L.k0;
+    const R fr = R(L.frac);
+    const bool lok = L.s <= smax && j < j1;
+    R chi_run = R(1);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const R d = R(n0 + k * rl) - fr;
+      bool in_reg;
+      if (SGN > 0) in_reg = d >= ra && d < rbx;
+      else if (SGN < 0) in_reg = d <= -ra && d > -rbx;
+      else in_reg = fabs(d) < rbx;
+      in_reg = in_reg && lok && ((act >> k) & 1u);
+      if constexpr (SURR) {
+        const float g = g_surr<COUNT>(d, L, sp, j, G, a, in_reg, cnt);
+        acc[k] += in_reg ? g : R(0);
+      } else {
+        (void)a;
+        const R g = shape_fast<R, COUNT>(d, L, sp, j, G, in_reg, cnt);
+        R chi;
+        if constexpr (CHIM == 0) {
+          chi = R(1);
+        } else if constexpr (CHIM == 1 && SGN != 0) {
+          chi_run = (k == 0) ? fast_exp2<R>(fma(c1s, d, c0)) : chi_run * chi_step;
+          chi = chi_run;
+        } else if constexpr (CHIM == 1) {
+          chi = fast_exp2<R>(fma(c1s, fabs(d), c0));
+        } else {
+          chi = chi_any<R>(fabs(d), G);
+        }
+        acc[k] += in_reg ? g * chi : R(0);
+      }
+      if (COUNT && in_reg) n_used++;
     }
-    if (COUNT && in_reg) n_used++;
   };
   int32_t j = j0 + slice;
   Rec La = load_rec(rec, j < j1 ? j : j1 - 1);
-  int32_t J = j0;
-  // full chunks of 2S lines: every lane's line exists
-  for (; J + 2 * S <= j1; J += 2 * S) {
-    const Rec Lb = load_rec(rec, J + S + slice);
-    step(La, J + slice, false);
-    La = load_rec(rec, J + 2 * S + slice < j1 ? J + 2 * S + slice : j1 - 1);
-    step(Lb, J + S + slice, false);
-    if (COUNT && (threadIdx.x & 63) == 0) cnt.iters += 2;
-  }
-  if (J < j1) {
+  for (int32_t J = j0; J < j1; J += 2 * S) {
     const Rec Lb = load_rec(rec, J + S + slice < j1 ? J + S + slice : j1 - 1);
-    step(La, J + slice, true);
+    step(La, J + slice);
+    La = load_rec(rec, J + 2 * S + slice < j1 ? J + 2 * S + slice : j1 - 1);
     if (COUNT && (threadIdx.x & 63) == 0) cnt.iters++;
     if (J + S < j1) {
-      step(Lb, J + S + slice, true);
+      step(Lb, J + S + slice);
       if (COUNT && (threadIdx.x & 63) == 0) cnt.iters++;
     }
   }
 }
 
 // scan_fast with the window's chi mode as a template argument
-template <typename R, bool COUNT, int SGN, bool SURR>
+template <typename R, bool COUNT, int SGN, bool SURR, int K>
 __device__ __forceinline__ void scan_fast_chi(const typename RecOf<R>::T* __restrict__ rec, const R* __restrict__ sp,
-                                              int32_t j0, int32_t j1, int S, int slice, int32_t X, R ra, R rbx,
-                                              int smax, bool chi_none, bool chi_mixed, R c0, R c1, const Geometry& G,
-                                              R& acc, Counts& cnt, uint32_t& n_used, const LevelArgs& a) {
+                                              int32_t j0, int32_t j1, int S, int slice, int32_t X0, int32_t rl,
+                                              uint32_t act, R ra, R rbx, int smax, bool chi_none, bool chi_mixed,
+                                              R c0, R c1, const Geometry& G, R* acc, Counts& cnt, uint32_t& n_used,
+                                              const LevelArgs& a) {
   if (chi_mixed)
-    scan_fast<R, COUNT, SGN, SURR, 2>(rec, sp, j0, j1, S, slice, X, ra, rbx, smax, c0, c1, G, acc, cnt, n_used, a);
+    scan_fast<R, COUNT, SGN, SURR, 2, K>(rec, sp, j0, j1, S, slice, X0, rl, act, ra, rbx, smax, c0, c1, G, acc, cnt,
+                                         n_used, a);
   else if (chi_none)
-    scan_fast<R, COUNT, SGN, SURR, 0>(rec, sp, j0, j1, S, slice, X, ra, rbx, smax, c0, c1, G, acc, cnt, n_used, a);
+    scan_fast<R, COUNT, SGN, SURR, 0, K>(rec, sp, j0, j1, S, slice, X0, rl, act, ra, rbx, smax, c0, c1, G, acc, cnt,
+                                         n_used, a);
   else
-    scan_fast<R, COUNT, SGN, SURR, 1>(rec, sp, j0, j1, S, slice, X, ra, rbx, smax, c0, c1, G, acc, cnt, n_used, a);
+    scan_fast<R, COUNT, SGN, SURR, 1, K>(rec, sp, j0, j1, S, slice, X0, rl, act, ra, rbx, smax, c0, c1, G, acc, cnt,
+                                         n_used, a);
+}
+
+// Fast region pass of one wavefront tile of nw = 2^lnw nodes: groups of K
+// consecutive nodes per lane, lane = group * S + slice, S = 64 K / nw line
+// slices.  iv->fast_ok: 2 = the own region of lines starting at l (one
+// window), 1 = the annulus [b_(l-1), b_l) of lines starting below l (two
+// sides).  The line windows (my_j) are fetched by the caller.
+template <typename R, bool COUNT, bool SURR, int K>
+__device__ __forceinline__ void region_fast(const Geometry& G, const LevelArgs& a, int l, int layer, int lnw,
+                                            int64_t rel0, int tile_left, const IntervalSet* iv, R* lds_acc,
+                                            int64_t item_first, int32_t my_j, Counts& cnt, uint32_t& n_used) {
+  using Rec = typename RecOf<R>::T;
+  constexpr int lK = K == 4 ? 2 : (K == 2 ? 1 : 0);
+  const int lane = threadIdx.x & 63;
+  const int lS = 6 - (lnw - lK);
+  const int S = 1 << lS;
+  const int node0 = (lane >> lS) * K;
+  const int slice = lane & (S - 1);
+  const int32_t rl = G.r[l];
+  const Rec* rec = reinterpret_cast<const Rec*>(a.rec) + (int64_t)layer * a.n_lines;
+  const R* sp = reinterpret_cast<const R*>(a.csp) + (int64_t)layer * a.n_lines;
+  const int64_t m0 = G.lo[l] + rel0 + node0;
+  const int32_t X0 = (int32_t)(m0 * rl);
+  uint32_t act = 0;
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+    if (rel0 + node0 + k < G.n[l] && node0 + k < tile_left) act |= 1u << k;
+  R acc[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) acc[k] = R(0);
+  const bool chi_mixed = iv->fchi_mixed != 0;
+  const bool chi_none = !chi_mixed && iv->fc0 == 0.0 && iv->fc1 == 0.0;
+  const R c0 = R(iv->fc0), c1 = R(iv->fc1);
+  const int smax = uniform(iv->fast_need_s) ? l : kLevels;
+  const R rbx = sizeof(R) == 4 ? R(iv->rbx32) : R(iv->rbx64);
+  if (uniform(iv->fast_ok) == 2) {
+    const int32_t j0 = uniform(__shfl(my_j, 0)), j1 = uniform(__shfl(my_j, 1));
+    if (j0 < j1)
+      scan_fast_chi<R, COUNT, 0, SURR, K>(rec, sp, j0, j1, S, slice, X0, rl, act, R(0), rbx, smax, chi_none,
+                                          chi_mixed, c0, c1, G, acc, cnt, n_used, a);
+  } else {
+    const R ra = sizeof(R) == 4 ? R(iv->ra32) : R(iv->ra64);
+    for (int side = 0; side < 2; ++side) {
+      const int32_t j0 = uniform(__shfl(my_j, 2 * side)), j1 = uniform(__shfl(my_j, 2 * side + 1));
+      if (j0 >= j1) continue;
+      if (side == 0)
+        scan_fast_chi<R, COUNT, 1, SURR, K>(rec, sp, j0, j1, S, slice, X0, rl, act, ra, rbx, smax, chi_none,
+                                            chi_mixed, c0, c1, G, acc, cnt, n_used, a);
+      else
+        scan_fast_chi<R, COUNT, -1, SURR, K>(rec, sp, j0, j1, S, slice, X0, rl, act, ra, rbx, smax, chi_none,
+                                             chi_mixed, c0, c1, G, acc, cnt, n_used, a);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    R v = acc[k];
+    for (int o = S >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if (((act >> k) & 1u) && slice == 0) lds_acc[m0 + k - G.lo[l] - item_first] = v;
+  }
 }
 
 
@@ -869,41 +946,26 @@ __device__ __forceinline__ void region_tile(const Geometry& G, const LevelArgs& 
     }
   }
   const int32_t my_j = (lane < 2 * nws) ? bk[my_bucket] : 0;
-  R acc = R(0);
   if (iv->fast_ok && G.shape != MARFA_SHAPE_DOPPLER) {
-    const bool chi_mixed = iv->fchi_mixed != 0;
-    const bool chi_none = !chi_mixed && iv->fc0 == 0.0 && iv->fc1 == 0.0;
-    const R c0 = R(iv->fc0), c1 = R(iv->fc1);
-    const int smax = uniform(iv->fast_need_s) ? l : kLevels;
-    if (uniform(iv->fast_ok) == 2) {
-      // no line starts below l: the own region, one window
-      const R rbx = active ? (sizeof(R) == 4 ? R(iv->rbx32) : R(iv->rbx64)) : R(-1);
-      const int32_t j0 = uniform(__shfl(my_j, 0)), j1 = uniform(__shfl(my_j, 1));
-      if (j0 < j1) {
-        scan_fast_chi<R, COUNT, 0, SURR>(rec, sp, j0, j1, S, slice, X, R(0), rbx, smax, chi_none, chi_mixed, c0, c1, G,
-                                     acc, cnt, n_used, a);
+    // K nodes per lane (up to 4, fewer for narrow tiles) in the single-
+    // precision plain kernel; one elsewhere (the counting, learned-shape and
+    // double-precision kernels are not timed and stay small)
+    if constexpr (sizeof(R) == 4 && !COUNT && !SURR) {
+      if (lnw >= 2) {
+        region_fast<R, COUNT, SURR, 4>(G, a, l, layer, lnw, rel0, tile_left, iv, lds_acc, item_first, my_j, cnt,
+                                       n_used);
+        return;
       }
-      for (int o = S >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-      if (active && slice == 0) lds_acc[m - G.lo[l] - item_first] = acc;
-      return;
+      if (lnw == 1) {
+        region_fast<R, COUNT, SURR, 2>(G, a, l, layer, lnw, rel0, tile_left, iv, lds_acc, item_first, my_j, cnt,
+                                       n_used);
+        return;
+      }
     }
-    // every line with a region here starts below l: one annulus window, two sides
-    const R ra = active ? (sizeof(R) == 4 ? R(iv->ra32) : R(iv->ra64)) : R(INFINITY);
-    const R rbx = sizeof(R) == 4 ? R(iv->rbx32) : R(iv->rbx64);
-    for (int side = 0; side < 2; ++side) {
-      const int32_t j0 = uniform(__shfl(my_j, 2 * side)), j1 = uniform(__shfl(my_j, 2 * side + 1));
-      if (j0 >= j1) continue;
-      if (side == 0)
-        scan_fast_chi<R, COUNT, 1, SURR>(rec, sp, j0, j1, S, slice, X, ra, rbx, smax, chi_none, chi_mixed, c0, c1, G,
-                                     acc, cnt, n_used, a);
-      else
-        scan_fast_chi<R, COUNT, -1, SURR>(rec, sp, j0, j1, S, slice, X, ra, rbx, smax, chi_none, chi_mixed, c0, c1, G,
-                                      acc, cnt, n_used, a);
-    }
-    for (int o = S >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-    if (active && slice == 0) lds_acc[m - G.lo[l] - item_first] = acc;
+    region_fast<R, COUNT, SURR, 1>(G, a, l, layer, lnw, rel0, tile_left, iv, lds_acc, item_first, my_j, cnt, n_used);
     return;
   }
+  R acc = R(0);
   int ws_i = 0;
   for (int k = 0; k < n_iv; ++k) {
     const R ra = R(iv->a[k]), rb = R(iv->b[k]);

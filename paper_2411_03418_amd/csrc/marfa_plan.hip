@@ -963,11 +963,12 @@ extern "C" marfa_status marfa_plan_tune(marfa_plan* p, void* out, int64_t stride
     for (const Tile& t : all)
       if (t.level == l) lv.push_back(t);
     if (lv.empty()) continue;
+    // every tile width (the time is not unimodal in the width: the lanes
+    // take 1, 2 or 4 nodes each depending on it)
     const int cur = p->G.lnw[l];
     int best_lnw = cur;
     float best = INFINITY;
-    for (int c = cur - 1; c <= cur + 1; ++c) {
-      if (c < 0 || c > 6) continue;
+    for (int c = 0; c <= 6; ++c) {
       p->G.lnw[l] = c;
       float ms = 0.f;
       st = time_level(p, lv, p->grid, out, stride, s, &ms);
