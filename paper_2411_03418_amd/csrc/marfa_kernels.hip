@@ -56,7 +56,7 @@ template <> struct RecOf<double> { using T = LineRec64; };
 // Wing series cut and the |z|^2 above which it replaces the rational core.
 template <typename R> struct Prec;
 template <> struct Prec<float> {
-  static constexpr float kEps = 1e-7f;
+  static constexpr float kEps = 1e-6f;
   static constexpr float kZ2 = 36.0f;
   static constexpr int kTerms = 12;
 };
@@ -468,7 +468,9 @@ template <> __device__ __forceinline__ double fast_exp2<double>(double x) { retu
 // while some live lane has (2k+1)!! e^k >= eps, i.e. e >= thr(k) with
 // thr(k) = (eps / (2k+1)!!)^(1/k), computed at compile time (Newton's method
 // for the k-th root).  The core takes |z| < 6 (FP32) / 8 (FP64); at |z| = 6
-// the FP32 series needs 8 terms for 1e-7.
+// the FP32 series needs 6 terms for 1e-6 (a cut well under the 3e-5 the
+// single-precision path is held to, and common to every pass, so it cancels
+// between a coarse sum and the band correction that removes it).
 constexpr double ct_pow(double x, int n) {
   double r = 1.0;
   for (int i = 0; i < n; ++i) r *= x;
@@ -488,12 +490,12 @@ template <typename R> struct Series;
 template <> struct Series<float> {
   static constexpr int kMax = 10;
   static constexpr float thr[kMax + 1] = {
-      0.f, (float)ct_series_thr(1e-7, 1), (float)ct_series_thr(1e-7, 2), (float)ct_series_thr(1e-7, 3),
-      (float)ct_series_thr(1e-7, 4), (float)ct_series_thr(1e-7, 5), (float)ct_series_thr(1e-7, 6),
-      (float)ct_series_thr(1e-7, 7), (float)ct_series_thr(1e-7, 8), (float)ct_series_thr(1e-7, 9),
-      (float)ct_series_thr(1e-7, 10)};
+      0.f, (float)ct_series_thr(1e-6, 1), (float)ct_series_thr(1e-6, 2), (float)ct_series_thr(1e-6, 3),
+      (float)ct_series_thr(1e-6, 4), (float)ct_series_thr(1e-6, 5), (float)ct_series_thr(1e-6, 6),
+      (float)ct_series_thr(1e-6, 7), (float)ct_series_thr(1e-6, 8), (float)ct_series_thr(1e-6, 9),
+      (float)ct_series_thr(1e-6, 10)};
 };
-static_assert(Series<float>::thr[2] > 8.1e-5f && Series<float>::thr[2] < 8.2e-5f, "sqrt(1e-7 / 15)");
+static_assert(Series<float>::thr[2] > 2.5e-4f && Series<float>::thr[2] < 2.6e-4f, "sqrt(1e-6 / 15)");
 template <> struct Series<double> { static constexpr int kMax = 60; };
 
 // chi of Eq.(10) without branches: exp2(c0 + c1 |d|) with the piece chosen by selects
