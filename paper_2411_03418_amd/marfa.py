@@ -421,12 +421,18 @@ def ptbin_name(layer_number: int) -> str:
 
 
 def write_pt_table(out, directory, nu_begin, stream=None) -> list:
-    """One .ptbin file per layer (rows of out), named by 1-based layer number."""
+    """One .ptbin file per layer (rows of out), named by 1-based layer number.
+    Records hold single precision (Appendix A): a double-precision output is
+    rounded to float32 on the device first."""
     os.makedirs(directory, exist_ok=True)
     paths = []
     for i in range(out.shape[0]):
+        row = out[i]
+        if not isinstance(row, np.ndarray):
+            import torch
+            row = row.to(torch.float32).contiguous()
         p = os.path.join(directory, ptbin_name(i + 1))
-        write_ptbin(p, out[i], nu_begin, truncate=True, stream=stream)
+        write_ptbin(p, row, nu_begin, truncate=True, stream=stream)
         paths.append(p)
     return paths
 

@@ -338,6 +338,26 @@ def test_long_cutoff_5pt(fp64):
     assert eg < (FP64_VS_GRID if fp64 else FP32_VS_GRID)
 
 
+def test_autotune_keeps_parity_5pt():
+    lines = synth.make_lines(3000, 930.0, 1090.0, 31, shift=True)
+    layers = synth.pt_table(3)
+    req = dict(nu_begin=1000.0, nu_end=1013.5, cutoff=60.0, chi="tonkov", prune=1e-6, stencil=5, R=24)
+    M = marfa()
+    plan = M.Plan(lines, layers, device=0, **req)
+    out = torch.empty((plan.n_layers, plan.points), dtype=torch.float32, device="cuda:0")
+    tiles = plan.tune(out=out)
+    got = plan.execute(out=out)
+    torch.cuda.synchronize()
+    got = got.double().cpu().numpy()
+    plan.close()
+    o = _oreq(req)
+    for i in range(layers.shape[0]):
+        ref_g = O.grid(lines, layers[i], threads=THREADS, **o)
+        eg = rel_err(got[i], ref_g)
+        print(f"5-point tuned {tiles['wave_nodes']} layer {i}: vs grid {eg:.2e}")
+        assert eg < FP32_VS_GRID
+
+
 def test_absorption_coefficient_output():
     lines = synth.make_lines(300, 980.0, 1030.0, 32)
     lay = [0.8, 280.0, 0.2, 0.0]

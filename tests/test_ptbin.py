@@ -170,3 +170,18 @@ def test_linedb_errors(tmp_path):
     with pytest.raises(M.MarfaError) as e:
         M.read_line_db(str(r), first=1, count=2)
     assert e.value.status == M.E_INVALID
+
+
+@pytest.mark.gpu
+def test_double_precision_output_rounds_to_float32_records(tmp_path):
+    torch = pytest.importorskip("torch")
+    from paper_2411_03418_amd import synth
+    lines = synth.make_lines(200, 990.0, 1030.0, 43)
+    plan = M.Plan(lines, synth.pt_table(2), nu_begin=1000.0, nu_end=1010.0, cutoff=25.0, fp64=True, device=0)
+    out = plan.execute()
+    torch.cuda.synchronize()
+    host = out.cpu().numpy()
+    paths = M.write_pt_table(out, str(tmp_path), 1000.0)
+    plan.close()
+    for i, p in enumerate(paths):
+        assert np.array_equal(read_record(p, 100), host[i].astype(np.float32))
