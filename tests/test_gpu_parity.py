@@ -274,7 +274,7 @@ def test_centres_within_rounding_of_a_node(tiles):
 FIVE = dict(stencil=5, R=12)
 
 
-@pytest.mark.parametrize("case", [ONE_LINE[i] for i in (0, 1, 2, 3, 5, 6, 8, 10)])
+@pytest.mark.parametrize("case", ONE_LINE)
 @pytest.mark.parametrize("fp64", [False, True])
 def test_one_line_parity_5pt(case, fp64):
     L, lay = _one(case["nu0"], case["gamma"], p=case.get("p", 1.0), T=case.get("T", 296.0))
