@@ -217,6 +217,71 @@ def test_intensity_temperature_invariants():
     assert abs(a / b - 0.5 / (296 / 400.0)) < 1e-12
 
 
+def _emission_factor(nu0, T, E=0.0):
+    """S(T) / S296 with the partition ratio and the Boltzmann factor divided out:
+    the stimulated-emission factor of the line-strength temperature law."""
+    c2 = 1.4387769
+    L = _lines1(nu0=nu0, S296=1e-20, E_lower=E)
+    S = O.line_state(L, (1.0, T, 1.0, 0.0), 0)["S"]
+    return S / float(np.float32(1e-20)) / (296.0 / T) / math.exp(-c2 * float(np.float32(E)) * (1 / T - 1 / 296.0))
+
+
+@pytest.mark.parametrize("T", [150.0, 250.0, 400.0, 740.0])
+def test_emission_factor_classical_limit_is_continuous(T):
+    # As nu0 -> 0+ the factor tends to its classical limit 296/T (hc nu0 << k T);
+    # at nu0 = 0 the oracle takes that limit directly.  A T <-> 296 swap in the
+    # ratio sends the nu0 > 0 branch to T/296 instead.
+    lim = _emission_factor(0.0, T)
+    assert abs(lim - 296.0 / T) < 1e-14
+    for nu in (1e-9, 1e-6, 1e-4):
+        f = _emission_factor(nu, T)
+        assert abs(f / lim - 1) < 2e-9 + 1.5 * 1.4387769 * nu * abs(1 / T - 1 / 296.0), (nu, f, lim)
+
+
+def test_emission_factor_direction_and_quantum_limit():
+    # Stimulated emission removes more absorption at higher T: the factor falls
+    # as T rises, lies between the classical limit 296/T (nu0 -> 0) and 1
+    # (hc nu0 >> k T), and is exactly 1 at the reference temperature.
+    for nu in (0.5, 10.0, 100.0, 700.0):
+        fs = [_emission_factor(nu, T) for T in (150.0, 200.0, 296.0, 400.0, 740.0)]
+        assert all(a > b for a, b in zip(fs[:-1], fs[1:])), (nu, fs)
+        assert abs(fs[2] - 1.0) < 1e-15
+        for T, f in zip((150.0, 200.0, 296.0, 400.0, 740.0), fs):
+            lo, hi = sorted((1.0, 296.0 / T))
+            assert lo - 1e-15 <= f <= hi + 1e-15, (nu, T, f)
+    # 100 cm^-1 at 150 K and 740 K: strongly inside the interval (the factor
+    # matters there), and monotone in nu0 towards 1
+    f150, f740 = _emission_factor(100.0, 150.0), _emission_factor(100.0, 740.0)
+    assert 1.2 < f150 < 296.0 / 150.0 - 0.3 and 296.0 / 740.0 + 0.02 < f740 < 0.6
+    prev = _emission_factor(1.0, 740.0)
+    for nu in (10.0, 100.0, 1000.0, 10000.0):
+        f = _emission_factor(nu, 740.0)
+        assert prev < f <= 1.0
+        prev = f
+    assert abs(_emission_factor(40000.0, 740.0) - 1.0) < 1e-12
+
+
+def test_lorentz_width_temperature_law():
+    # gamma_L scales as (296/T)^n_air: it falls as T rises for n_air > 0, and
+    # doubling T from 296 K divides it by 2^n_air exactly (p fixed).
+    L = _lines1(nu0=1500.0, gamma_air=0.07, gamma_self=0.07)
+    g = [O.line_state(L, (1.0, T, 0.0, 0.0), 0)["gamma_L"] for T in (150.0, 296.0, 592.0, 740.0)]
+    assert g[0] > g[1] > g[2] > g[3]
+    assert abs(g[2] / g[1] - 2.0 ** -0.75) < 1e-15
+    assert abs(g[0] / g[1] - (296.0 / 150.0) ** 0.75) < 1e-14
+    # n_air = 0: no temperature dependence; n_air = 1: inverse proportionality
+    L.n_air[:] = 0.0
+    assert O.line_state(L, (1.0, 592.0, 0.0, 0.0), 0)["gamma_L"] == O.line_state(L, (1.0, 296.0, 0.0, 0.0), 0)["gamma_L"]
+    L.n_air[:] = 1.0
+    a = O.line_state(L, (1.0, 592.0, 0.0, 0.0), 0)["gamma_L"]
+    b = O.line_state(L, (1.0, 296.0, 0.0, 0.0), 0)["gamma_L"]
+    assert abs(a / b - 0.5) < 1e-15
+    # pressure broadening is linear in p at fixed T and mixing
+    c = O.line_state(L, (3.0, 400.0, 0.0, 0.0), 0)["gamma_L"]
+    d = O.line_state(L, (1.0, 400.0, 0.0, 0.0), 0)["gamma_L"]
+    assert abs(c / d - 3.0) < 1e-14
+
+
 def test_number_density_loschmidt():
     # n(273.15 K, 1 atm) = Loschmidt constant 2.686780111e19 cm^-3 (CODATA 2018)
     assert abs(O.number_density((1.0, 273.15, 1.0, 0.0)) / 2.686780111e19 - 1) < 1e-9
