@@ -158,6 +158,7 @@ def surrogate_leg(args):
     ms_plain = timed_steps(plan, out, 3, 1)
     plain = out.clone()
     plan.set_surrogate(S)
+    plan.set_eval("surrogate")
     ms_surr = timed_steps(plan, out, args.surrogate_steps, 1)
     dev = rel_dev(plain, out)
     _, t = plan.execute_timed(out=out)

@@ -84,9 +84,11 @@ typedef struct {
   int32_t shape;              /* marfa_shape */
   int32_t chi;                /* marfa_chi */
   int32_t out_kind;           /* marfa_output */
-  int32_t eval;               /* MARFA_EVAL_PLAIN; MARFA_EVAL_SURROGATE is refused here
-                                 (MARFA_E_UNSUPPORTED): attach a trained network to a
-                                 plain plan with marfa_plan_set_surrogate */
+  int32_t eval;               /* marfa_eval: MARFA_EVAL_PLAIN evaluates the line shapes
+                                 directly; MARFA_EVAL_SURROGATE through the learned line
+                                 shape attached with marfa_plan_set_surrogate (the execute
+                                 calls return MARFA_E_UNSUPPORTED while none is attached).
+                                 marfa_plan_set_eval switches it later. */
   double prune_rel;
   double R;
   int32_t level_table;
@@ -252,7 +254,10 @@ typedef struct {
 marfa_status marfa_surrogate_create(marfa_surrogate** out, int32_t chi, double cutoff, uint64_t seed,
                                     int32_t device);
 /* Replace / read the FP32 parameters (host arrays of n = 12801 values);
- * setting them resets the optimizer state.  Synchronous. */
+ * setting them resets the optimizer state.  Synchronous: set_params first
+ * waits for all work already enqueued on the surrogate's device (plans that
+ * evaluate with the old weights finish with them), then returns once the new
+ * weights are in place. */
 marfa_status marfa_surrogate_set_params(marfa_surrogate* s, const float* params, int64_t n);
 marfa_status marfa_surrogate_get_params(const marfa_surrogate* s, float* params, int64_t n);
 /* Network output t for n samples: X_dev [n][3] features, out_dev [n], both
@@ -270,19 +275,27 @@ marfa_status marfa_surrogate_loss_grad(marfa_surrogate* s, const float* X_dev, c
 marfa_status marfa_surrogate_make_samples(marfa_surrogate* s, const marfa_sample_cfg* c, uint64_t seed, int64_t n,
                                           float* X_dev, float* T_dev, void* hip_stream);
 /* Draw samples and train on the device (forward, backward and Adam kernels);
- * synchronous; fills *report and marks the network trained. */
+ * synchronous (like set_params it first waits for all work enqueued on the
+ * device); fills *report and marks the network trained. */
 marfa_status marfa_surrogate_train(marfa_surrogate* s, const marfa_sample_cfg* c, const marfa_train_cfg* cfg,
                                    marfa_train_report* report);
 void marfa_surrogate_destroy(marfa_surrogate* s);
 
-/* Evaluate the plan's line shapes with a trained surrogate (NULL: the plain
- * line shape again).  Pairs outside the trained domain (y outside
- * [1e-4, 1e3] or |x| above the report's x_max) take the plain line shape.
- * Requires a single-precision Voigt plan with the surrogate's chi and
- * cut-off.  The surrogate must outlive its use by the plan.  Errors:
- * MARFA_E_INVALID (mismatch), MARFA_E_UNSUPPORTED (untrained network, a
- * cut-off under two coarsest steps). */
+/* Attach a trained surrogate to a plan (NULL detaches it).  A plan whose
+ * eval is MARFA_EVAL_SURROGATE evaluates its line shapes with it; pairs
+ * outside the trained domain (y outside [1e-4, 1e3] or |x| above the
+ * report's x_max) take the plain line shape.  Requires a single-precision
+ * Voigt plan with the surrogate's chi and cut-off.  The surrogate must
+ * outlive its use by the plan.  Waits for the device's queued work before
+ * rebuilding the plan's graphs.  Errors: MARFA_E_INVALID (mismatch),
+ * MARFA_E_UNSUPPORTED (untrained network, a cut-off under two coarsest
+ * steps). */
 marfa_status marfa_plan_set_surrogate(marfa_plan* plan, const marfa_surrogate* s);
+
+/* Switch the plan's line-shape evaluation (marfa_eval, as the request's
+ * eval field).  Waits for the device's queued work before rebuilding the
+ * plan's graphs.  Errors: MARFA_E_INVALID for an unknown value. */
+marfa_status marfa_plan_set_eval(marfa_plan* plan, int32_t eval);
 
 /* Spectral line database file (Appendix B): packed little-endian records of
  * 36 bytes, one per line, in this order: nu0 (float64), S296, gamma_air,

@@ -17,6 +17,12 @@ constexpr int kWave = 64;        // CDNA wavefront
 constexpr int kWeidemanN32 = 28; // rational-series length, single-precision path (1.5e-7 for |z| < 6)
 constexpr int kWeidemanN64 = 48; // rational-series length, double-precision path
 constexpr int kBucketPerCm = 256; // line-index buckets per cm^-1 (8 finest steps)
+// per-device table of Weideman coefficients: single-precision path, double-
+// precision path, then the two scale parameters L
+constexpr int kWeidOff32 = 0;
+constexpr int kWeidOff64 = kWeidOff32 + kWeidemanN32 + 1;
+constexpr int kWeidOffL = kWeidOff64 + kWeidemanN64 + 1;
+constexpr int kWeidTotal = kWeidOffL + 2;
 
 // Lattice geometry, identical for every layer.  Positions are in units of the
 // finest step h0 = 2^-11 cm^-1 ("fine units"); node m of level l sits at
@@ -43,6 +49,7 @@ struct Geometry {
   int32_t pad2;
   // Tonkov chi pieces as exp2(chi_c0[i] + chi_c1[i] |d|), |d| in cm (host-computed)
   double chi_c0[3], chi_c1[3];
+  const double* weid;        // the device's Weideman table (kWeidTotal values)
 };
 
 // Region windows (|d| in fine units, closed, disjoint) scanned at one level
@@ -178,7 +185,8 @@ struct LevelArgs {
   MlpDev mlp;
 };
 
-hipError_t upload_weideman(const double* a32, const double* a64, const double* L2);
+// the Weideman table of a device prepared by marfa_use_device (device memory)
+const double* device_weideman(int device);
 void launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t s);
 void launch_fill_u32(unsigned int* p, int64_t n, unsigned int v, hipStream_t s);
 struct PrepArgs {
@@ -204,13 +212,15 @@ struct MlpSampleCfg {
   double cutoff;           // [cm^-1]
   int32_t chi, pad;
 };
-void launch_mlp_samples(const MlpSampleCfg& c, uint64_t seed, int64_t n, float* X, float* T, hipStream_t s);
+void launch_mlp_samples(const MlpSampleCfg& c, uint64_t seed, int64_t n, float* X, float* T, const double* wd,
+                        hipStream_t s);
 // error text of the calling thread, and device set-up (Weideman tables)
 marfa_status marfa_set_error(marfa_status st, const char* msg);
 marfa_status marfa_use_device(int device);
 void launch_rank(const LineIn& in, const double* layers, int nL, const double* span, int32_t* perm, hipStream_t s);
 void launch_cascade(const Geometry& G, int nL, void* A, void* out, int64_t stride, const double* scale, bool fp64,
                     hipStream_t s);
-void launch_voigt_eval(int64_t n, const double* x, const double* y, double* out, bool fp64, hipStream_t s);
+void launch_voigt_eval(int64_t n, const double* x, const double* y, double* out, bool fp64, const double* wd,
+                       hipStream_t s);
 
 }  // namespace marfa

@@ -27,170 +27,9 @@
 #include <math.h>
 #include <stdint.h>
 
-#include <type_traits>
-
-#include "marfa_internal.h"
+#include "marfa_device.h"
 
 namespace marfa {
-
-// physical constants (CODATA 2018) and HITRAN reference temperature
-constexpr double kC2 = 1.438776877;           // hc/k_B [cm K]
-constexpr double kTref = 296.0;
-constexpr double kBoltzmann = 1.380649e-23;   // [J/K]
-constexpr double kNA = 6.02214076e23;         // [1/mol]
-constexpr double kCLight = 299792458.0;       // [m/s]
-constexpr double kAtmPa = 101325.0;
-constexpr double kLn2d = 0.693147180559945309417;
-constexpr double kInvPi = 0.318309886183790671538;
-constexpr double kInvSqrtPi = 0.564189583547756286948;
-constexpr double kH0 = 1.0 / 2048.0;
-
-__constant__ double c_weid32[kWeidemanN32 + 1];
-__constant__ double c_weid64[kWeidemanN64 + 1];
-__constant__ double c_weidL[2];
-
-template <typename R> struct RecOf;
-template <> struct RecOf<float> { using T = LineRec32; };
-template <> struct RecOf<double> { using T = LineRec64; };
-
-// Wing series cut and the |z|^2 above which it replaces the rational core.
-template <typename R> struct Prec;
-template <> struct Prec<float> {
-  static constexpr float kEps = 1e-6f;
-  static constexpr float kZ2 = 36.0f;
-  static constexpr int kTerms = 12;
-};
-template <> struct Prec<double> {
-  static constexpr double kEps = 1e-17;
-  static constexpr double kZ2 = 64.0;
-  static constexpr int kTerms = 60;
-};
-
-// ------------------------------------------------------------------
-// line shapes
-// ------------------------------------------------------------------
-
-// Re w(z) for |z| small, w the Faddeeva function, by Weideman's rational
-// series in Z = (L+iz)/(L-iz):  w = 1/(sqrt(pi)(L-iz)) + 2/(L-iz)^2 sum_n a_n Z^(n-1).
-// Evaluated in double precision in both paths (the real part is small next to
-// |w| near the real axis, so single precision would lose it).
-// P(Z) = sum_{n=1..N} a_n Z^(n-1) has real coefficients.  QUAD evaluates it
-// by synthetic division by (X - Z)(X - conj Z) = X^2 - 2 Re Z X + |Z|^2:
-// b_m = a_(m+1) + 2 Re Z b_(m+1) - |Z|^2 b_(m+2), P(Z) = b_0 - b_1 conj(Z),
-// two real FMAs per degree instead of a complex multiply-add (its rounding
-// grows like 1/|arg Z| near the real axis: 1e-9 relative here, used by the
-// single-precision path); otherwise complex Horner.
-template <int N, bool QUAD = false>
-__device__ __forceinline__ double voigt_core(double x, double y, const double* a, double L) {
-  double Ar = L + y, Ai = -x;
-  double inv = 1.0 / (Ar * Ar + Ai * Ai);
-  double iAr = Ar * inv, iAi = -Ai * inv;
-  double Br = L - y, Bi = x;
-  double Zr = Br * iAr - Bi * iAi, Zi = Br * iAi + Bi * iAr;
-  double pr, pim;
-  if constexpr (QUAD) {
-    const double r = 2.0 * Zr, s = -(Zr * Zr + Zi * Zi);
-    double b1 = a[N], b2 = 0.0;
-#pragma unroll
-    for (int m = N - 2; m >= 0; --m) {
-      const double b0 = fma(r, b1, fma(s, b2, a[m + 1]));
-      b2 = b1;
-      b1 = b0;
-    }
-    pr = fma(-b2, Zr, b1);
-    pim = b2 * Zi;
-  } else {
-    pr = a[N];
-    pim = 0.0;
-#pragma unroll
-    for (int n = N - 1; n >= 1; --n) {
-      double tr = fma(pr, Zr, fma(-pim, Zi, a[n]));
-      pim = fma(pr, Zi, pim * Zr);
-      pr = tr;
-    }
-  }
-  double i2r = iAr * iAr - iAi * iAi, i2i = 2.0 * iAr * iAi;
-  return iAr * kInvSqrtPi + 2.0 * (pr * i2r - pim * i2i);
-}
-
-// Voigt far from the core (|z| large): f = Re[i/(pi (d + i g))] times the
-// asymptotic series sum_k (2k-1)!! e^k U_2k(cos th), e = alpha_D^2/(2 ln2 |d+ig|^2),
-// cos^2 th = d^2/(d^2+g^2), U the Chebyshev polynomials of the second kind
-// (Re[i/u^(2k+1)] = g sin((2k+1)th)/(|u|^(2k+2) sin th)).  k = 1 is the
-// 1 + 3/(2x^2) correction of Appendix C.  Returns f and the number of extra terms.
-template <typename R>
-__device__ __forceinline__ R voigt_wing(R dd, R gam, R gam2, R ae, int& terms) {
-  R Q = R(1) / (dd + gam2);
-  R e = ae * Q;
-  R acc = R(1);
-  if (e * R(3) >= Prec<R>::kEps) {
-    R s = dd * Q;
-    R t = R(4) * s - R(2);
-    R ck = R(1), Um = R(-1), U = R(1);
-    for (int k = 1; k <= Prec<R>::kTerms; ++k) {
-      ck *= R(2 * k - 1) * e;
-      R Un = t * U - Um;
-      Um = U;
-      U = Un;
-      acc += ck * U;
-      ++terms;
-      if (ck * R(2 * k + 1) < Prec<R>::kEps) break;
-    }
-  }
-  return gam * Q * R(kInvPi) * acc;
-}
-
-template <typename R>
-__device__ __forceinline__ R tonkov(R a) {
-  // Eq.(10): 1.084 e^{-0.027|d|} on [3,150], 0.208 e^{-0.016|d|} on (150,300],
-  // 0.025 e^{-0.009|d|} above 300, 1 otherwise
-  if (a < R(3)) return R(1);
-  if (a <= R(150)) return R(1.084) * exp(R(-0.027) * a);
-  if (a <= R(300)) return R(0.208) * exp(R(-0.016) * a);
-  return R(0.025) * exp(R(-0.009) * a);
-}
-
-struct Counts {
-  uint32_t core, wing, terms;
-  uint32_t iters;        // wavefront iterations over line windows (lane 0 counts)
-  uint32_t band_iters;   // iterations that ran the band correction
-};
-
-// g(d) = S' F(d) chi(|d|) [|d| <= c], d in fine units
-template <typename R, bool COUNT>
-__device__ __forceinline__ R line_value(R d, const typename RecOf<R>::T& L, R Sp, const Geometry& G, R cfine,
-                                        Counts& cnt) {
-  R ad = fabs(d);
-  if (ad > cfine) return R(0);
-  R dcm = d * R(kH0);
-  R dd = dcm * dcm;
-  R f;
-  if (G.shape == MARFA_SHAPE_LORENTZ) {
-    f = R(L.gam) * R(kInvPi) / (dd + R(L.gam2));
-  } else if (G.shape == MARFA_SHAPE_DOPPLER) {
-    R x = R(L.xs) * dcm;
-    f = R(L.xs) * R(kInvSqrtPi) * exp(-x * x);
-  } else {
-    R x = R(L.xs) * dcm;
-    R y = R(L.xs) * R(L.gam);
-    R z2 = x * x + y * y;
-    if (L.xs == 0 || z2 >= Prec<R>::kZ2) {
-      int terms = 0;
-      f = voigt_wing<R>(dd, R(L.gam), R(L.gam2), R(L.ae), terms);
-      if (COUNT) { cnt.wing++; cnt.terms += terms; }
-    } else {
-      double K;
-      if (sizeof(R) == 4)
-        K = voigt_core<kWeidemanN32, true>(fabs((double)x), (double)y, c_weid32, c_weidL[0]);
-      else
-        K = voigt_core<kWeidemanN64>(fabs((double)x), (double)y, c_weid64, c_weidL[1]);
-      f = R((double)L.xs * kInvSqrtPi * K);
-      if (COUNT) cnt.core++;
-    }
-  }
-  R chi = (G.chi == MARFA_CHI_TONKOV) ? tonkov<R>(ad * R(kH0)) : R(1);
-  return Sp * f * chi;
-}
 
 // ------------------------------------------------------------------
 // fills
@@ -441,934 +280,6 @@ __global__ void k_layer_scale(const double* __restrict__ layers, const unsigned 
 }
 
 // ------------------------------------------------------------------
-// level accumulation
-// ------------------------------------------------------------------
-__device__ __forceinline__ int64_t floor_div(int64_t a, int64_t b) {
-  int64_t q = a / b;
-  if ((a % b != 0) && ((a < 0) != (b < 0))) --q;
-  return q;
-}
-
-// T_l(d) of a line with start level s: zero in the hole of a wing level
-template <typename R, bool COUNT>
-__device__ __forceinline__ R T_level(R d, int l, int s, const typename RecOf<R>::T& L, R Sp, const Geometry& G,
-                                     R cfine, R b_prev, Counts& cnt) {
-  if (l > s && fabs(d) < b_prev) return R(0);
-  return line_value<R, COUNT>(d, L, Sp, G, cfine, cnt);
-}
-
-template <typename R> __device__ __forceinline__ R fast_rcp(R x);
-template <> __device__ __forceinline__ float fast_rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
-template <> __device__ __forceinline__ double fast_rcp<double>(double x) { return 1.0 / x; }
-template <typename R> __device__ __forceinline__ R fast_exp2(R x);
-template <> __device__ __forceinline__ float fast_exp2<float>(float x) { return __builtin_amdgcn_exp2f(x); }
-template <> __device__ __forceinline__ double fast_exp2<double>(double x) { return exp2(x); }
-
-// Wing series of the fast path.  Term k (coefficient (2k-1)!! e^k) is kept
-// while some live lane has (2k+1)!! e^k >= eps, i.e. e >= thr(k) with
-// thr(k) = (eps / (2k+1)!!)^(1/k), computed at compile time (Newton's method
-// for the k-th root).  The core takes |z| < 6 (FP32) / 8 (FP64); at |z| = 6
-// the FP32 series needs 6 terms for 1e-6 (a cut well under the 3e-5 the
-// single-precision path is held to, and common to every pass, so it cancels
-// between a coarse sum and the band correction that removes it).
-constexpr double ct_pow(double x, int n) {
-  double r = 1.0;
-  for (int i = 0; i < n; ++i) r *= x;
-  return r;
-}
-constexpr double ct_root(double a, int k) {
-  double r = 1.0;
-  for (int i = 0; i < 400; ++i) r -= (ct_pow(r, k) - a) / (k * ct_pow(r, k - 1));
-  return r;
-}
-constexpr double ct_series_thr(double eps, int k) {
-  double df = 1.0;
-  for (int i = 1; i <= k; ++i) df *= 2.0 * i + 1.0;
-  return ct_root(eps / df, k);
-}
-template <typename R> struct Series;
-template <> struct Series<float> {
-  static constexpr int kMax = 10;
-  static constexpr float thr[kMax + 1] = {
-      0.f, (float)ct_series_thr(1e-6, 1), (float)ct_series_thr(1e-6, 2), (float)ct_series_thr(1e-6, 3),
-      (float)ct_series_thr(1e-6, 4), (float)ct_series_thr(1e-6, 5), (float)ct_series_thr(1e-6, 6),
-      (float)ct_series_thr(1e-6, 7), (float)ct_series_thr(1e-6, 8), (float)ct_series_thr(1e-6, 9),
-      (float)ct_series_thr(1e-6, 10)};
-};
-static_assert(Series<float>::thr[2] > 2.5e-4f && Series<float>::thr[2] < 2.6e-4f, "sqrt(1e-6 / 15)");
-template <> struct Series<double> { static constexpr int kMax = 60; };
-
-// chi of Eq.(10) without branches: exp2(c0 + c1 |d|) with the piece chosen by selects
-template <typename R>
-__device__ __forceinline__ R chi_any(R ad_fine, const Geometry& G) {
-  if (G.chi != MARFA_CHI_TONKOV) return R(1);
-  const R a = ad_fine * R(kH0);
-  R c0 = R(0), c1 = R(0);
-  c0 = a >= R(3) ? R(G.chi_c0[0]) : c0;
-  c1 = a >= R(3) ? R(G.chi_c1[0]) : c1;
-  c0 = a > R(150) ? R(G.chi_c0[1]) : c0;
-  c1 = a > R(150) ? R(G.chi_c1[1]) : c1;
-  c0 = a > R(300) ? R(G.chi_c0[2]) : c0;
-  c1 = a > R(300) ? R(G.chi_c1[2]) : c1;
-  return fast_exp2<R>(c0 + c1 * a);
-}
-
-// S' F(d) of the rational core, kept out of line: the region scans inline
-// the wing many times over and take the core for few pairs
-template <typename R>
-__device__ __attribute__((noinline)) R core_value(R dcm, R xs, R gam, R sp) {
-  const R x = xs * dcm;
-  const R y = xs * gam;
-  double K;
-  if (sizeof(R) == 4)
-    K = voigt_core<kWeidemanN32, true>(fabs((double)x), (double)y, c_weid32, c_weidL[0]);
-  else
-    K = voigt_core<kWeidemanN64>(fabs((double)x), (double)y, c_weid64, c_weidL[1]);
-  return sp * R((double)xs * kInvSqrtPi * K);
-}
-
-// S' F(d) (without chi and the cut-off) for the Voigt shape (Lorentz: ae = 0):
-// the asymptotic wing series with a wave-uniform number of terms, and the
-// rational core for lanes with |z| < sqrt(kZ2).  `live` marks lanes whose
-// value is used (they alone steer the term count and the core branch).  The
-// wing is A Q sum with A = S' gamma_L / pi and Q = 1/(d^2 + gamma_L^2); the
-// core needs S' itself (sp[j]).
-template <typename R, bool COUNT>
-__device__ __forceinline__ R shape_fast(R d, const typename RecOf<R>::T& L, const R* __restrict__ sp, int32_t j,
-                                        const Geometry& G, bool live, Counts& cnt) {
-  const R dcm = d * R(kH0);
-  const R den = fma(dcm, dcm, R(L.gam2));
-  const R Q = fast_rcp<R>(den);
-  const R e = R(L.ae) * Q;
-  const bool core = e > R(0.5 / Prec<R>::kZ2);     // |z|^2 = 1/(2e) < kZ2
-  // U_2 = 4 d^2 Q - 1 = 3 - 4 gamma^2 Q
-  R U = fma(R(-4) * R(L.gam2), Q, R(3));
-  R sum = fma(e, U, R(1));
-  const bool wing = live && !core;
-  // term k, with coefficient c_k = (2k-1)!! e^k, is kept while some live
-  // wing lane has (2k+1)!! e^k >= eps: e >= thr(k) (FP32), or from the
-  // running coefficient (2k+1)(2k-1) c_(k-1) e >= eps (FP64)
-  const R eps = Prec<R>::kEps;
-  auto more = [&](int k, R ck_prev) -> bool {
-    if constexpr (sizeof(R) == 4) return e >= Series<float>::thr[k];
-    else return R((2 * k + 1) * (2 * k - 1)) * ck_prev * e >= eps;
-  };
-  if (__builtin_amdgcn_ballot_w64(wing && more(2, e))) {
-    const R t = U - R(1);
-    R Um = R(1), ck = e;
-#pragma unroll
-    for (int k = 2; k < Series<R>::kMax; ++k) {
-      ck *= R(2 * k - 1) * e;
-      const R Un = t * U - Um;
-      Um = U;
-      U = Un;
-      sum += ck * U;
-      if (COUNT && wing) cnt.terms++;
-      if (k + 1 >= Series<R>::kMax || !__builtin_amdgcn_ballot_w64(wing && more(k + 1, ck))) break;
-    }
-  }
-  R f = R(L.A) * Q * sum;
-  if (__builtin_amdgcn_ballot_w64(live && core)) {
-    if (live && core) f = core_value<R>(dcm, L.xs, L.gam, sp[j]);
-  }
-  if (COUNT && live) { if (core) cnt.core++; else cnt.wing++; }
-  return f;
-}
-
-// g(d) = S' F(d) chi(|d|) [|d| <= c] for any shape
-template <typename R, bool COUNT>
-__device__ __forceinline__ R g_any(R d, const typename RecOf<R>::T& L, const R* __restrict__ sp, int32_t j,
-                                   const Geometry& G, R cfine, bool live, Counts& cnt) {
-  if (G.shape == MARFA_SHAPE_DOPPLER) return live ? line_value<R, COUNT>(d, L, sp[j], G, cfine, cnt) : R(0);
-  const R ad = fabs(d);
-  const R v = shape_fast<R, COUNT>(d, L, sp, j, G, live && ad <= cfine, cnt) * chi_any<R>(ad, G);
-  return ad <= cfine ? v : R(0);
-}
-
-// S' F(d) chi(|d|) through the learned line shape, for one (line, node) pair
-// per lane; wave-collective (all 64 lanes call it together).  Pairs outside
-// the trained domain that are live use the plain shape.  With A = S'
-// gamma_L / pi and y = xs gamma_L: S' F chi = A sqrt(pi) xs^2 / y Kb e^t.
-template <bool COUNT>
-__device__ float g_surr(float d, const LineRec32& L, const float* __restrict__ sp, int32_t j, const Geometry& G,
-                        const LevelArgs& a, bool live, Counts& cnt) {
-  const float dcm = d * float(kH0);
-  const float x = L.xs * dcm;
-  const float y = L.xs * L.gam;
-  const bool dom = y >= kMlpYMin && y <= kMlpYMax && fabsf(x) <= a.mlp_xmax;
-  float f1, f2, f3;
-  mlp_features(x, dom ? y : 1.0f, fabsf(dcm), a.mlp_inv_c, f1, f2, f3);
-  const float t = mlp_forward_wave(a.mlp, f1, f2, f3);
-  float v = L.A * 1.7724538509055160f * L.xs * L.xs * __builtin_amdgcn_rcpf(dom ? y : 1.0f) * mlp_base(x, y) *
-            __expf(t);
-  v = dom ? v : 0.0f;
-  if (__builtin_amdgcn_ballot_w64(live && !dom)) {
-    const float pv = shape_fast<float, COUNT>(d, L, sp, j, G, live && !dom, cnt) * chi_any<float>(fabsf(d), G);
-    v = dom ? v : pv;
-  }
-  return v;
-}
-
-// g(d) with the cut-off for the band pass, chi given for the jump's
-// neighbourhood (mode 0: 1, 1: one piece exp2(c0 + c1 |d|), 2: any piece)
-template <typename R, bool COUNT, bool SURR>
-__device__ __forceinline__ R g_band(R d, const typename RecOf<R>::T& L, const R* __restrict__ sp, int32_t j,
-                                    const Geometry& G, R cfine, bool live, Counts& cnt, const LevelArgs& a,
-                                    int chi_mode, R c0, R c1) {
-  if (SURR || G.shape == MARFA_SHAPE_DOPPLER) return g_eval<R, COUNT, SURR>(d, L, sp, j, G, cfine, live, cnt, a);
-  const R ad = fabs(d);
-  const R f = shape_fast<R, COUNT>(d, L, sp, j, G, live && ad <= cfine, cnt);
-  R chi;
-  if (chi_mode == 0) chi = R(1);
-  else if (chi_mode == 1) chi = fast_exp2<R>(fma(c1, ad, c0));
-  else chi = chi_any<R>(ad, G);
-  return ad <= cfine ? f * chi : R(0);
-}
-
-// g(d) with the cut-off, plain or learned (wave-collective when SURR)
-template <typename R, bool COUNT, bool SURR>
-__device__ __forceinline__ R g_eval(R d, const typename RecOf<R>::T& L, const R* __restrict__ sp, int32_t j,
-                                    const Geometry& G, R cfine, bool live, Counts& cnt, const LevelArgs& a) {
-  if constexpr (SURR) {
-    const float v = g_surr<COUNT>(d, L, sp, j, G, a, live && fabsf(d) <= cfine, cnt);
-    return fabsf(d) <= cfine ? v : 0.0f;
-  } else {
-    (void)a;
-    return g_any<R, COUNT>(d, L, sp, j, G, cfine, live, cnt);
-  }
-}
-
-// Region pass: scan lines [j0, j1) of one window side (SGN = +1: d > 0,
-// -1: d < 0, 0: both) and add g(d) for every (node, line) pair in the line's
-// region at this level.
-template <typename R, bool COUNT, int SGN, bool SURR>
-__device__ __forceinline__ void scan_region(const typename RecOf<R>::T* __restrict__ rec, const R* __restrict__ sp,
-                                            int32_t j0, int32_t j1,
-                                            int S, int slice, int32_t X, bool active, R ra, R rb, bool chi_one,
-                                            bool chi_mixed, R c0, R c1, int l, const Geometry& G, R cfine,
-                                            R b_prev, R b_cur, R& acc, Counts& cnt, uint32_t& n_used,
-                                            const LevelArgs& a) {
-  using Rec = typename RecOf<R>::T;
-  const bool generic_shape = G.shape == MARFA_SHAPE_DOPPLER;
-  int32_t jn = j0 + slice;
-  Rec Lnext = load_rec(rec, jn < j1 ? jn : j1 - 1);
-  for (int32_t J = j0; J < j1; J += S) {
-    const int32_t j = J + slice;
-    const Rec L = Lnext;
-    jn = j + S;
-    if (J + S < j1) Lnext = load_rec(rec, jn < j1 ? jn : j1 - 1);
-    const R d = R(X - L.k0) - R(L.frac);
-    const R ad = fabs(d);
-    bool in_win = active && j < j1 && ad >= ra && ad <= rb;
-    if (SGN > 0) in_win = in_win && d > R(0);
-    if (SGN < 0) in_win = in_win && d < R(0);
-    const int ls = L.s;
-    const R rlo = (l == ls) ? R(0) : b_prev;
-    const bool in_reg = in_win && ls <= l && ad >= rlo && ad < b_cur && ad <= cfine;
-    R val;
-    if constexpr (SURR) {
-      (void)generic_shape;
-      const float g = g_surr<COUNT>(d, L, sp, j, G, a, in_reg, cnt);
-      val = in_reg ? g : R(0);
-    } else if (!generic_shape) {
-      const R g = shape_fast<R, COUNT>(d, L, sp, j, G, in_reg, cnt);
-      R chi;
-      if (chi_one) chi = R(1);
-      else if (!chi_mixed) chi = fast_exp2<R>(c0 + c1 * ad);
-      else chi = chi_any<R>(ad, G);
-      val = in_reg ? g * chi : R(0);
-    } else {
-      val = in_reg ? line_value<R, COUNT>(d, L, sp[j], G, cfine, cnt) : R(0);
-    }
-    acc += val;
-    if (COUNT) {
-      if (in_reg) n_used++;
-      if ((threadIdx.x & 63) == 0) cnt.iters++;
-    }
-  }
-}
-
-__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
-
-// Line record j of a layer through a 32-bit byte offset from the layer's
-// base in the global address space (plans keep a layer's records under
-// 4 GiB), so the load can take the scalar-base + vector-offset form.
-template <typename Rec>
-__device__ __forceinline__ Rec load_rec(const Rec* __restrict__ rec, int32_t j) {
-#if __HIP_DEVICE_COMPILE__
-  typedef const __attribute__((address_space(1))) char gchar;
-  typedef const __attribute__((address_space(1))) Rec grec;
-  gchar* base = (gchar*)rec;
-  return *(grec*)(base + (uint32_t)j * (uint32_t)sizeof(Rec));
-#else
-  return rec[j];   // host pass: parsed, never run
-#endif
-}
-
-// Fast region scan over one window: SGN = +1 / -1 one side of the annulus
-// |d| in [ra, rbx); SGN = 0 the own region |d| < rbx.  Each lane takes K
-// consecutive level nodes (X0, X0 + rl, ...) against one line per step, so a
-// line record is loaded and unpacked once per K pairs.  Lanes past the
-// window's last line read that line again and are masked; act masks nodes
-// outside the tile.  Lines with start level
-// above smax are skipped.  CHIM: 0 no chi, 1 one exponential piece over the
-// window, 2 any piece.  With one piece and a signed distance, chi of node k is
-// chi of node k-1 times the constant exp2(c1 rl).
-template <typename R, bool COUNT, int SGN, bool SURR, int CHIM, int K>
-__device__ __forceinline__ void scan_fast(const typename RecOf<R>::T* __restrict__ rec, const R* __restrict__ sp,
-                                          int32_t j0, int32_t j1, int S, int slice, int32_t X0, int32_t rl,
-                                          uint32_t act, R ra, R rbx, int smax, R c0, R c1, const Geometry& G,
-                                          R* acc, Counts& cnt, uint32_t& n_used, const LevelArgs& a) {
-  using Rec = typename RecOf<R>::T;
-  const R c1s = SGN < 0 ? -c1 : c1;   // chi exponent slope in the signed distance
-  const R chi_step = (CHIM == 1 && SGN != 0) ? fast_exp2<R>(c1s * R(rl)) : R(1);
-  auto step = [&](const Rec& L, int32_t j) {
-    const int32_t n0 = X0 - L.k0;
-    const R fr = R(L.frac);
-    const bool lok = L.s <= smax && j < j1;
-    R chi_run = R(1);
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const R d = R(n0 + k * rl) - fr;
-      bool in_reg;
-      if (SGN > 0) in_reg = d >= ra && d < rbx;
-      else if (SGN < 0) in_reg = d <= -ra && d > -rbx;
-      else in_reg = fabs(d) < rbx;
-      in_reg = in_reg && lok && ((act >> k) & 1u);
-      if constexpr (SURR) {
-        const float g = g_surr<COUNT>(d, L, sp, j, G, a, in_reg, cnt);
-        acc[k] += in_reg ? g : R(0);
-      } else {
-        (void)a;
-        const R g = shape_fast<R, COUNT>(d, L, sp, j, G, in_reg, cnt);
-        R chi;
-        if constexpr (CHIM == 0) {
-          chi = R(1);
-        } else if constexpr (CHIM == 1 && SGN != 0) {
-          chi_run = (k == 0) ? fast_exp2<R>(fma(c1s, d, c0)) : chi_run * chi_step;
-          chi = chi_run;
-        } else if constexpr (CHIM == 1) {
-          chi = fast_exp2<R>(fma(c1s, fabs(d), c0));
-        } else {
-          chi = chi_any<R>(fabs(d), G);
-        }
-        acc[k] += in_reg ? g * chi : R(0);
-      }
-      if (COUNT && in_reg) n_used++;
-    }
-  };
-  int32_t j = j0 + slice;
-  Rec La = load_rec(rec, j < j1 ? j : j1 - 1);
-  for (int32_t J = j0; J < j1; J += 2 * S) {
-    const Rec Lb = load_rec(rec, J + S + slice < j1 ? J + S + slice : j1 - 1);
-    step(La, J + slice);
-    La = load_rec(rec, J + 2 * S + slice < j1 ? J + 2 * S + slice : j1 - 1);
-    if (COUNT && (threadIdx.x & 63) == 0) cnt.iters++;
-    if (J + S < j1) {
-      step(Lb, J + S + slice);
-      if (COUNT && (threadIdx.x & 63) == 0) cnt.iters++;
-    }
-  }
-}
-
-// scan_fast with the window's chi mode as a template argument
-template <typename R, bool COUNT, int SGN, bool SURR, int K>
-__device__ __forceinline__ void scan_fast_chi(const typename RecOf<R>::T* __restrict__ rec, const R* __restrict__ sp,
-                                              int32_t j0, int32_t j1, int S, int slice, int32_t X0, int32_t rl,
-                                              uint32_t act, R ra, R rbx, int smax, bool chi_none, bool chi_mixed,
-                                              R c0, R c1, const Geometry& G, R* acc, Counts& cnt, uint32_t& n_used,
-                                              const LevelArgs& a) {
-  if (chi_mixed)
-    scan_fast<R, COUNT, SGN, SURR, 2, K>(rec, sp, j0, j1, S, slice, X0, rl, act, ra, rbx, smax, c0, c1, G, acc, cnt,
-                                         n_used, a);
-  else if (chi_none)
-    scan_fast<R, COUNT, SGN, SURR, 0, K>(rec, sp, j0, j1, S, slice, X0, rl, act, ra, rbx, smax, c0, c1, G, acc, cnt,
-                                         n_used, a);
-  else
-    scan_fast<R, COUNT, SGN, SURR, 1, K>(rec, sp, j0, j1, S, slice, X0, rl, act, ra, rbx, smax, c0, c1, G, acc, cnt,
-                                         n_used, a);
-}
-
-// Fast region pass of one wavefront tile of nw = 2^lnw nodes: groups of K
-// consecutive nodes per lane, lane = group * S + slice, S = 64 K / nw line
-// slices.  iv->fast_ok: 2 = the own region of lines starting at l (one
-// window), 1 = the annulus [b_(l-1), b_l) of lines starting below l (two
-// sides).  The line windows (my_j) are fetched by the caller.
-template <typename R, bool COUNT, bool SURR, int K>
-__device__ __forceinline__ void region_fast(const Geometry& G, const LevelArgs& a, int l, int layer, int lnw,
-                                            int64_t rel0, int tile_left, const IntervalSet* iv, R* lds_acc,
-                                            int64_t item_first, int32_t my_j, Counts& cnt, uint32_t& n_used) {
-  using Rec = typename RecOf<R>::T;
-  constexpr int lK = K == 4 ? 2 : (K == 2 ? 1 : 0);
-  const int lane = threadIdx.x & 63;
-  const int lS = 6 - (lnw - lK);
-  const int S = 1 << lS;
-  const int node0 = (lane >> lS) * K;
-  const int slice = lane & (S - 1);
-  const int32_t rl = G.r[l];
-  const Rec* rec = reinterpret_cast<const Rec*>(a.rec) + (int64_t)layer * a.n_lines;
-  const R* sp = reinterpret_cast<const R*>(a.csp) + (int64_t)layer * a.n_lines;
-  const int64_t m0 = G.lo[l] + rel0 + node0;
-  const int32_t X0 = (int32_t)(m0 * rl);
-  uint32_t act = 0;
-#pragma unroll
-  for (int k = 0; k < K; ++k)
-    if (rel0 + node0 + k < G.n[l] && node0 + k < tile_left) act |= 1u << k;
-  R acc[K];
-#pragma unroll
-  for (int k = 0; k < K; ++k) acc[k] = R(0);
-  const bool chi_mixed = iv->fchi_mixed != 0;
-  const bool chi_none = !chi_mixed && iv->fc0 == 0.0 && iv->fc1 == 0.0;
-  const R c0 = R(iv->fc0), c1 = R(iv->fc1);
-  const int smax = uniform(iv->fast_need_s) ? l : kLevels;
-  const R rbx = sizeof(R) == 4 ? R(iv->rbx32) : R(iv->rbx64);
-  if (uniform(iv->fast_ok) == 2) {
-    const int32_t j0 = uniform(__shfl(my_j, 0)), j1 = uniform(__shfl(my_j, 1));
-    if (j0 < j1)
-      scan_fast_chi<R, COUNT, 0, SURR, K>(rec, sp, j0, j1, S, slice, X0, rl, act, R(0), rbx, smax, chi_none,
-                                          chi_mixed, c0, c1, G, acc, cnt, n_used, a);
-  } else {
-    const R ra = sizeof(R) == 4 ? R(iv->ra32) : R(iv->ra64);
-    for (int side = 0; side < 2; ++side) {
-      const int32_t j0 = uniform(__shfl(my_j, 2 * side)), j1 = uniform(__shfl(my_j, 2 * side + 1));
-      if (j0 >= j1) continue;
-      if (side == 0)
-        scan_fast_chi<R, COUNT, 1, SURR, K>(rec, sp, j0, j1, S, slice, X0, rl, act, ra, rbx, smax, chi_none,
-                                            chi_mixed, c0, c1, G, acc, cnt, n_used, a);
-      else
-        scan_fast_chi<R, COUNT, -1, SURR, K>(rec, sp, j0, j1, S, slice, X0, rl, act, ra, rbx, smax, chi_none,
-                                             chi_mixed, c0, c1, G, acc, cnt, n_used, a);
-    }
-  }
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    R v = acc[k];
-    for (int o = S >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    if (((act >> k) & 1u) && slice == 0) lds_acc[m0 + k - G.lo[l] - item_first] = v;
-  }
-}
-
-
-
-__device__ __forceinline__ int64_t bucket_of(double nu, const Geometry& G) {
-  int64_t b = (int64_t)floor((nu - G.bucket_origin) * kBucketPerCm);
-  return b < 0 ? 0 : (b > G.nbucket ? G.nbucket : b);
-}
-
-// Lagrange weight of offset i (in -H..H) at t for the 2H+1 nodes -H..H
-template <int H>
-__host__ __device__ constexpr double lagrange_den(int i) {
-  double v = 1.0;
-  for (int j = -H; j <= H; ++j)
-    if (j != i) v *= (double)(i - j);
-  return v;
-}
-template <int H>
-__host__ __device__ __forceinline__ constexpr double lagrange_w(int i, double t) {
-  double v = 1.0;
-  for (int j = -H; j <= H; ++j)
-    if (j != i) v *= (t - j);
-  return v * (1.0 / lagrange_den<H>(i));
-}
-
-// Stencil of level-l node m on level l+1 (positions in fine units): G.ns
-// coarse nodes centred on the nearest one (a tie goes to the lower); one
-// node where m coincides with a coarse node
-template <typename R>
-__device__ __forceinline__ int stencil_of(const Geometry& G, int l, int64_t m, int32_t* Xs, R* ws) {
-  const int64_t rl = G.r[l];
-  const int64_t rho = G.r[l + 1] / rl;
-  const int64_t q = floor_div(m, rho);
-  const int64_t rem = m - q * rho;
-  const int64_t r1 = G.r[l + 1];
-  // at rem == 0 the stencil at t = 0 has weights (.., 0, 1, 0, ..) exactly
-  const double f = (double)rem / (double)rho;
-  double tt;
-  int64_t kc;
-  if (f <= 0.5) { kc = q; tt = f; } else { kc = q + 1; tt = f - 1.0; }
-  // both stencils, selected per slot (the 3-point one padded with zero weights)
-  const bool five = G.ns == 5;
-  const int64_t k0 = five ? kc - 2 : kc - 1;
-#pragma unroll
-  for (int i = 0; i < 5; ++i) {
-    Xs[i] = (int32_t)((k0 + (i < 3 || five ? i : 2)) * r1);
-    const double w3 = i < 3 ? lagrange_w<1>(i - 1, tt) : 0.0;
-    ws[i] = R(five ? lagrange_w<2>(i - 2, tt) : w3);
-  }
-  return rem == 0 ? 1 : G.ns;
-}
-
-// Region pass of one wavefront tile: nw = 2^lnw consecutive nodes of level l;
-// lane = node * S + slice, S = 64 / nw.  For every region window the tile
-// walks the union of its nodes' line ranges, S consecutive lines per step
-// (coalesced loads); node sums are reduced over slices and stored to LDS.
-template <typename R, bool COUNT, bool SURR>
-__device__ __forceinline__ void region_tile(const Geometry& G, const LevelArgs& a, int l, int layer, int lnw, int64_t rel0,
-                            int tile_left, const IntervalSet* iv, R* lds_acc, int64_t item_first, Counts& cnt,
-                            uint32_t& n_used) {
-  using Rec = typename RecOf<R>::T;
-  const int lane = threadIdx.x & 63;
-  const int nw = 1 << lnw;
-  const int lS = 6 - lnw;
-  const int S = 1 << lS;
-  const int node = lane >> lS;
-  const int slice = lane & (S - 1);
-  const int32_t rl = G.r[l];
-  const Rec* rec = reinterpret_cast<const Rec*>(a.rec) + (int64_t)layer * a.n_lines;
-  const R* sp = reinterpret_cast<const R*>(a.csp) + (int64_t)layer * a.n_lines;
-  const int32_t* bk = a.bucket + (int64_t)layer * (G.nbucket + 1);
-  const R cfine = R(G.c_fine);
-  const R b_prev = (l > 0) ? R(G.b[l - 1]) : R(0);
-  const R b_cur = (l < kLevels - 1) ? R(G.b[l]) : R(INFINITY);
-  const int64_t m = G.lo[l] + rel0 + node;
-  const bool active = (rel0 + node < G.n[l]) && (node < tile_left);
-  const int32_t X = (int32_t)(m * rl);
-  const int64_t Xf = (G.lo[l] + rel0) * rl;
-  const int64_t Xl = Xf + (int64_t)(nw - 1) * rl;
-  // line ranges of every (window, side), fetched in one round.  Region
-  // membership is decided on the single-precision distance, which can round
-  // onto a window edge from outside; one fine unit of margin keeps such
-  // lines in the scan, where the membership test decides.
-  constexpr double kEdge = 1.0;
-  const int n_iv = uniform(iv->n_iv);
-  int nws = 0;
-  int my_bucket = 0;
-  for (int k = 0; k < n_iv; ++k) {
-    const double ia = iv->a[k], ib = iv->b[k];
-    const int nside = (ia == 0.0) ? 1 : 2;
-    for (int side = 0; side < nside; ++side, ++nws) {
-      double plo, phi;
-      if (nside == 1) { plo = (double)Xf - ib - kEdge; phi = (double)Xl + ib + kEdge; }
-      else if (side == 0) { plo = (double)Xf - ib - kEdge; phi = (double)Xl - ia + kEdge; }
-      else { plo = (double)Xf + ia - kEdge; phi = (double)Xl + ib + kEdge; }
-      const int64_t blo = bucket_of(plo * kH0, G);
-      const int64_t bhi = bucket_of(phi * kH0, G) + 1 > G.nbucket ? G.nbucket : bucket_of(phi * kH0, G) + 1;
-      if (lane == 2 * nws) my_bucket = (int)blo;
-      if (lane == 2 * nws + 1) my_bucket = (int)bhi;
-    }
-  }
-  const int32_t my_j = (lane < 2 * nws) ? bk[my_bucket] : 0;
-  if (iv->fast_ok && G.shape != MARFA_SHAPE_DOPPLER) {
-    // K nodes per lane (up to 4, fewer for narrow tiles) in the single-
-    // precision plain kernel; one elsewhere (the counting, learned-shape and
-    // double-precision kernels are not timed and stay small)
-    if constexpr (sizeof(R) == 4 && !COUNT && !SURR) {
-      if (lnw >= 2) {
-        region_fast<R, COUNT, SURR, 4>(G, a, l, layer, lnw, rel0, tile_left, iv, lds_acc, item_first, my_j, cnt,
-                                       n_used);
-        return;
-      }
-      if (lnw == 1) {
-        region_fast<R, COUNT, SURR, 2>(G, a, l, layer, lnw, rel0, tile_left, iv, lds_acc, item_first, my_j, cnt,
-                                       n_used);
-        return;
-      }
-    }
-    region_fast<R, COUNT, SURR, 1>(G, a, l, layer, lnw, rel0, tile_left, iv, lds_acc, item_first, my_j, cnt, n_used);
-    return;
-  }
-  R acc = R(0);
-  int ws_i = 0;
-  for (int k = 0; k < n_iv; ++k) {
-    const R ra = R(iv->a[k]), rb = R(iv->b[k]);
-    const bool chi_mixed = iv->chi_mixed[k] != 0;
-    const R c0 = R(iv->chi_c0[k]), c1 = R(iv->chi_c1[k]);
-    const bool chi_one = !chi_mixed && iv->chi_c0[k] == 0.0 && iv->chi_c1[k] == 0.0;
-    if (iv->a[k] == 0.0) {
-      const int32_t j0 = uniform(__shfl(my_j, 2 * ws_i)), j1 = uniform(__shfl(my_j, 2 * ws_i + 1));
-      ++ws_i;
-      if (j0 < j1)
-        scan_region<R, COUNT, 0, SURR>(rec, sp, j0, j1, S, slice, X, active, ra, rb, chi_one, chi_mixed, c0, c1, l, G, cfine,
-                                 b_prev, b_cur, acc, cnt, n_used, a);
-    } else {
-      int32_t j0 = uniform(__shfl(my_j, 2 * ws_i)), j1 = uniform(__shfl(my_j, 2 * ws_i + 1));
-      ++ws_i;
-      if (j0 < j1)
-        scan_region<R, COUNT, 1, SURR>(rec, sp, j0, j1, S, slice, X, active, ra, rb, chi_one, chi_mixed, c0, c1, l, G, cfine,
-                                 b_prev, b_cur, acc, cnt, n_used, a);
-      j0 = uniform(__shfl(my_j, 2 * ws_i));
-      j1 = uniform(__shfl(my_j, 2 * ws_i + 1));
-      ++ws_i;
-      if (j0 < j1)
-        scan_region<R, COUNT, -1, SURR>(rec, sp, j0, j1, S, slice, X, active, ra, rb, chi_one, chi_mixed, c0, c1, l, G, cfine,
-                                  b_prev, b_cur, acc, cnt, n_used, a);
-    }
-  }
-  for (int o = S >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-  if (active && slice == 0) lds_acc[m - G.lo[l] - item_first] = acc;
-}
-
-// Residual-band pass: lane = one node of level l whose stencil on level l+1
-// has three points.  For every jump q of T_(l+1) and side, the lane walks the
-// lines whose |d| lies within reach of q (its own window), and for each line
-// whose stencil hull holds a jump — counted at the smallest such jump only —
-// adds D_l = T_l(d) - sum_i w_i T_(l+1)(d_i) minus the region value already
-// added.
-template <typename R, bool COUNT>
-__device__ __forceinline__ void band_group(const Geometry& G, const LevelArgs& a, int l, int layer, int64_t rel0, int group_left,
-                           const IntervalSet* iv, R* lds_acc, int64_t item_first, Counts& cnt, uint32_t& n_used,
-                           uint32_t& n_band) {
-  using Rec = typename RecOf<R>::T;
-  const int lane = threadIdx.x & 63;
-  const int32_t rl = G.r[l];
-  const Rec* rec = reinterpret_cast<const Rec*>(a.rec) + (int64_t)layer * a.n_lines;
-  const R* sp = reinterpret_cast<const R*>(a.csp) + (int64_t)layer * a.n_lines;
-  const int32_t* bk = a.bucket + (int64_t)layer * (G.nbucket + 1);
-  const R cfine = R(G.c_fine);
-  const R b_prev = (l > 0) ? R(G.b[l - 1]) : R(0);
-  const R b_cur = R(G.b[l]);
-  const double hb = G.hb[l];
-  const int64_t m = G.lo[l] + rel0 + lane;
-  int32_t Xs[5];
-  R ws[5];
-  const int ns = stencil_of<R>(G, l, m, Xs, ws);
-  const bool active = (rel0 + lane < G.n[l]) && (lane < group_left) && ns > 1;
-  const int nsg = G.ns;
-  const int32_t x_last = Xs[0] + (nsg - 1) * G.r[l + 1];   // stencil nodes are r_(l+1) apart
-  if (!__any(active)) return;
-  const int32_t X = (int32_t)(m * rl);
-  const int nj = uniform(iv->n_jump);
-  R acc = R(0);
-  for (int k = 0; k < nj; ++k) {
-    const double q = iv->jq[k];
-    const R rq = R(q);
-    for (int side = 0; side < 2; ++side) {
-      // side 0: d > 0 (line below the node), side 1: d <= 0
-      const double plo = side == 0 ? (double)X - q - hb : (double)X + q - hb;
-      const double phi = side == 0 ? (double)X - q + hb : (double)X + q + hb;
-      const int64_t b0 = bucket_of(plo * kH0, G);
-      int64_t b1 = bucket_of(phi * kH0, G) + 1;
-      b1 = b1 > G.nbucket ? G.nbucket : b1;
-      const int32_t j0 = active ? bk[b0] : 0;
-      const int32_t j1 = active ? bk[b1] : 0;
-      for (int32_t j = j0; __any(j < j1); ++j) {
-        if (j < j1) {
-          const Rec L = rec[j];
-          const R d = R(X - L.k0) - R(L.frac);
-          const bool side_ok = side == 0 ? d > R(0) : !(d > R(0));
-          const int ls = L.s;
-          const int cls = (l >= ls) ? 1 : 2;
-          const R d0 = R(Xs[0] - L.k0) - R(L.frac);
-          const R d2 = R(x_last - L.k0) - R(L.frac);
-          const R lo = (d0 * d2 <= R(0)) ? R(0) : fmin(fabs(d0), fabs(d2));
-          const R hi = fmax(fabs(d0), fabs(d2));
-          // the smallest straddled jump of this line's class
-          R qmin = R(INFINITY);
-          for (int i = 0; i < nj; ++i) {
-            const R qi = R(iv->jq[i]);
-            if ((iv->jmask[i] & cls) && qi >= lo && qi <= hi) qmin = fmin(qmin, qi);
-          }
-          if (side_ok && qmin == rq) {
-            const R ad = fabs(d);
-            const R rlo = (l == ls) ? R(0) : b_prev;
-            const bool in_reg = ls <= l && ad >= rlo && ad < b_cur && ad <= cfine;
-            const bool tl = ad <= cfine && !(l > ls && ad < b_prev);
-            R v = R(0);
-            if (tl && !in_reg) v = g_any<R, COUNT>(d, L, sp, j, G, cfine, true, cnt);
-#pragma unroll
-            for (int i = 0; i < 5; ++i) {
-              if (i >= nsg) break;
-              const R di = R(Xs[i] - L.k0) - R(L.frac);
-              const R adi = fabs(di);
-              if (adi <= cfine && !(l + 1 > ls && adi < b_cur)) v -= ws[i] * g_any<R, COUNT>(di, L, sp, j, G, cfine, true, cnt);
-            }
-            acc += v;
-            if (COUNT) { n_band++; if (!in_reg) n_used++; }
-          }
-        }
-        if (COUNT && lane == 0) cnt.band_iters++;
-      }
-    }
-  }
-  if (active) lds_acc[m - G.lo[l] - item_first] += acc;
-}
-
-// One chunk of 64 lines of the line-major band pass for one jump and side:
-// NC candidate centres from kc0 with NSP-point stencils (see band_lines).
-template <typename R, bool COUNT, int RHO, bool SURR, int NSP, int NC>
-__device__ __forceinline__ void band_chunk(const typename RecOf<R>::T& L, int32_t jl, int ls, int cls, bool ok,
-                                           int64_t kc0, int side, R rq, bool iso, const IntervalSet* iv,
-                                           int chi_mode, R cc0, R cc1, int l, int32_t rl, int32_t r1, R cfine,
-                                           R b_prev, R b_cur, int64_t m_a, int64_t m_b, int64_t base,
-                                           const R* __restrict__ sp, const Geometry& G, const LevelArgs& a,
-                                           R* lds_acc, Counts& cnt, uint32_t& n_used, uint32_t& n_band) {
-  const int lane = threadIdx.x & 63;
-  constexpr int H = NSP / 2;
-  // T_(l+1) at level-(l+1) nodes kc0-H .. kc0+NC-1+H
-  R dd[NC + 2 * H], T1[NC + 2 * H];
-#pragma unroll
-  for (int i = 0; i < NC + 2 * H; ++i) {
-    dd[i] = R((int32_t)((kc0 - H + i) * r1) - L.k0) - R(L.frac);
-    const R adi = fabs(dd[i]);
-    const bool act = ok && adi <= cfine && !(l + 1 > ls && adi < b_cur);
-    const R g = g_band<R, COUNT, SURR>(dd[i], L, sp, jl, G, cfine, act, cnt, a, chi_mode, cc0, cc1);
-    T1[i] = act ? g : R(0);
-  }
-  // segments of lanes with equal kc0 (non-decreasing over lanes)
-  const int32_t u32 = (int32_t)kc0;
-  uint32_t same = 0;
-#pragma unroll
-  for (int st = 0; st < 6; ++st) {
-    const int32_t uo = __shfl_up(u32, 1 << st);
-    if (lane >= (1 << st) && uo == u32) same |= 1u << st;
-  }
-  const int32_t un = __shfl_down(u32, 1);
-  const bool seg_end = lane == 63 || un != u32;
-  // at fine levels lines are sparse: no two lanes share a centre and the merge is skipped
-  const bool merge = __builtin_amdgcn_ballot_w64(same != 0u) != 0;
-#pragma unroll
-  for (int c = 0; c < NC; ++c) {
-    const int64_t kc = kc0 + c;
-    const R d0 = dd[c], d2 = dd[c + 2 * H];
-    const R lo = (d0 * d2 <= R(0)) ? R(0) : fmin(fabs(d0), fabs(d2));
-    const R hi = fmax(fabs(d0), fabs(d2));
-    bool strad;
-    if (iso) {
-      strad = ok && rq >= lo && rq <= hi;
-    } else {
-      R qmin = R(INFINITY);
-      const int nj = uniform(iv->n_jump);
-      for (int i = 0; i < nj; ++i) {
-        const R qi = R(iv->jq[i]);
-        if ((iv->jmask[i] & cls) && qi >= lo && qi <= hi) qmin = fmin(qmin, qi);
-      }
-      strad = ok && qmin == rq;
-    }
-#pragma unroll
-    for (int jj = -RHO / 2 + 1; jj <= RHO / 2; ++jj) {
-      if (jj == 0) continue;
-      const int64_t m = kc * RHO + jj;
-      const R d = R((int32_t)(m * rl) - L.k0) - R(L.frac);
-      const bool side_ok = side == 0 ? d > R(0) : !(d > R(0));
-      const bool own = m >= m_a && m <= m_b;
-      const bool use = strad && own && side_ok;
-      const R ad = fabs(d);
-      const R rlo = (l == ls) ? R(0) : b_prev;
-      const bool in_reg = ls <= l && ad >= rlo && ad < b_cur && ad <= cfine;
-      const bool tl = ad <= cfine && !(l > ls && ad < b_prev);
-      const bool need = use && tl && !in_reg;
-      R gl = R(0);
-      if (__builtin_amdgcn_ballot_w64(need))
-        gl = g_band<R, COUNT, SURR>(d, L, sp, jl, G, cfine, need, cnt, a, chi_mode, cc0, cc1);
-      const double tt = (double)jj / (double)RHO;
-      R interp = R(0);
-#pragma unroll
-      for (int i = 0; i < NSP; ++i) interp += R(lagrange_w<H>(i - H, tt)) * T1[c + i];
-      const R v0 = (need ? gl : R(0)) - interp;
-      R v = use ? v0 : R(0);
-      if (merge) {
-#pragma unroll
-        for (int st = 0; st < 6; ++st) {
-          const R vo = __shfl_up(v, 1 << st);
-          if (same & (1u << st)) v += vo;
-        }
-      }
-      if (seg_end && own) lds_acc[m - base] += v;
-      if (COUNT && use) { n_band++; if (!in_reg) n_used++; }
-    }
-  }
-
-}
-
-// Residual-band pass, line-major form, for one wavefront owning the item's
-// nodes [own_lo, own_hi).  For a jump q of T_(l+1) and a side, put the
-// line's jump point at P = nu~0 + q (nodes above the line) or nu~0 - q (nodes
-// below).  A level-l node's stencil hull [(kc-H) r1, (kc+H) r1] (H = 1 for the
-// 3-point stencil, 2 for the 5-point one) holds P only if its nearest
-// level-(l+1) centre kc is within H steps of P / r1, so the nodes to correct
-// are the (RHO - 1) interpolated nodes around each of 2H (2H + 1 when P / r1
-// is an integer) centres.  Lane = line: T_(l+1) is evaluated once at
-// the level-(l+1) nodes around P, every candidate node gets D_l = T_l(d) - sum w_i T_(l+1)(d_i)
-// minus the region value (zero unless its hull straddles q and q is the
-// smallest straddled jump), and a segmented sum over lanes with the same
-// centre estimate -- non-decreasing in line order -- merges corrections of a
-// node before one lane adds them to its LDS slot.  Per slot there is one
-// writer and a fixed summation order, so results are reproducible.
-template <typename R, bool COUNT, int RHO, bool SURR, int NSP>
-__device__ __forceinline__ void band_lines(const Geometry& G, const LevelArgs& a, int l, int layer, int64_t item_first, int own_lo,
-                           int own_hi, const IntervalSet* iv, R* lds_acc, Counts& cnt, uint32_t& n_used,
-                           uint32_t& n_band) {
-  using Rec = typename RecOf<R>::T;
-  const int lane = threadIdx.x & 63;
-  if (own_hi <= own_lo) return;
-  const int32_t rl = G.r[l];
-  const int32_t r1 = G.r[l + 1];
-  const Rec* rec = reinterpret_cast<const Rec*>(a.rec) + (int64_t)layer * a.n_lines;
-  const R* sp = reinterpret_cast<const R*>(a.csp) + (int64_t)layer * a.n_lines;
-  const int32_t* bk = a.bucket + (int64_t)layer * (G.nbucket + 1);
-  const R cfine = R(G.c_fine);
-  const R b_prev = (l > 0) ? R(G.b[l - 1]) : R(0);
-  const R b_cur = R(G.b[l]);
-  const double eps = iv->lc_eps;
-  const double inv_r1 = 1.0 / (double)r1;
-  const int nj = uniform(iv->n_jump);
-  const int64_t base = G.lo[l] + item_first;   // absolute index of the item's first node
-  const int64_t m_a = base + own_lo, m_b = base + own_hi - 1;
-  const bool iso = uniform(iv->jumps_isolated) != 0;
-  for (int k = 0; k < nj; ++k) {
-    const double q = iv->jq[k];
-    const R rq = R(q);
-    const int mask = iv->jmask[k];
-    const int chi_mode = uniform(iv->jchi_mode[k]);
-    const R cc0 = R(iv->jchi_c0[k]), cc1 = R(iv->jchi_c1[k]);
-    for (int side = 0; side < 2; ++side) {
-      const double sq = side == 0 ? q : -q;
-      // lines whose candidate nodes can reach [m_a, m_b]
-      const double marg = (NSP / 2 + 1.5) * r1 + 2.0;
-      const double plo = (double)(m_a * rl) - marg - sq;
-      const double phi = (double)(m_b * rl) + marg - sq;
-      const int64_t b0 = bucket_of(plo * kH0, G);
-      int64_t b1 = bucket_of(phi * kH0, G) + 1;
-      b1 = b1 > G.nbucket ? G.nbucket : b1;
-      const int32_t j0 = uniform(bk[b0]), j1 = uniform(bk[b1]);
-      for (int32_t J = j0; J < j1; J += kWave) {
-        const int32_t jl = (J + lane < j1) ? J + lane : j1 - 1;
-        const Rec L = load_rec(rec, jl);
-        const int ls = L.s;
-        const int cls = (l >= ls) ? 1 : 2;
-        const bool ok = (J + lane < j1) && (mask & cls);
-        const double P = (double)L.k0 + (double)L.frac + sq;
-        // Candidate centres: kc in [P/r1 - H, P/r1 + H].  Unless P/r1 lies
-        // within single-precision rounding of an integer (eps), these are the
-        // 2H centres from floor(P/r1) - H + 1; otherwise 2H + 1, from
-        // floor(P/r1 + eps) - H.  The wavefront takes the wider set when any
-        // of its used lanes needs it.
-        constexpr int H = NSP / 2;
-        const double Pr = P * inv_r1;
-        const double fl = floor(Pr);
-        const bool edge = (Pr - fl) < eps || (Pr - fl) > 1.0 - eps;
-        if (__builtin_amdgcn_ballot_w64(ok && edge))
-          band_chunk<R, COUNT, RHO, SURR, NSP, 2 * H + 1>(L, jl, ls, cls, ok, (int64_t)floor(Pr + eps) - H, side, rq,
-                                                          iso, iv, chi_mode, cc0, cc1, l, rl, r1, cfine, b_prev,
-                                                          b_cur, m_a, m_b, base, sp, G, a, lds_acc, cnt, n_used,
-                                                          n_band);
-        else
-          band_chunk<R, COUNT, RHO, SURR, NSP, 2 * H>(L, jl, ls, cls, ok, (int64_t)fl - H + 1, side, rq, iso, iv,
-                                                      chi_mode, cc0, cc1, l, rl, r1, cfine, b_prev, b_cur, m_a, m_b,
-                                                      base, sp, G, a, lds_acc, cnt, n_used, n_band);
-        if (COUNT && lane == 0) cnt.band_iters++;
-      }
-    }
-  }
-}
-
-// Persistent work queue: each workgroup takes items (consecutive nodes of one
-// level of one layer, heaviest levels first).  Its four wavefronts split the
-// item into region tiles, then into band groups of 64 nodes; node sums meet in
-// LDS and are written once.
-template <typename R, bool COUNT, bool SURR>
-__global__ void __launch_bounds__(256) k_level(Geometry G, LevelArgs a_in) {
-  extern __shared__ char smem_raw[];
-  R* lds_acc = reinterpret_cast<R*>(smem_raw);
-  LevelArgs a = a_in;
-  if constexpr (SURR) {
-    // the learned line shape's weights, staged once per workgroup
-    __shared__ float4 s_w0b[kMlpHid];
-    __shared__ uint4 s_wp[kMlpHidLayers * 8 * 64];
-    __shared__ float s_bh[kMlpHidLayers * kMlpHid];
-    __shared__ float s_w4[kMlpHid];
-    __shared__ float s_b4[1];
-    for (int i = threadIdx.x; i < kMlpHid; i += 256) {
-      s_w0b[i] = a_in.mlp.w0b[i];
-      s_w4[i] = a_in.mlp.w4[i];
-    }
-    for (int i = threadIdx.x; i < kMlpHidLayers * 8 * 64; i += 256) s_wp[i] = a_in.mlp.wp[i];
-    for (int i = threadIdx.x; i < kMlpHidLayers * kMlpHid; i += 256) s_bh[i] = a_in.mlp.bh[i];
-    if (threadIdx.x == 0) s_b4[0] = a_in.mlp.b4[0];
-    __syncthreads();
-    a.mlp.w0b = s_w0b;
-    a.mlp.wp = s_wp;
-    a.mlp.bh = s_bh;
-    a.mlp.w4 = s_w4;
-    a.mlp.b4 = s_b4;
-  }
-  __shared__ int64_t s_item;
-  const int wv = threadIdx.x >> 6;
-  const int lane = threadIdx.x & 63;
-  const int64_t total = a.n_tiles * a.n_layers;
-  for (;;) {
-    __syncthreads();
-    if (threadIdx.x == 0) s_item = (int64_t)atomicAdd(a.counter, 1u);
-    __syncthreads();
-    const int64_t item_v = s_item;
-    const int64_t item = (int64_t)(((uint64_t)(uint32_t)uniform((int)(item_v >> 32)) << 32) |
-                                   (uint32_t)uniform((int)item_v));
-    if (item >= total) break;
-    const int tix = uniform((int)(item / a.n_layers));
-    const int layer = uniform((int)(item % a.n_layers));
-    const int l = uniform(a.tiles[tix].level);
-    const int count = uniform(a.tiles[tix].count);
-    const int64_t first = a.tiles[tix].first;
-    const int32_t* gc = a.gcount + layer * (kGroups + 1);
-    int below = 0, above = 0;
-    for (int g = 0; g < l; ++g) below += gc[g];
-    for (int g = l + 1; g < kGroups; ++g) above += gc[g];
-    const int combo = uniform((below > 0 ? 1 : 0) | (gc[l] > 0 ? 2 : 0) | (above > 0 ? 4 : 0));
-    const IntervalSet* iv = a.ivs + (l * 8 + combo);
-    Counts cnt{0, 0, 0, 0, 0};
-    uint32_t n_used = 0, n_band = 0;
-    // region pass
-    const int lnw = G.lnw[l];
-    const int ntile = (count + (1 << lnw) - 1) >> lnw;
-    for (int t = wv; t < ntile; t += 4)
-      region_tile<R, COUNT, SURR>(G, a, l, layer, lnw, first + ((int64_t)t << lnw), count - (t << lnw), iv, lds_acc,
-                            first, cnt, n_used);
-    __syncthreads();
-    // residual-band pass
-    if (l < kLevels - 1 && iv->n_jump > 0) {
-      if (iv->lc_ok) {
-        // each wavefront owns a contiguous quarter of the item's nodes
-        const int own_lo = (int)(((int64_t)count * wv) >> 2);
-        const int own_hi = (int)(((int64_t)count * (wv + 1)) >> 2);
-        const bool two = G.r[l + 1] == 2 * G.r[l];
-        if (G.ns == 5) {
-          if (two)
-            band_lines<R, COUNT, 2, SURR, 5>(G, a, l, layer, first, own_lo, own_hi, iv, lds_acc, cnt, n_used, n_band);
-          else
-            band_lines<R, COUNT, 4, SURR, 5>(G, a, l, layer, first, own_lo, own_hi, iv, lds_acc, cnt, n_used, n_band);
-        } else {
-          if (two)
-            band_lines<R, COUNT, 2, SURR, 3>(G, a, l, layer, first, own_lo, own_hi, iv, lds_acc, cnt, n_used, n_band);
-          else
-            band_lines<R, COUNT, 4, SURR, 3>(G, a, l, layer, first, own_lo, own_hi, iv, lds_acc, cnt, n_used, n_band);
-        }
-      } else {
-        const int ngroup = (count + 63) >> 6;
-        for (int g = wv; g < ngroup; g += 4)
-          band_group<R, COUNT>(G, a, l, layer, first + ((int64_t)g << 6), count - (g << 6), iv, lds_acc, first, cnt,
-                               n_used, n_band);
-      }
-    }
-    __syncthreads();
-    if (COUNT) {
-      unsigned long long v[7] = {n_used, n_band, cnt.core, cnt.wing, cnt.terms, cnt.iters, cnt.band_iters};
-      for (int i = 0; i < 7; ++i) {
-        unsigned long long x = v[i];
-        for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
-        v[i] = x;
-      }
-      if (lane == 0) {
-        atomicAdd(&a.stats[l], v[0]);
-        atomicAdd(&a.stats[11], v[1]);
-        atomicAdd(&a.stats[12], v[2]);
-        atomicAdd(&a.stats[13], v[3]);
-        atomicAdd(&a.stats[14], v[4]);
-        atomicAdd(&a.stats[16 + l], v[5]);
-        atomicAdd(&a.stats[27 + l], v[6]);
-      }
-    } else {
-      for (int i = threadIdx.x; i < count; i += 256) {
-        const R v = lds_acc[i];
-        if (l == 0)
-          reinterpret_cast<R*>(a.out)[(int64_t)layer * a.stride + first + i] = v;
-        else
-          reinterpret_cast<R*>(a.A)[(int64_t)layer * G.a_total + G.aoff[l] + first + i] = v;
-      }
-    }
-  }
-}
-
-// ------------------------------------------------------------------
 // cascade: A_l += P(A_(l+1)); level 0 also scales into the output
 // ------------------------------------------------------------------
 template <typename R>
@@ -1407,12 +318,13 @@ __global__ void k_cascade(Geometry G, int l, R* A, R* out, int64_t stride, const
 // K(x, y) through the hot-path shape code: a line with alpha_D = sqrt(ln 2)
 // (so x = d and y = gamma_L in cm^-1) and unit intensity has F = K / sqrt(pi)
 template <typename R>
-__device__ double device_K(double x, double y) {
+__device__ double device_K(double x, double y, const double* wd) {
   typename RecOf<R>::T L{};
   L.k0 = 0; L.frac = 0; L.A = R(y * kInvPi);
   L.gam = R(y); L.gam2 = R(y) * R(y);
   L.ae = R(0.5); L.xs = R(1); L.s = 0;
   Geometry G{};
+  G.weid = wd;
   G.shape = MARFA_SHAPE_VOIGT;
   G.chi = MARFA_CHI_NONE;
   Counts c{0, 0, 0, 0, 0};
@@ -1423,10 +335,10 @@ __device__ double device_K(double x, double y) {
 
 // device Voigt for tests
 template <typename R>
-__global__ void k_voigt_eval(int64_t n, const double* x, const double* y, double* out) {
+__global__ void k_voigt_eval(int64_t n, const double* x, const double* y, double* out, const double* wd) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  out[i] = device_K<R>(x[i], y[i]);
+  out[i] = device_K<R>(x[i], y[i], wd);
 }
 
 // ------------------------------------------------------------------
@@ -1450,7 +362,7 @@ __device__ __forceinline__ double uniform01(uint64_t seed, uint64_t ctr) {
 // network features; the target is log(K chi) - log(Kb) with K from the
 // double-precision device line shape and chi from Eq.(10).
 __global__ void k_mlp_samples(MlpSampleCfg c, uint64_t seed, int64_t n, float* __restrict__ X,
-                              float* __restrict__ T) {
+                              float* __restrict__ T, const double* __restrict__ wd) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const uint64_t b = (uint64_t)i * 8;
@@ -1470,7 +382,7 @@ __global__ void k_mlp_samples(MlpSampleCfg c, uint64_t seed, int64_t n, float* _
     y = exp(log(fmax(c.y_lo, 1e-2)) + (log(fmin(c.y_hi, 10.0)) - log(fmax(c.y_lo, 1e-2))) * uniform01(seed, b + 5));
   }
   const double x = sq * ad / aD;
-  const double K = device_K<double>(x, y);
+  const double K = device_K<double>(x, y, wd);
   const double chi = c.chi == MARFA_CHI_TONKOV ? tonkov<double>(ad) : 1.0;
   const double x2 = x * x, r = x2 + y * y, up = 1.0 + 1.7724538509055160 * y;
   const double kb = y * (1.0 + (3.0 * x2 - y * y) / (2.0 * r * r + 1.0)) / (1.7724538509055160 * (r + 0.5 * exp(-r))) +
@@ -1484,14 +396,6 @@ __global__ void k_mlp_samples(MlpSampleCfg c, uint64_t seed, int64_t n, float* _
 // ------------------------------------------------------------------
 // host-side launchers
 // ------------------------------------------------------------------
-hipError_t upload_weideman(const double* a32, const double* a64, const double* L2) {
-  hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(c_weid32), a32, sizeof(double) * (kWeidemanN32 + 1));
-  if (e != hipSuccess) return e;
-  e = hipMemcpyToSymbol(HIP_SYMBOL(c_weid64), a64, sizeof(double) * (kWeidemanN64 + 1));
-  if (e != hipSuccess) return e;
-  return hipMemcpyToSymbol(HIP_SYMBOL(c_weidL), L2, sizeof(double) * 2);
-}
-
 void launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t s) {
   if (n > 0) k_fill_u64<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(p, n, v);
 }
@@ -1521,15 +425,20 @@ void launch_prep(const LineIn& in, const double* layers, int nL, const Geometry&
   k_layer_scale<<<(nL + 255) / 256, 256, 0, s>>>(layers, pa.smax, nL, pa.out_kind, pa.scale);
 }
 
+void launch_level_f32(const Geometry& G, const LevelArgs& a, int grid, hipStream_t s);
+void launch_level_f32_count(const Geometry& G, const LevelArgs& a, int grid, hipStream_t s);
+void launch_level_f32_surr(const Geometry& G, const LevelArgs& a, int grid, hipStream_t s);
+void launch_level_f64(const Geometry& G, const LevelArgs& a, int grid, hipStream_t s);
+void launch_level_f64_count(const Geometry& G, const LevelArgs& a, int grid, hipStream_t s);
+
 void launch_level(const Geometry& G, const LevelArgs& a, int grid, bool fp64, bool count, hipStream_t s) {
-  const size_t smem = (size_t)a.max_item * (fp64 ? sizeof(double) : sizeof(float));
   if (fp64) {
-    if (count) k_level<double, true, false><<<grid, 256, smem, s>>>(G, a);
-    else k_level<double, false, false><<<grid, 256, smem, s>>>(G, a);
+    if (count) launch_level_f64_count(G, a, grid, s);
+    else launch_level_f64(G, a, grid, s);
   } else {
-    if (count) k_level<float, true, false><<<grid, 256, smem, s>>>(G, a);
-    else if (a.surr) k_level<float, false, true><<<grid, 256, smem, s>>>(G, a);
-    else k_level<float, false, false><<<grid, 256, smem, s>>>(G, a);
+    if (count) launch_level_f32_count(G, a, grid, s);
+    else if (a.surr) launch_level_f32_surr(G, a, grid, s);
+    else launch_level_f32(G, a, grid, s);
   }
 }
 
@@ -1550,16 +459,18 @@ void launch_cascade(const Geometry& G, int nL, void* A, void* out, int64_t strid
   }
 }
 
-void launch_mlp_samples(const MlpSampleCfg& c, uint64_t seed, int64_t n, float* X, float* T, hipStream_t s) {
+void launch_mlp_samples(const MlpSampleCfg& c, uint64_t seed, int64_t n, float* X, float* T, const double* wd,
+                        hipStream_t s) {
   if (n <= 0) return;
-  k_mlp_samples<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(c, seed, n, X, T);
+  k_mlp_samples<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(c, seed, n, X, T, wd);
 }
 
-void launch_voigt_eval(int64_t n, const double* x, const double* y, double* out, bool fp64, hipStream_t s) {
+void launch_voigt_eval(int64_t n, const double* x, const double* y, double* out, bool fp64, const double* wd,
+                       hipStream_t s) {
   if (n <= 0) return;
   unsigned g = (unsigned)((n + 255) / 256);
-  if (fp64) k_voigt_eval<double><<<g, 256, 0, s>>>(n, x, y, out);
-  else k_voigt_eval<float><<<g, 256, 0, s>>>(n, x, y, out);
+  if (fp64) k_voigt_eval<double><<<g, 256, 0, s>>>(n, x, y, out, wd);
+  else k_voigt_eval<float><<<g, 256, 0, s>>>(n, x, y, out, wd);
 }
 
 }  // namespace marfa

@@ -69,6 +69,7 @@ static void weideman_coeffs(int N, double* a, double* Lout) {
 
 static std::mutex g_dev_mu;
 static bool g_dev_ready[64];
+static double* g_weid[64];   // per-device coefficient tables, kept until the process ends
 
 static marfa_status ensure_device(int device) {
   int cnt = 0;
@@ -81,16 +82,24 @@ static marfa_status ensure_device(int device) {
   HIP_TRY(hipSetDevice(device));
   std::lock_guard<std::mutex> lk(g_dev_mu);
   if (!g_dev_ready[device]) {
-    double a32[kWeidemanN32 + 1], a64[kWeidemanN64 + 1], L2[2];
-    weideman_coeffs(kWeidemanN32, a32, &L2[0]);
-    weideman_coeffs(kWeidemanN64, a64, &L2[1]);
-    HIP_TRY(upload_weideman(a32, a64, L2));
+    double tab[kWeidTotal];
+    weideman_coeffs(kWeidemanN32, tab + kWeidOff32, &tab[kWeidOffL]);
+    weideman_coeffs(kWeidemanN64, tab + kWeidOff64, &tab[kWeidOffL + 1]);
+    double* d = nullptr;
+    HIP_TRY(hipMalloc((void**)&d, sizeof tab));
+    hipError_t e = hipMemcpy(d, tab, sizeof tab, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      (void)hipFree(d);
+      return fail(MARFA_E_DEVICE, "coefficient upload: %s", hipGetErrorString(e));
+    }
+    g_weid[device] = d;
     g_dev_ready[device] = true;
   }
   return MARFA_OK;
 }
 
 namespace marfa {
+const double* device_weideman(int device) { return (device >= 0 && device < 64) ? g_weid[device] : nullptr; }
 marfa_status marfa_set_error(marfa_status st, const char* msg) { return fail(st, "%s", msg); }
 marfa_status marfa_use_device(int device) { return ensure_device(device); }
 }  // namespace marfa
@@ -458,7 +467,6 @@ static marfa_status validate(const marfa_lines* L, const marfa_layer* lay, int32
   if (rq->stencil != 0 && rq->stencil != 3 && rq->stencil != 5) return fail(MARFA_E_INVALID, "stencil must be 3 or 5");
   if (rq->fp64 < 0 || rq->fp64 > 1) return fail(MARFA_E_INVALID, "fp64");
   if (!(rq->prune_rel >= 0.0) || !(rq->prune_rel < 1.0)) return fail(MARFA_E_INVALID, "prune_rel in [0,1)");
-  if (rq->eval == MARFA_EVAL_SURROGATE) return fail(MARFA_E_UNSUPPORTED, "surrogate evaluation needs a trained network");
   return MARFA_OK;
 }
 
@@ -517,6 +525,7 @@ extern "C" marfa_status marfa_plan_create(marfa_plan** out, const marfa_lines* l
     nu_max = nu_max + std::max(0.0, dhi * pmax);
   }
   make_geometry(*req, nu_max - nu_min, p->G);
+  p->G.weid = device_weideman(device);
   p->G.bucket_origin = std::floor(nu_min);
   {
     double lo = INFINITY, hi = -INFINITY;
@@ -728,7 +737,7 @@ static void enqueue(marfa_plan* p, int first, int count, void* out, int64_t stri
   a.stride = stride;
   a.stats = p->d.stats;
   a.max_item = tl.max_item;
-  a.surr = (p->surr && !count_mode) ? 1 : 0;
+  a.surr = (p->surr && p->req.eval == MARFA_EVAL_SURROGATE && !count_mode) ? 1 : 0;
   a.mlp_xmax = p->mlp_xmax;
   a.mlp_inv_c = p->mlp_inv_c;
   a.mlp = p->mlp;
@@ -742,6 +751,8 @@ static void enqueue(marfa_plan* p, int first, int count, void* out, int64_t stri
 }
 
 static marfa_status capture(marfa_plan* p, void* out, int64_t stride, int stages, hipGraph_t* g, hipGraphExec_t* x) {
+  // a launch of the graph being replaced may still be queued
+  if (*x) HIP_TRY(hipDeviceSynchronize());
   if (*x) { (void)hipGraphExecDestroy(*x); *x = nullptr; }
   if (*g) { (void)hipGraphDestroy(*g); *g = nullptr; }
   HIP_TRY(hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal));
@@ -868,7 +879,13 @@ extern "C" marfa_status marfa_plan_count(marfa_plan* p, marfa_stats* out) {
   return MARFA_OK;
 }
 
+// Destroy the plan's captured graphs.  A launch of them may still be queued
+// on a caller's stream, so the device finishes its work first.
 static void drop_graphs(marfa_plan* p) {
+  if (p->exec || p->sexec[0] || p->sexec[1] || p->sexec[2]) {
+    (void)hipSetDevice(p->device);
+    (void)hipDeviceSynchronize();
+  }
   if (p->exec) { (void)hipGraphExecDestroy(p->exec); p->exec = nullptr; }
   if (p->graph) { (void)hipGraphDestroy(p->graph); p->graph = nullptr; }
   for (int i = 0; i < 3; ++i) {
@@ -1037,6 +1054,16 @@ extern "C" marfa_status marfa_plan_set_surrogate(marfa_plan* p, const marfa_surr
   return MARFA_OK;
 }
 
+extern "C" marfa_status marfa_plan_set_eval(marfa_plan* p, int32_t eval) {
+  if (!p) return fail(MARFA_E_INVALID, "null plan");
+  if (eval != MARFA_EVAL_PLAIN && eval != MARFA_EVAL_SURROGATE) return fail(MARFA_E_INVALID, "eval");
+  if (eval != p->req.eval) {
+    drop_graphs(p);
+    p->req.eval = eval;
+  }
+  return MARFA_OK;
+}
+
 extern "C" void marfa_plan_destroy(marfa_plan* p) {
   if (!p) return;
   (void)hipSetDevice(p->device);
@@ -1079,7 +1106,7 @@ extern "C" marfa_status marfa_voigt_eval(int32_t device, int64_t n, const double
     hipError_t e = hipMemcpy(dx, x, n * sizeof(double), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(dy, y, n * sizeof(double), hipMemcpyHostToDevice);
     if (e == hipSuccess) {
-      launch_voigt_eval(n, dx, dy, dout, fp64 != 0, nullptr);
+      launch_voigt_eval(n, dx, dy, dout, fp64 != 0, device_weideman(device), nullptr);
       e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipMemcpy(out, dout, n * sizeof(double), hipMemcpyDeviceToHost);

@@ -471,6 +471,9 @@ extern "C" marfa_status marfa_surrogate_set_params(marfa_surrogate* s, const flo
   for (int64_t i = 0; i < n; ++i)
     if (!std::isfinite(params[i])) return sfail(MARFA_E_INVALID, "non-finite parameter");
   SHIP(hipSetDevice(s->device));
+  // plans may have queued work on other streams that reads the evaluation
+  // form rewritten below: let every enqueued kernel of the device finish first
+  SHIP(hipDeviceSynchronize());
   SHIP(hipMemcpyAsync(s->master, params, n * sizeof(float), hipMemcpyHostToDevice, s->stream));
   SHIP(hipMemsetAsync(s->m, 0, n * sizeof(float), s->stream));
   SHIP(hipMemsetAsync(s->v, 0, n * sizeof(float), s->stream));
@@ -531,7 +534,7 @@ extern "C" marfa_status marfa_surrogate_make_samples(marfa_surrogate* s, const m
   SHIP(hipSetDevice(s->device));
   MlpSampleCfg mc{c->nu_lo, c->nu_hi, c->T_lo, c->T_hi, c->molar_mass_g, (double)kMlpYMin, (double)kMlpYMax,
                   s->cutoff, s->chi, 0};
-  launch_mlp_samples(mc, seed, n, X, T, (hipStream_t)stream);
+  launch_mlp_samples(mc, seed, n, X, T, device_weideman(s->device), (hipStream_t)stream);
   SHIP(hipGetLastError());
   return MARFA_OK;
 }
@@ -544,6 +547,8 @@ extern "C" marfa_status marfa_surrogate_train(marfa_surrogate* s, const marfa_sa
       (cfg->loss_power != 2 && cfg->loss_power != 4))
     return sfail(MARFA_E_INVALID, "training configuration");
   SHIP(hipSetDevice(s->device));
+  // training rewrites the weights that queued plan launches may still read
+  SHIP(hipDeviceSynchronize());
   const auto t0 = std::chrono::steady_clock::now();
   std::memset(rep, 0, sizeof *rep);
   const int64_t N = cfg->n_train, V = cfg->n_val;

@@ -19,6 +19,7 @@ OK, E_INVALID, E_NOMEM, E_DEVICE, E_UNSUPPORTED, E_STATE, E_IO = 0, -1, -2, -3, 
 PTBIN_NT = 20481          # values per PT-table record (Appendix A)
 PTBIN_TRUNCATE = 1
 SHAPES = {"voigt": 0, "lorentz": 1, "doppler": 2}
+EVALS = {"plain": 0, "surrogate": 1}
 CHIS = {"none": 0, "tonkov": 1}
 OUTS = {"sigma": 0, "k": 1}
 
@@ -122,13 +123,14 @@ def lib():
         L.marfa_surrogate_destroy.argtypes = [vp]
         L.marfa_surrogate_destroy.restype = None
         L.marfa_plan_set_surrogate.argtypes = [vp, vp]
+        L.marfa_plan_set_eval.argtypes = [vp, i32]
         L.marfa_ptbin_write.argtypes = [C.c_char_p, vp, i64, C.c_double, i32, vp, i32, C.POINTER(i32)]
         L.marfa_linedb_count.argtypes = [C.c_char_p, C.POINTER(i64)]
         L.marfa_linedb_read.argtypes = [C.c_char_p, i64, i64, vp, vp, vp, vp, vp, vp, vp, vp]
         L.marfa_linedb_write.argtypes = [C.c_char_p, C.POINTER(Lines)]
         for f in ("marfa_surrogate_create", "marfa_surrogate_set_params", "marfa_surrogate_get_params",
                   "marfa_surrogate_forward", "marfa_surrogate_loss_grad", "marfa_surrogate_make_samples",
-                  "marfa_surrogate_train", "marfa_plan_set_surrogate"):
+                  "marfa_surrogate_train", "marfa_plan_set_surrogate", "marfa_plan_set_eval"):
             getattr(L, f).restype = C.c_int32
         for f in ("marfa_plan_create", "marfa_plan_points", "marfa_execute", "marfa_execute_layers",
                   "marfa_plan_count", "marfa_plan_tiles", "marfa_execute_timed", "marfa_plan_tune", "marfa_last_error",
@@ -166,7 +168,7 @@ class Plan:
     """
 
     def __init__(self, lines, layers, *, nu_begin, nu_end, cutoff, shape="voigt", chi="none", out="sigma",
-                 prune=0.0, R=48, level_table=0, fp64=False, stencil=3, device=0):
+                 prune=0.0, R=48, level_table=0, fp64=False, stencil=3, eval="plain", device=0):
         L = lib()
         self._arrs = [np.ascontiguousarray(lines.nu0, np.float64),
                       np.ascontiguousarray(lines.S296, np.float32),
@@ -185,7 +187,8 @@ class Plan:
         lay = np.ascontiguousarray(np.asarray(layers, np.float64).reshape(-1, 4))
         lays = (Layer * lay.shape[0])(*[Layer(*row) for row in lay])
         rq = Request(float(nu_begin), float(nu_end), float(cutoff), SHAPES.get(shape, shape),
-                     CHIS.get(chi, chi), OUTS.get(out, out), 0, float(prune), float(R), int(level_table),
+                     CHIS.get(chi, chi), OUTS.get(out, out), EVALS.get(eval, eval), float(prune), float(R),
+                     int(level_table),
                      1 if fp64 else 0, int(stencil), (C.c_int32 * 3)(0, 0, 0))
         h = C.c_void_p()
         _check(L.marfa_plan_create(C.byref(h), C.byref(ls), lays, lay.shape[0], C.byref(rq), int(device)))
@@ -262,9 +265,14 @@ class Plan:
         return self.tiles()
 
     def set_surrogate(self, surrogate):
-        """Evaluate line shapes with a trained Surrogate (None: plain shapes)."""
+        """Attach a trained Surrogate (None detaches); it evaluates the line
+        shapes while the plan's eval is "surrogate" (see set_eval)."""
         _check(lib().marfa_plan_set_surrogate(self._h, surrogate._h if surrogate is not None else None))
         self._surrogate = surrogate
+
+    def set_eval(self, eval):
+        """Line-shape evaluation: "plain" or "surrogate" (the attached network)."""
+        _check(lib().marfa_plan_set_eval(self._h, EVALS.get(eval, eval)))
 
     def close(self):
         if getattr(self, "_h", None):
@@ -303,6 +311,8 @@ class Surrogate:
         return p
 
     def set_params(self, params):
+        """Replace the parameters; the library first waits for the device's
+        queued work, so launches already enqueued use the old weights."""
         p = np.ascontiguousarray(params, np.float32)
         _check(lib().marfa_surrogate_set_params(self._h, _ptr(p), p.size))
 

@@ -114,6 +114,7 @@ def test_null_handles_are_rejected():
     t = marfa.Tiles()
     assert L.marfa_plan_set_tiles(None, C.byref(t)) == marfa.E_INVALID
     assert L.marfa_plan_set_surrogate(None, None) == marfa.E_INVALID
+    assert L.marfa_plan_set_eval(None, 1) == marfa.E_INVALID
     assert L.marfa_surrogate_set_params(None, None, 0) == marfa.E_INVALID
     assert L.marfa_surrogate_train(None, None, None, None) == marfa.E_INVALID
     assert L.marfa_plan_tune(None, None, 0, None) == marfa.E_INVALID

@@ -80,28 +80,57 @@ def test_params_round_trip():
     S.close()
 
 
-def test_gradient_matches_oracle():
+def _grad_tolerance(p, X, T):
+    """Per-parameter bound on the device gradient's error.  The oracle's
+    per-sample gradients c_b (batch of one, divided by n) give
+    A = sum_b |c_b|, the sum of the magnitudes the device accumulates.  The
+    device forms the hidden-layer weight gradients as matrix-core products of
+    BF16-rounded dZ and H (two roundings of at most 2^-9 each per product:
+    2^-8 A), everything else in single precision (1e-5 A)."""
+    n = X.shape[0]
+    A = np.zeros(p.size)
+    for b in range(n):
+        _, gb = O.mlp_loss_grad(WIDTHS, eval_params(p), X[b:b + 1].astype(np.float64),
+                                T[b:b + 1].astype(np.float64))
+        A += np.abs(gb) / n
+    rel = np.full(p.size, 1e-5)
+    off = 0
+    for i in range(len(WIDTHS) - 1):
+        nw = WIDTHS[i] * WIDTHS[i + 1]
+        if 1 <= i <= 3:
+            rel[off:off + nw] += 2.0 ** -8
+        off += nw + WIDTHS[i + 1]
+    return rel * A + 1e-12 * A.max()
+
+
+@pytest.mark.parametrize("targets", ["random", "offset"])
+def test_gradient_matches_oracle_elementwise(targets):
     S = M().Surrogate(seed=3)
     p = random_params(21)
     S.set_params(p)
-    n = 1000
+    n = 1000   # 31 full groups of 32 samples and a ragged one
     X = random_features(n, 22)
     rng = np.random.default_rng(23)
-    T = rng.normal(0, 0.5, n).astype(np.float32)
+    if targets == "random":
+        T = rng.normal(0, 0.5, n).astype(np.float32)
+    else:
+        # every error between 1 and 1.2: little cancellation between samples
+        t = O.mlp_forward(WIDTHS, eval_params(p), X.astype(np.float64))[:, 0]
+        T = (t - 1.0 - 0.2 * rng.uniform(0, 1, n)).astype(np.float32)
     loss, g = S.loss_grad(torch.tensor(X, device="cuda:0"), torch.tensor(T, device="cuda:0"))
     ref_loss, ref_g = O.mlp_loss_grad(WIDTHS, eval_params(p), X.astype(np.float64), T.astype(np.float64))
     print(f"loss {loss:.6e} vs {ref_loss:.6e}")
     assert abs(loss - ref_loss) <= 1e-4 * ref_loss
-    # per layer: weight and bias blocks, BF16 activations in the weight-gradient products
-    off = 0
-    for i in range(len(WIDTHS) - 1):
-        for nw in (WIDTHS[i] * WIDTHS[i + 1], WIDTHS[i + 1]):
-            a, b = g[off:off + nw].astype(np.float64), ref_g[off:off + nw]
-            rel = np.linalg.norm(a - b) / np.linalg.norm(b)
-            cos = a @ b / (np.linalg.norm(a) * np.linalg.norm(b))
-            print(f"block at {off} ({nw}): rel {rel:.2e} cos {cos:.8f}")
-            assert rel < 1e-2 and cos > 0.9999
-            off += nw
+    tol = _grad_tolerance(p, X, T)
+    err = np.abs(g.astype(np.float64) - ref_g)
+    worst = int(np.argmax(err / tol))
+    print(f"gradient: max |err|/tol {err[worst] / tol[worst]:.3f} at parameter {worst}; "
+          f"max rel err {np.max(err / np.maximum(np.abs(ref_g), 1e-30)):.2e}")
+    assert np.all(err <= tol), np.flatnonzero(err > tol)[:20]
+    # the bound is tight enough that a sign error in almost any entry exceeds it
+    caught = float(np.mean(2.0 * np.abs(ref_g) > tol))
+    print(f"entries whose sign flip the bound catches: {caught:.4f}")
+    assert caught > 0.9
     S.close()
 
 
@@ -155,9 +184,9 @@ def test_surrogate_pt_table_vs_direct_and_vs_base_alone():
     plan = mm.Plan(lines, layers, device=0, **req)
     plain = plan.execute().clone()
     plan.set_surrogate(S)
+    plan.set_eval("surrogate")
     surr = plan.execute().clone()
     S.set_params(np.zeros(mm.N_PARAMS, np.float32))   # t = 0: the analytic base alone
-    plan.set_surrogate(S)
     base = plan.execute().clone()
     torch.cuda.synchronize()
     plan.close()
@@ -177,4 +206,50 @@ def test_surrogate_pt_table_vs_direct_and_vs_base_alone():
     print(f"surrogate vs plain, every node: {full:.2e}")
     assert max(e_s) < 1e-3
     assert max(e_b) > 10 * max(e_s)
+    S.close()
+
+
+def test_surrogate_eval_switch_and_set_params_after_execute():
+    """The request's eval field selects the line shape, and replacing the
+    network's weights right after an execute (no synchronisation in between)
+    leaves that execute's output computed with the old weights."""
+    from paper_2411_03418_amd import synth
+    mm = M()
+    lines = synth.make_lines(2000, 940.0, 1080.0, 43, shift=True)
+    layers = synth.pt_table(4)
+    req = dict(nu_begin=1000.0, nu_end=1012.0, cutoff=60.0, chi="tonkov", prune=1e-6)
+    S = mm.Surrogate(chi="tonkov", cutoff=60.0, seed=2)
+    S.train(n_train=65536, n_val=4096, epochs=2, batch=4096, lr_max=2e-3, lr_min=1e-4, seed=9,
+            nu_lo=935.0, nu_hi=1085.0, T_lo=150.0, T_hi=740.0)
+    trained = S.get_params()
+    # a plan asking for the learned shape refuses to run until one is attached
+    plan = mm.Plan(lines, layers, device=0, eval="surrogate", **req)
+    with pytest.raises(mm.MarfaError) as e:
+        plan.execute()
+    assert e.value.status == mm.E_UNSUPPORTED
+    plan.set_surrogate(S)
+    ref = plan.execute().clone()
+    torch.cuda.synchronize()
+    # plain evaluation with the network still attached ignores it
+    plan.set_eval("plain")
+    plain = plan.execute().clone()
+    torch.cuda.synchronize()
+    assert not torch.equal(plain, ref)
+    plan.set_eval("surrogate")
+    again = plan.execute().clone()
+    torch.cuda.synchronize()
+    assert torch.equal(again, ref)
+    # weights replaced while the execute may still be running
+    out = plan.execute()
+    S.set_params(np.zeros(mm.N_PARAMS, np.float32))
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref)
+    base = plan.execute().clone()
+    torch.cuda.synchronize()
+    assert not torch.equal(base, ref)
+    S.set_params(trained)
+    back = plan.execute().clone()
+    torch.cuda.synchronize()
+    assert torch.equal(back, ref)
+    plan.close()
     S.close()
