@@ -29,7 +29,7 @@ template <typename R> struct RecOf;
 template <> struct RecOf<float> { using T = LineRec32; };
 template <> struct RecOf<double> { using T = LineRec64; };
 
-// Wing series cut and the |z|^2 above which it replaces the rational core.
+// Wing series cut and the |z|^2 above which it replaces the core.
 template <typename R> struct Prec;
 template <> struct Prec<float> {
   static constexpr float kEps = 1e-6f;
@@ -47,46 +47,57 @@ template <> struct Prec<double> {
 // ------------------------------------------------------------------
 
 // Re w(z) for |z| small, w the Faddeeva function, by Weideman's rational
-// series in Z = (L+iz)/(L-iz):  w = 1/(sqrt(pi)(L-iz)) + 2/(L-iz)^2 sum_n a_n Z^(n-1).
-// Evaluated in double precision in both paths (the real part is small next to
-// |w| near the real axis, so single precision would lose it).
-// P(Z) = sum_{n=1..N} a_n Z^(n-1) has real coefficients.  QUAD evaluates it
-// by synthetic division by (X - Z)(X - conj Z) = X^2 - 2 Re Z X + |Z|^2:
-// b_m = a_(m+1) + 2 Re Z b_(m+1) - |Z|^2 b_(m+2), P(Z) = b_0 - b_1 conj(Z),
-// two real FMAs per degree instead of a complex multiply-add (its rounding
-// grows like 1/|arg Z| near the real axis: 1e-9 relative here, used by the
-// single-precision path); otherwise complex Horner.
-template <int N, bool QUAD = false>
+// series in Z = (L+iz)/(L-iz):  w = 1/(sqrt(pi)(L-iz)) + 2/(L-iz)^2 sum_n a_n Z^(n-1),
+// in double precision (double-precision path).  P(Z) = sum_{n=1..N} a_n Z^(n-1)
+// by complex Horner.
+template <int N>
 __device__ __forceinline__ double voigt_core(double x, double y, const double* a, double L) {
   double Ar = L + y, Ai = -x;
   double inv = 1.0 / (Ar * Ar + Ai * Ai);
   double iAr = Ar * inv, iAi = -Ai * inv;
   double Br = L - y, Bi = x;
   double Zr = Br * iAr - Bi * iAi, Zi = Br * iAi + Bi * iAr;
-  double pr, pim;
-  if constexpr (QUAD) {
-    const double r = 2.0 * Zr, s = -(Zr * Zr + Zi * Zi);
-    double b1 = a[N], b2 = 0.0;
+  double pr = a[N], pim = 0.0;
 #pragma unroll
-    for (int m = N - 2; m >= 0; --m) {
-      const double b0 = fma(r, b1, fma(s, b2, a[m + 1]));
-      b2 = b1;
-      b1 = b0;
-    }
-    pr = fma(-b2, Zr, b1);
-    pim = b2 * Zi;
-  } else {
-    pr = a[N];
-    pim = 0.0;
-#pragma unroll
-    for (int n = N - 1; n >= 1; --n) {
-      double tr = fma(pr, Zr, fma(-pim, Zi, a[n]));
-      pim = fma(pr, Zi, pim * Zr);
-      pr = tr;
-    }
+  for (int n = N - 1; n >= 1; --n) {
+    double tr = fma(pr, Zr, fma(-pim, Zi, a[n]));
+    pim = fma(pr, Zi, pim * Zr);
+    pr = tr;
   }
   double i2r = iAr * iAr - iAi * iAi, i2i = 2.0 * iAr * iAi;
   return iAr * kInvSqrtPi + 2.0 * (pr * i2r - pim * i2i);
+}
+
+// K(x, y) = Re w(x + iy) for x, y >= 0, |z| < 6, in single precision: the
+// Taylor series of w about the nearest lattice centre z0 = (i + j sqrt(-1))/4,
+//   w(z0 + u) = sum_n c_n u^n,  c_n = w^(n)(z0)/n!,  |u| <= sqrt(2)/8,
+// nine terms, complex Horner in u = (x - i/4) + (y - j/4) sqrt(-1).  The
+// coefficients are tabulated in double precision and rounded once; on the real
+// axis their real parts are the Hermite forms d^n/dx^n exp(-x^2)/n!.  Because
+// the real and imaginary parts of each c_n are stored separately, Re w near the
+// real axis (where it is far smaller than Im w) comes out with a relative, not
+// an absolute, rounding error: every product that forms it is of its own size.
+__device__ __forceinline__ float voigt_core32(float x, float y, const float4* __restrict__ tab) {
+  const float fi = fminf(rintf(x * float(kTaylorPerUnit)), float(kTaylorSide - 1));
+  const float fj = fminf(rintf(y * float(kTaylorPerUnit)), float(kTaylorSide - 1));
+  const float d = fmaf(fi, -1.0f / kTaylorPerUnit, x);
+  const float e = fmaf(fj, -1.0f / kTaylorPerUnit, y);
+  const float4* c = tab + ((int)fj * kTaylorSide + (int)fi) * kTaylorQuads;
+  const float4 q4 = c[4], q3 = c[3], q2 = c[2], q1 = c[1], q0 = c[0];
+  float pr = q4.x, pi = q4.y;
+  auto step = [&](float cr, float ci) {
+    const float nr = fmaf(pr, d, fmaf(-pi, e, cr));
+    pi = fmaf(pr, e, fmaf(pi, d, ci));
+    pr = nr;
+  };
+  step(q3.z, q3.w);
+  step(q3.x, q3.y);
+  step(q2.z, q2.w);
+  step(q2.x, q2.y);
+  step(q1.z, q1.w);
+  step(q1.x, q1.y);
+  step(q0.z, q0.w);
+  return fmaf(pr, d, fmaf(-pi, e, q0.x));
 }
 
 // Voigt far from the core (|z| large): f = Re[i/(pi (d + i g))] times the
@@ -155,12 +166,12 @@ __device__ __forceinline__ R line_value(R d, const typename RecOf<R>::T& L, R Sp
       f = voigt_wing<R>(dd, R(L.gam), R(L.gam2), R(L.ae), terms);
       if (COUNT) { cnt.wing++; cnt.terms += terms; }
     } else {
-      double K;
-      if (sizeof(R) == 4)
-        K = voigt_core<kWeidemanN32, true>(fabs((double)x), (double)y, G.weid + kWeidOff32, G.weid[kWeidOffL]);
-      else
-        K = voigt_core<kWeidemanN64>(fabs((double)x), (double)y, G.weid + kWeidOff64, G.weid[kWeidOffL + 1]);
-      f = R((double)L.xs * kInvSqrtPi * K);
+      if constexpr (sizeof(R) == 4) {
+        f = L.xs * float(kInvSqrtPi) * voigt_core32(fabsf(x), y, G.ktab);
+      } else {
+        const double K = voigt_core<kWeidemanN64>(fabs(x), y, G.weid, G.weid[kWeidemanN64 + 1]);
+        f = L.xs * kInvSqrtPi * K;
+      }
       if (COUNT) cnt.core++;
     }
   }

@@ -14,15 +14,22 @@ constexpr int kGroups = 11;      // lines grouped by start level 0..10
 constexpr int kMaxIntervals = 8; // disjoint |d| windows per (level, start-level classes)
 constexpr int kMaxJumps = 5;     // jump points of T_(l+1) per (level, start level)
 constexpr int kWave = 64;        // CDNA wavefront
-constexpr int kWeidemanN32 = 28; // rational-series length, single-precision path (1.5e-7 for |z| < 6)
-constexpr int kWeidemanN64 = 48; // rational-series length, double-precision path
+constexpr int kWeidemanN64 = 48; // rational-series length of the double-precision Voigt core
 constexpr int kBucketPerCm = 256; // line-index buckets per cm^-1 (8 finest steps)
-// per-device table of Weideman coefficients: single-precision path, double-
-// precision path, then the two scale parameters L
-constexpr int kWeidOff32 = 0;
-constexpr int kWeidOff64 = kWeidOff32 + kWeidemanN32 + 1;
-constexpr int kWeidOffL = kWeidOff64 + kWeidemanN64 + 1;
-constexpr int kWeidTotal = kWeidOffL + 2;
+// Single-precision Voigt core: Taylor expansions of the Faddeeva function about
+// the centres (i + j sqrt(-1)) / kTaylorPerUnit, 0 <= i, j < kTaylorSide, with
+// kTaylorTerms coefficients each (packed as re/im pairs in kTaylorQuads float4)
+constexpr int kTaylorPerUnit = 4;
+constexpr int kTaylorSide = 25;
+constexpr int kTaylorTerms = 9;
+constexpr int kTaylorQuads = 5;
+
+// Coefficient tables of a device, computed on the host at first use of the
+// device and kept until the process ends.
+struct DeviceTables {
+  double weid[kWeidemanN64 + 2];   // Weideman a_0 .. a_N, then the scale L
+  float taylor[kTaylorSide * kTaylorSide * kTaylorQuads * 4];
+};
 
 // Lattice geometry, identical for every layer.  Positions are in units of the
 // finest step h0 = 2^-11 cm^-1 ("fine units"); node m of level l sits at
@@ -49,7 +56,8 @@ struct Geometry {
   int32_t pad2;
   // Tonkov chi pieces as exp2(chi_c0[i] + chi_c1[i] |d|), |d| in cm (host-computed)
   double chi_c0[3], chi_c1[3];
-  const double* weid;        // the device's Weideman table (kWeidTotal values)
+  const double* weid;        // the device's Weideman coefficients (double-precision core)
+  const float4* ktab;        // the device's Taylor table (single-precision core)
 };
 
 // Region windows (|d| in fine units, closed, disjoint) scanned at one level
@@ -185,8 +193,8 @@ struct LevelArgs {
   MlpDev mlp;
 };
 
-// the Weideman table of a device prepared by marfa_use_device (device memory)
-const double* device_weideman(int device);
+// the coefficient tables of a device prepared by marfa_use_device (device memory)
+const DeviceTables* device_tables(int device);
 void launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t s);
 void launch_fill_u32(unsigned int* p, int64_t n, unsigned int v, hipStream_t s);
 struct PrepArgs {
@@ -212,15 +220,15 @@ struct MlpSampleCfg {
   double cutoff;           // [cm^-1]
   int32_t chi, pad;
 };
-void launch_mlp_samples(const MlpSampleCfg& c, uint64_t seed, int64_t n, float* X, float* T, const double* wd,
-                        hipStream_t s);
+void launch_mlp_samples(const MlpSampleCfg& c, uint64_t seed, int64_t n, float* X, float* T,
+                        const DeviceTables* tabs, hipStream_t s);
 // error text of the calling thread, and device set-up (Weideman tables)
 marfa_status marfa_set_error(marfa_status st, const char* msg);
 marfa_status marfa_use_device(int device);
 void launch_rank(const LineIn& in, const double* layers, int nL, const double* span, int32_t* perm, hipStream_t s);
 void launch_cascade(const Geometry& G, int nL, void* A, void* out, int64_t stride, const double* scale, bool fp64,
                     hipStream_t s);
-void launch_voigt_eval(int64_t n, const double* x, const double* y, double* out, bool fp64, const double* wd,
-                       hipStream_t s);
+void launch_voigt_eval(int64_t n, const double* x, const double* y, double* out, bool fp64,
+                       const DeviceTables* tabs, hipStream_t s);
 
 }  // namespace marfa

@@ -318,13 +318,14 @@ __global__ void k_cascade(Geometry G, int l, R* A, R* out, int64_t stride, const
 // K(x, y) through the hot-path shape code: a line with alpha_D = sqrt(ln 2)
 // (so x = d and y = gamma_L in cm^-1) and unit intensity has F = K / sqrt(pi)
 template <typename R>
-__device__ double device_K(double x, double y, const double* wd) {
+__device__ double device_K(double x, double y, const DeviceTables* tabs) {
   typename RecOf<R>::T L{};
   L.k0 = 0; L.frac = 0; L.A = R(y * kInvPi);
   L.gam = R(y); L.gam2 = R(y) * R(y);
   L.ae = R(0.5); L.xs = R(1); L.s = 0;
   Geometry G{};
-  G.weid = wd;
+  G.weid = tabs->weid;
+  G.ktab = reinterpret_cast<const float4*>(tabs->taylor);
   G.shape = MARFA_SHAPE_VOIGT;
   G.chi = MARFA_CHI_NONE;
   Counts c{0, 0, 0, 0, 0};
@@ -335,10 +336,10 @@ __device__ double device_K(double x, double y, const double* wd) {
 
 // device Voigt for tests
 template <typename R>
-__global__ void k_voigt_eval(int64_t n, const double* x, const double* y, double* out, const double* wd) {
+__global__ void k_voigt_eval(int64_t n, const double* x, const double* y, double* out, const DeviceTables* tabs) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  out[i] = device_K<R>(x[i], y[i], wd);
+  out[i] = device_K<R>(x[i], y[i], tabs);
 }
 
 // ------------------------------------------------------------------
@@ -362,7 +363,7 @@ __device__ __forceinline__ double uniform01(uint64_t seed, uint64_t ctr) {
 // network features; the target is log(K chi) - log(Kb) with K from the
 // double-precision device line shape and chi from Eq.(10).
 __global__ void k_mlp_samples(MlpSampleCfg c, uint64_t seed, int64_t n, float* __restrict__ X,
-                              float* __restrict__ T, const double* __restrict__ wd) {
+                              float* __restrict__ T, const DeviceTables* __restrict__ tabs) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const uint64_t b = (uint64_t)i * 8;
@@ -382,7 +383,7 @@ __global__ void k_mlp_samples(MlpSampleCfg c, uint64_t seed, int64_t n, float* _
     y = exp(log(fmax(c.y_lo, 1e-2)) + (log(fmin(c.y_hi, 10.0)) - log(fmax(c.y_lo, 1e-2))) * uniform01(seed, b + 5));
   }
   const double x = sq * ad / aD;
-  const double K = device_K<double>(x, y, wd);
+  const double K = device_K<double>(x, y, tabs);
   const double chi = c.chi == MARFA_CHI_TONKOV ? tonkov<double>(ad) : 1.0;
   const double x2 = x * x, r = x2 + y * y, up = 1.0 + 1.7724538509055160 * y;
   const double kb = y * (1.0 + (3.0 * x2 - y * y) / (2.0 * r * r + 1.0)) / (1.7724538509055160 * (r + 0.5 * exp(-r))) +
@@ -459,18 +460,18 @@ void launch_cascade(const Geometry& G, int nL, void* A, void* out, int64_t strid
   }
 }
 
-void launch_mlp_samples(const MlpSampleCfg& c, uint64_t seed, int64_t n, float* X, float* T, const double* wd,
-                        hipStream_t s) {
+void launch_mlp_samples(const MlpSampleCfg& c, uint64_t seed, int64_t n, float* X, float* T,
+                        const DeviceTables* tabs, hipStream_t s) {
   if (n <= 0) return;
-  k_mlp_samples<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(c, seed, n, X, T, wd);
+  k_mlp_samples<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(c, seed, n, X, T, tabs);
 }
 
-void launch_voigt_eval(int64_t n, const double* x, const double* y, double* out, bool fp64, const double* wd,
-                       hipStream_t s) {
+void launch_voigt_eval(int64_t n, const double* x, const double* y, double* out, bool fp64,
+                       const DeviceTables* tabs, hipStream_t s) {
   if (n <= 0) return;
   unsigned g = (unsigned)((n + 255) / 256);
-  if (fp64) k_voigt_eval<double><<<g, 256, 0, s>>>(n, x, y, out, wd);
-  else k_voigt_eval<float><<<g, 256, 0, s>>>(n, x, y, out, wd);
+  if (fp64) k_voigt_eval<double><<<g, 256, 0, s>>>(n, x, y, out, tabs);
+  else k_voigt_eval<float><<<g, 256, 0, s>>>(n, x, y, out, tabs);
 }
 
 }  // namespace marfa

@@ -77,18 +77,20 @@ __device__ __forceinline__ R chi_any(R ad_fine, const Geometry& G) {
   return fast_exp2<R>(c0 + c1 * a);
 }
 
-// S' F(d) of the rational core, kept out of line: the region scans inline
-// the wing many times over and take the core for few pairs
+// S' F(d) of the core (|z| < 6): the single-precision Taylor-table core
+// inline; the double-precision Weideman core kept out of line (its path is
+// not timed and stays small)
+__device__ __attribute__((noinline)) double core_value64(double dcm, double xs, double gam, double sp,
+                                                         const double* __restrict__ wd) {
+  const double K = voigt_core<kWeidemanN64>(fabs(xs * dcm), xs * gam, wd, wd[kWeidemanN64 + 1]);
+  return sp * (xs * kInvSqrtPi * K);
+}
 template <typename R>
-__device__ __attribute__((noinline)) R core_value(R dcm, R xs, R gam, R sp, const double* __restrict__ wd) {
-  const R x = xs * dcm;
-  const R y = xs * gam;
-  double K;
-  if (sizeof(R) == 4)
-    K = voigt_core<kWeidemanN32, true>(fabs((double)x), (double)y, wd + kWeidOff32, wd[kWeidOffL]);
+__device__ __forceinline__ R core_value(R dcm, R xs, R gam, R sp, const Geometry& G) {
+  if constexpr (sizeof(R) == 4)
+    return sp * (xs * float(kInvSqrtPi)) * voigt_core32(fabsf(xs * dcm), xs * gam, G.ktab);
   else
-    K = voigt_core<kWeidemanN64>(fabs((double)x), (double)y, wd + kWeidOff64, wd[kWeidOffL + 1]);
-  return sp * R((double)xs * kInvSqrtPi * K);
+    return core_value64(dcm, xs, gam, sp, G.weid);
 }
 
 // S' F(d) (without chi and the cut-off) for the Voigt shape (Lorentz: ae = 0):
@@ -133,7 +135,7 @@ __device__ __forceinline__ R shape_fast(R d, const typename RecOf<R>::T& L, cons
   }
   R f = R(L.A) * Q * sum;
   if (__builtin_amdgcn_ballot_w64(live && core)) {
-    if (live && core) f = core_value<R>(dcm, L.xs, L.gam, sp[j], G.weid);
+    if (live && core) f = core_value<R>(dcm, L.xs, L.gam, sp[j], G);
   }
   if (COUNT && live) { if (core) cnt.core++; else cnt.wing++; }
   return f;

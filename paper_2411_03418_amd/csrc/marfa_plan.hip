@@ -8,6 +8,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <complex>
+#include <cstddef>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -67,9 +69,66 @@ static void weideman_coeffs(int N, double* a, double* Lout) {
   *Lout = L;
 }
 
+// Faddeeva function w(z) = exp(-z^2) erfc(-iz) in double precision on the host,
+// by the Weideman series (coefficients a, scale L) for Im z >= 0 and the
+// reflection w(z) = 2 exp(-z^2) - w(-z) below the real axis.
+static std::complex<double> host_faddeeva(std::complex<double> z, const double* a, int N, double L) {
+  if (z.imag() < 0.0) return 2.0 * std::exp(-z * z) - host_faddeeva(-z, a, N, L);
+  const std::complex<double> I(0.0, 1.0);
+  const std::complex<double> A = L - I * z;
+  const std::complex<double> Z = (L + I * z) / A;
+  std::complex<double> P = a[N];
+  for (int n = N - 1; n >= 1; --n) P = P * Z + a[n];
+  return 1.0 / (std::sqrt(M_PI) * A) + 2.0 * P / (A * A);
+}
+
+// Taylor coefficients c_n = w^(n)(z0)/n!, n < kTaylorTerms, about every centre
+// z0 = (i + j sqrt(-1)) / kTaylorPerUnit, by the trapezoid rule for Cauchy's
+// integral on a circle of radius 0.6 around z0 (64 points; w is entire, so the
+// rule converges geometrically).  On the real axis (j = 0) the real parts are
+// the closed forms d^n/dx^n exp(-x^2)/n! = (-1)^n H_n(x) exp(-x^2)/n! (Hermite
+// polynomials by their recurrence), which are tiny there and must not carry the
+// integral's absolute rounding.  Packed per centre as float4 quads (re c_2k,
+// im c_2k, re c_2k+1, im c_2k+1), the last quad (re c_8, im c_8, 0, 0).
+static void taylor_table(const double* a, int N, double L, float* out) {
+  const int M = 64;
+  const double rho = 0.6;
+  for (int j = 0; j < kTaylorSide; ++j)
+    for (int i = 0; i < kTaylorSide; ++i) {
+      const std::complex<double> z0((double)i / kTaylorPerUnit, (double)j / kTaylorPerUnit);
+      std::complex<double> c[kTaylorTerms];
+      for (int n = 0; n < kTaylorTerms; ++n) c[n] = 0.0;
+      for (int k = 0; k < M; ++k) {
+        const double th = 2.0 * M_PI * k / M;
+        const std::complex<double> wv = host_faddeeva(z0 + std::polar(rho, th), a, N, L);
+        for (int n = 0; n < kTaylorTerms; ++n) c[n] += wv * std::polar(1.0, -n * th);
+      }
+      for (int n = 0; n < kTaylorTerms; ++n) c[n] /= (double)M * std::pow(rho, n);
+      if (j == 0) {
+        const double x = z0.real();
+        double H[kTaylorTerms + 1];
+        H[0] = 1.0;
+        H[1] = 2.0 * x;
+        for (int n = 1; n < kTaylorTerms; ++n) H[n + 1] = 2.0 * x * H[n] - 2.0 * n * H[n - 1];
+        double fact = 1.0;
+        for (int n = 0; n < kTaylorTerms; ++n) {
+          if (n > 0) fact *= n;
+          const double re = ((n & 1) ? -1.0 : 1.0) * H[n] * std::exp(-x * x) / fact;
+          c[n] = std::complex<double>(re, c[n].imag());
+        }
+      }
+      float* q = out + (size_t)(j * kTaylorSide + i) * kTaylorQuads * 4;
+      for (int n = 0; n < kTaylorQuads * 2; ++n) {
+        const std::complex<double> v = n < kTaylorTerms ? c[n] : std::complex<double>(0.0, 0.0);
+        q[2 * n] = (float)v.real();
+        q[2 * n + 1] = (float)v.imag();
+      }
+    }
+}
+
 static std::mutex g_dev_mu;
 static bool g_dev_ready[64];
-static double* g_weid[64];   // per-device coefficient tables, kept until the process ends
+static DeviceTables* g_tabs[64];   // per-device coefficient tables, kept until the process ends
 
 static marfa_status ensure_device(int device) {
   int cnt = 0;
@@ -82,24 +141,25 @@ static marfa_status ensure_device(int device) {
   HIP_TRY(hipSetDevice(device));
   std::lock_guard<std::mutex> lk(g_dev_mu);
   if (!g_dev_ready[device]) {
-    double tab[kWeidTotal];
-    weideman_coeffs(kWeidemanN32, tab + kWeidOff32, &tab[kWeidOffL]);
-    weideman_coeffs(kWeidemanN64, tab + kWeidOff64, &tab[kWeidOffL + 1]);
-    double* d = nullptr;
-    HIP_TRY(hipMalloc((void**)&d, sizeof tab));
-    hipError_t e = hipMemcpy(d, tab, sizeof tab, hipMemcpyHostToDevice);
+    std::vector<DeviceTables> host(1);
+    DeviceTables& t = host[0];
+    weideman_coeffs(kWeidemanN64, t.weid, &t.weid[kWeidemanN64 + 1]);
+    taylor_table(t.weid, kWeidemanN64, t.weid[kWeidemanN64 + 1], t.taylor);
+    DeviceTables* d = nullptr;
+    HIP_TRY(hipMalloc((void**)&d, sizeof(DeviceTables)));
+    hipError_t e = hipMemcpy(d, &t, sizeof(DeviceTables), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
       (void)hipFree(d);
       return fail(MARFA_E_DEVICE, "coefficient upload: %s", hipGetErrorString(e));
     }
-    g_weid[device] = d;
+    g_tabs[device] = d;
     g_dev_ready[device] = true;
   }
   return MARFA_OK;
 }
 
 namespace marfa {
-const double* device_weideman(int device) { return (device >= 0 && device < 64) ? g_weid[device] : nullptr; }
+const DeviceTables* device_tables(int device) { return (device >= 0 && device < 64) ? g_tabs[device] : nullptr; }
 marfa_status marfa_set_error(marfa_status st, const char* msg) { return fail(st, "%s", msg); }
 marfa_status marfa_use_device(int device) { return ensure_device(device); }
 }  // namespace marfa
@@ -525,7 +585,11 @@ extern "C" marfa_status marfa_plan_create(marfa_plan** out, const marfa_lines* l
     nu_max = nu_max + std::max(0.0, dhi * pmax);
   }
   make_geometry(*req, nu_max - nu_min, p->G);
-  p->G.weid = device_weideman(device);
+  {
+    const char* base = reinterpret_cast<const char*>(device_tables(device));
+    p->G.weid = reinterpret_cast<const double*>(base + offsetof(DeviceTables, weid));
+    p->G.ktab = reinterpret_cast<const float4*>(base + offsetof(DeviceTables, taylor));
+  }
   p->G.bucket_origin = std::floor(nu_min);
   {
     double lo = INFINITY, hi = -INFINITY;
@@ -1106,7 +1170,7 @@ extern "C" marfa_status marfa_voigt_eval(int32_t device, int64_t n, const double
     hipError_t e = hipMemcpy(dx, x, n * sizeof(double), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(dy, y, n * sizeof(double), hipMemcpyHostToDevice);
     if (e == hipSuccess) {
-      launch_voigt_eval(n, dx, dy, dout, fp64 != 0, device_weideman(device), nullptr);
+      launch_voigt_eval(n, dx, dy, dout, fp64 != 0, device_tables(device), nullptr);
       e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipMemcpy(out, dout, n * sizeof(double), hipMemcpyDeviceToHost);

@@ -534,7 +534,7 @@ extern "C" marfa_status marfa_surrogate_make_samples(marfa_surrogate* s, const m
   SHIP(hipSetDevice(s->device));
   MlpSampleCfg mc{c->nu_lo, c->nu_hi, c->T_lo, c->T_hi, c->molar_mass_g, (double)kMlpYMin, (double)kMlpYMax,
                   s->cutoff, s->chi, 0};
-  launch_mlp_samples(mc, seed, n, X, T, device_weideman(s->device), (hipStream_t)stream);
+  launch_mlp_samples(mc, seed, n, X, T, device_tables(s->device), (hipStream_t)stream);
   SHIP(hipGetLastError());
   return MARFA_OK;
 }
