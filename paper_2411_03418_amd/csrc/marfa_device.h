@@ -29,6 +29,10 @@ template <typename R> struct RecOf;
 template <> struct RecOf<float> { using T = LineRec32; };
 template <> struct RecOf<double> { using T = LineRec64; };
 
+// gamma_L^2 of a record (the single-precision record keeps gamma_L only)
+__device__ __forceinline__ float gam2_of(const LineRec32& L) { return L.gam * L.gam; }
+__device__ __forceinline__ double gam2_of(const LineRec64& L) { return L.gam2; }
+
 // Wing series cut and the |z|^2 above which it replaces the core.
 template <typename R> struct Prec;
 template <> struct Prec<float> {
@@ -153,7 +157,7 @@ __device__ __forceinline__ R line_value(R d, const typename RecOf<R>::T& L, R Sp
   R dd = dcm * dcm;
   R f;
   if (G.shape == MARFA_SHAPE_LORENTZ) {
-    f = R(L.gam) * R(kInvPi) / (dd + R(L.gam2));
+    f = R(L.gam) * R(kInvPi) / (dd + gam2_of(L));
   } else if (G.shape == MARFA_SHAPE_DOPPLER) {
     R x = R(L.xs) * dcm;
     f = R(L.xs) * R(kInvSqrtPi) * exp(-x * x);
@@ -163,7 +167,7 @@ __device__ __forceinline__ R line_value(R d, const typename RecOf<R>::T& L, R Sp
     R z2 = x * x + y * y;
     if (L.xs == 0 || z2 >= Prec<R>::kZ2) {
       int terms = 0;
-      f = voigt_wing<R>(dd, R(L.gam), R(L.gam2), R(L.ae), terms);
+      f = voigt_wing<R>(dd, R(L.gam), gam2_of(L), R(L.ae), terms);
       if (COUNT) { cnt.wing++; cnt.terms += terms; }
     } else {
       if constexpr (sizeof(R) == 4) {

@@ -115,7 +115,7 @@ struct LineRec32 {
   float frac;     // nu~0 * 2048 - k0, in [0, 1)
   float A;        // S'/pi gamma_L with S' = S(T)/max S(T) (Voigt, Lorentz); S' (Doppler)
   float gam;      // gamma_L [cm^-1]
-  float gam2;     // gamma_L^2
+  float amp;      // S' sqrt(ln 2) / (sqrt(pi) alpha_D): scale of K(x, y) in the core (0 without Doppler width)
   float ae;       // alpha_D^2 / (2 ln 2); the core branch holds for d^2 + gamma_L^2 < 72 ae
   float xs;       // sqrt(ln 2) / alpha_D, 0 when alpha_D = 0
   int32_t s;      // start level
@@ -125,7 +125,7 @@ struct LineRec64 {
   int32_t k0;
   int32_t s;
   double frac, A, gam, gam2, ae, xs;
-  double pad;     // 64-byte records
+  double amp;     // as LineRec32 (64-byte records)
 };
 static_assert(sizeof(LineRec32) == 32, "LineRec32 is two 16-byte words");
 static_assert(sizeof(LineRec64) == 64, "LineRec64 is four 16-byte words");

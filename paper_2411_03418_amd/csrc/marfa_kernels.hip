@@ -194,11 +194,13 @@ __global__ void k_prep_scatter(LineIn in, const double* __restrict__ layers, Geo
   const double sp = sm > 0.0 ? st.S / sm : 0.0;
   r.A = G.shape == MARFA_SHAPE_DOPPLER ? R(sp) : R(sp * st.gL * kInvPi);
   r.gam = R(st.gL);
-  r.gam2 = R(st.gL * st.gL);
+  if constexpr (sizeof(R) == 8) r.gam2 = R(st.gL * st.gL);
   // the Lorentz shape is the Voigt wing with alpha_D = 0
   const bool lor = G.shape == MARFA_SHAPE_LORENTZ;
   r.ae = lor ? R(0) : R(st.aD * st.aD / (2.0 * kLn2d));
-  r.xs = (st.aD > 0.0 && !lor) ? R(sqrt(kLn2d) / st.aD) : R(0);
+  const double xs = (st.aD > 0.0 && !lor) ? sqrt(kLn2d) / st.aD : 0.0;
+  r.xs = R(xs);
+  r.amp = R(sp * xs * kInvSqrtPi);
   r.s = key;
   reinterpret_cast<typename RecOf<R>::T*>(pa.rec)[base + dest] = r;
   reinterpret_cast<R*>(pa.csp)[base + dest] = R(sp);
@@ -321,7 +323,9 @@ template <typename R>
 __device__ double device_K(double x, double y, const DeviceTables* tabs) {
   typename RecOf<R>::T L{};
   L.k0 = 0; L.frac = 0; L.A = R(y * kInvPi);
-  L.gam = R(y); L.gam2 = R(y) * R(y);
+  L.gam = R(y);
+  if constexpr (sizeof(R) == 8) L.gam2 = R(y) * R(y);
+  L.amp = R(kInvSqrtPi);
   L.ae = R(0.5); L.xs = R(1); L.s = 0;
   Geometry G{};
   G.weid = tabs->weid;

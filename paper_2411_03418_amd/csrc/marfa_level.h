@@ -80,35 +80,34 @@ __device__ __forceinline__ R chi_any(R ad_fine, const Geometry& G) {
 // S' F(d) of the core (|z| < 6): the single-precision Taylor-table core
 // inline; the double-precision Weideman core kept out of line (its path is
 // not timed and stays small)
-__device__ __attribute__((noinline)) double core_value64(double dcm, double xs, double gam, double sp,
+__device__ __attribute__((noinline)) double core_value64(double dcm, double xs, double gam, double amp,
                                                          const double* __restrict__ wd) {
-  const double K = voigt_core<kWeidemanN64>(fabs(xs * dcm), xs * gam, wd, wd[kWeidemanN64 + 1]);
-  return sp * (xs * kInvSqrtPi * K);
+  return amp * voigt_core<kWeidemanN64>(fabs(xs * dcm), xs * gam, wd, wd[kWeidemanN64 + 1]);
 }
+// amp = S' sqrt(ln 2) / (sqrt(pi) alpha_D) from the record
 template <typename R>
-__device__ __forceinline__ R core_value(R dcm, R xs, R gam, R sp, const Geometry& G) {
+__device__ __forceinline__ R core_value(R dcm, R xs, R gam, R amp, const Geometry& G) {
   if constexpr (sizeof(R) == 4)
-    return sp * (xs * float(kInvSqrtPi)) * voigt_core32(fabsf(xs * dcm), xs * gam, G.ktab);
+    return amp * voigt_core32(fabsf(xs * dcm), xs * gam, G.ktab);
   else
-    return core_value64(dcm, xs, gam, sp, G.weid);
+    return core_value64(dcm, xs, gam, amp, G.weid);
 }
 
-// S' F(d) (without chi and the cut-off) for the Voigt shape (Lorentz: ae = 0):
-// the asymptotic wing series with a wave-uniform number of terms, and the
-// rational core for lanes with |z| < sqrt(kZ2).  `live` marks lanes whose
-// value is used (they alone steer the term count and the core branch).  The
-// wing is A Q sum with A = S' gamma_L / pi and Q = 1/(d^2 + gamma_L^2); the
-// core needs S' itself (sp[j]).
+// S' F(d) (without chi and the cut-off) for the Voigt shape (Lorentz: ae = 0)
+// outside the core: the asymptotic wing series with a wave-uniform number of
+// terms.  `live` marks lanes whose value is used (they alone steer the term
+// count).  The wing is A Q sum with A = S' gamma_L / pi and
+// Q = 1/(d^2 + gamma_L^2).  `core` returns whether the pair is live and in the
+// core (|z| < sqrt(kZ2)), where the returned value is not the line shape.
 template <typename R, bool COUNT>
-__device__ __forceinline__ R shape_fast(R d, const typename RecOf<R>::T& L, const R* __restrict__ sp, int32_t j,
-                                        const Geometry& G, bool live, Counts& cnt) {
-  const R dcm = d * R(kH0);
-  const R den = fma(dcm, dcm, R(L.gam2));
+__device__ __forceinline__ R shape_wing(R dcm, const typename RecOf<R>::T& L, bool live, Counts& cnt, bool& core_out) {
+  const R g2 = gam2_of(L);
+  const R den = fma(dcm, dcm, g2);
   const R Q = fast_rcp<R>(den);
   const R e = R(L.ae) * Q;
   const bool core = e > R(0.5 / Prec<R>::kZ2);     // |z|^2 = 1/(2e) < kZ2
   // U_2 = 4 d^2 Q - 1 = 3 - 4 gamma^2 Q
-  R U = fma(R(-4) * R(L.gam2), Q, R(3));
+  R U = fma(R(-4) * g2, Q, R(3));
   R sum = fma(e, U, R(1));
   const bool wing = live && !core;
   // term k, with coefficient c_k = (2k-1)!! e^k, is kept while some live
@@ -133,12 +132,72 @@ __device__ __forceinline__ R shape_fast(R d, const typename RecOf<R>::T& L, cons
       if (k + 1 >= Series<R>::kMax || !__builtin_amdgcn_ballot_w64(wing && more(k + 1, ck))) break;
     }
   }
-  R f = R(L.A) * Q * sum;
-  if (__builtin_amdgcn_ballot_w64(live && core)) {
-    if (live && core) f = core_value<R>(dcm, L.xs, L.gam, sp[j], G);
-  }
+  core_out = live && core;
   if (COUNT && live) { if (core) cnt.core++; else cnt.wing++; }
+  return R(L.A) * Q * sum;
+}
+
+// S' F(d) (without chi and the cut-off) for the Voigt shape: the wing series,
+// and the core for lanes with |z| < sqrt(kZ2).  The core needs S' itself (sp[j]).
+template <typename R, bool COUNT>
+__device__ __forceinline__ R shape_fast(R d, const typename RecOf<R>::T& L, const R* __restrict__ sp, int32_t j,
+                                        const Geometry& G, bool live, Counts& cnt) {
+  const R dcm = d * R(kH0);
+  bool core;
+  R f = shape_wing<R, COUNT>(dcm, L, live, cnt, core);
+  if (__builtin_amdgcn_ballot_w64(core)) {
+    if (core) f = core_value<R>(dcm, L.xs, L.gam, R(L.amp), G);
+  }
   return f;
+}
+
+// Wave-local queue of core pairs (single-precision plain kernel): the pairs of
+// one line step whose |z| is below the core radius are packed densely over
+// the wavefront's lanes, evaluated 64 at a time, and handed back to the lanes
+// they came from, which add them in their usual order (the sums are the same
+// bits as with the core evaluated in place).
+constexpr int kCoreQueue = 256;   // 64 lanes x up to 4 nodes per lane
+struct CoreQueue {
+  float* x;        // [kCoreQueue] |x| of the queued pair, then its value
+  uint8_t* src;    // [kCoreQueue] lane that queued the pair
+  float* y;        // [64] y of each lane's line
+  float* amp;      // [64] the core scale of each lane's line
+};
+
+// For the K node slots of a lane (pairs d[k] with the lane's line L): replace
+// f[k] by the core value wherever core[k].
+template <int K>
+__device__ __forceinline__ void core_batch(const CoreQueue& q, const LineRec32& L, const float* d, const bool* core,
+                                           float* f, const Geometry& G) {
+  const int lane = threadIdx.x & 63;
+  q.y[lane] = L.xs * L.gam;
+  q.amp[lane] = L.amp;
+  int pos[K];
+  int n = 0;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const uint64_t m = __builtin_amdgcn_ballot_w64(core[k]);
+    pos[k] = n + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+    if (core[k]) {
+      q.x[pos[k]] = fabsf(L.xs * (d[k] * float(kH0)));
+      q.src[pos[k]] = (uint8_t)lane;
+    }
+    n += __builtin_popcountll(m);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  for (int r = 0; r < n; r += 64) {
+    const int i = r + lane;
+    if (i < n) {
+      const int s = q.src[i];
+      const float Kv = voigt_core32(q.x[i], q.y[s], G.ktab);
+      q.x[i] = q.amp[s] * Kv;
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+    if (core[k]) f[k] = q.x[pos[k]];
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 }
 
 // g(d) = S' F(d) chi(|d|) [|d| <= c] for any shape
@@ -284,15 +343,53 @@ template <typename R, bool COUNT, int SGN, bool SURR, int CHIM, int K>
 __device__ __forceinline__ void scan_fast(const typename RecOf<R>::T* __restrict__ rec, const R* __restrict__ sp,
                                           int32_t j0, int32_t j1, int S, int slice, int32_t X0, int32_t rl,
                                           uint32_t act, R ra, R rbx, int smax, R c0, R c1, const Geometry& G,
-                                          R* acc, Counts& cnt, uint32_t& n_used, const LevelArgs& a) {
+                                          R* acc, Counts& cnt, uint32_t& n_used, const LevelArgs& a,
+                                          const CoreQueue& cq) {
   using Rec = typename RecOf<R>::T;
   const R c1s = SGN < 0 ? -c1 : c1;   // chi exponent slope in the signed distance
   const R chi_step = (CHIM == 1 && SGN != 0) ? fast_exp2<R>(c1s * R(rl)) : R(1);
+  auto chi_of = [&](int k, R d, R& chi_run) -> R {
+    if constexpr (CHIM == 0) {
+      return R(1);
+    } else if constexpr (CHIM == 1 && SGN != 0) {
+      chi_run = (k == 0) ? fast_exp2<R>(fma(c1s, d, c0)) : chi_run * chi_step;
+      return chi_run;
+    } else if constexpr (CHIM == 1) {
+      return fast_exp2<R>(fma(c1s, fabs(d), c0));
+    } else {
+      return chi_any<R>(fabs(d), G);
+    }
+  };
   auto step = [&](const Rec& L, int32_t j) {
     const int32_t n0 = X0 - L.k0;
     const R fr = R(L.frac);
     const bool lok = L.s <= smax && j < j1;
     R chi_run = R(1);
+    if constexpr (sizeof(R) == 4 && !COUNT && !SURR) {
+      // wing values first, core pairs through the wave's queue, then chi and
+      // the accumulation in node order
+      R d[K], f[K];
+      bool reg[K], core[K];
+      bool any = false;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        d[k] = R(n0 + k * rl) - fr;
+        bool in_reg;
+        if (SGN > 0) in_reg = d[k] >= ra && d[k] < rbx;
+        else if (SGN < 0) in_reg = d[k] <= -ra && d[k] > -rbx;
+        else in_reg = fabs(d[k]) < rbx;
+        reg[k] = in_reg && lok && ((act >> k) & 1u);
+        f[k] = shape_wing<R, false>(d[k] * R(kH0), L, reg[k], cnt, core[k]);
+        any = any || core[k];
+      }
+      if (__builtin_amdgcn_ballot_w64(any)) core_batch<K>(cq, L, d, core, f, G);
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const R chi = chi_of(k, d[k], chi_run);
+        acc[k] += reg[k] ? f[k] * chi : R(0);
+      }
+      return;
+    }
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const R d = R(n0 + k * rl) - fr;
@@ -307,17 +404,7 @@ __device__ __forceinline__ void scan_fast(const typename RecOf<R>::T* __restrict
       } else {
         (void)a;
         const R g = shape_fast<R, COUNT>(d, L, sp, j, G, in_reg, cnt);
-        R chi;
-        if constexpr (CHIM == 0) {
-          chi = R(1);
-        } else if constexpr (CHIM == 1 && SGN != 0) {
-          chi_run = (k == 0) ? fast_exp2<R>(fma(c1s, d, c0)) : chi_run * chi_step;
-          chi = chi_run;
-        } else if constexpr (CHIM == 1) {
-          chi = fast_exp2<R>(fma(c1s, fabs(d), c0));
-        } else {
-          chi = chi_any<R>(fabs(d), G);
-        }
+        const R chi = chi_of(k, d, chi_run);
         acc[k] += in_reg ? g * chi : R(0);
       }
       if (COUNT && in_reg) n_used++;
@@ -343,16 +430,16 @@ __device__ __forceinline__ void scan_fast_chi(const typename RecOf<R>::T* __rest
                                               int32_t j0, int32_t j1, int S, int slice, int32_t X0, int32_t rl,
                                               uint32_t act, R ra, R rbx, int smax, bool chi_none, bool chi_mixed,
                                               R c0, R c1, const Geometry& G, R* acc, Counts& cnt, uint32_t& n_used,
-                                              const LevelArgs& a) {
+                                              const LevelArgs& a, const CoreQueue& cq) {
   if (chi_mixed)
     scan_fast<R, COUNT, SGN, SURR, 2, K>(rec, sp, j0, j1, S, slice, X0, rl, act, ra, rbx, smax, c0, c1, G, acc, cnt,
-                                         n_used, a);
+                                         n_used, a, cq);
   else if (chi_none)
     scan_fast<R, COUNT, SGN, SURR, 0, K>(rec, sp, j0, j1, S, slice, X0, rl, act, ra, rbx, smax, c0, c1, G, acc, cnt,
-                                         n_used, a);
+                                         n_used, a, cq);
   else
     scan_fast<R, COUNT, SGN, SURR, 1, K>(rec, sp, j0, j1, S, slice, X0, rl, act, ra, rbx, smax, c0, c1, G, acc, cnt,
-                                         n_used, a);
+                                         n_used, a, cq);
 }
 
 // Fast region pass of one wavefront tile of nw = 2^lnw nodes: groups of K
@@ -363,7 +450,8 @@ __device__ __forceinline__ void scan_fast_chi(const typename RecOf<R>::T* __rest
 template <typename R, bool COUNT, bool SURR, int K>
 __device__ __forceinline__ void region_fast(const Geometry& G, const LevelArgs& a, int l, int layer, int lnw,
                                             int64_t rel0, int tile_left, const IntervalSet* iv, R* lds_acc,
-                                            int64_t item_first, int32_t my_j, Counts& cnt, uint32_t& n_used) {
+                                            int64_t item_first, int32_t my_j, Counts& cnt, uint32_t& n_used,
+                                            const CoreQueue& cq) {
   using Rec = typename RecOf<R>::T;
   constexpr int lK = K == 4 ? 2 : (K == 2 ? 1 : 0);
   const int lane = threadIdx.x & 63;
@@ -392,7 +480,7 @@ __device__ __forceinline__ void region_fast(const Geometry& G, const LevelArgs& 
     const int32_t j0 = uniform(__shfl(my_j, 0)), j1 = uniform(__shfl(my_j, 1));
     if (j0 < j1)
       scan_fast_chi<R, COUNT, 0, SURR, K>(rec, sp, j0, j1, S, slice, X0, rl, act, R(0), rbx, smax, chi_none,
-                                          chi_mixed, c0, c1, G, acc, cnt, n_used, a);
+                                          chi_mixed, c0, c1, G, acc, cnt, n_used, a, cq);
   } else {
     const R ra = sizeof(R) == 4 ? R(iv->ra32) : R(iv->ra64);
     for (int side = 0; side < 2; ++side) {
@@ -400,10 +488,10 @@ __device__ __forceinline__ void region_fast(const Geometry& G, const LevelArgs& 
       if (j0 >= j1) continue;
       if (side == 0)
         scan_fast_chi<R, COUNT, 1, SURR, K>(rec, sp, j0, j1, S, slice, X0, rl, act, ra, rbx, smax, chi_none,
-                                            chi_mixed, c0, c1, G, acc, cnt, n_used, a);
+                                            chi_mixed, c0, c1, G, acc, cnt, n_used, a, cq);
       else
         scan_fast_chi<R, COUNT, -1, SURR, K>(rec, sp, j0, j1, S, slice, X0, rl, act, ra, rbx, smax, chi_none,
-                                             chi_mixed, c0, c1, G, acc, cnt, n_used, a);
+                                             chi_mixed, c0, c1, G, acc, cnt, n_used, a, cq);
     }
   }
 #pragma unroll
@@ -455,7 +543,7 @@ __device__ __forceinline__ int stencil_of(const Geometry& G, int l, int64_t m, i
 template <typename R, bool COUNT, bool SURR>
 __device__ __forceinline__ void region_tile(const Geometry& G, const LevelArgs& a, int l, int layer, int lnw, int64_t rel0,
                             int tile_left, const IntervalSet* iv, R* lds_acc, int64_t item_first, Counts& cnt,
-                            uint32_t& n_used) {
+                            uint32_t& n_used, const CoreQueue& cq) {
   using Rec = typename RecOf<R>::T;
   const int lane = threadIdx.x & 63;
   const int nw = 1 << lnw;
@@ -505,16 +593,17 @@ __device__ __forceinline__ void region_tile(const Geometry& G, const LevelArgs& 
     if constexpr (sizeof(R) == 4 && !COUNT && !SURR) {
       if (lnw >= 2) {
         region_fast<R, COUNT, SURR, 4>(G, a, l, layer, lnw, rel0, tile_left, iv, lds_acc, item_first, my_j, cnt,
-                                       n_used);
+                                       n_used, cq);
         return;
       }
       if (lnw == 1) {
         region_fast<R, COUNT, SURR, 2>(G, a, l, layer, lnw, rel0, tile_left, iv, lds_acc, item_first, my_j, cnt,
-                                       n_used);
+                                       n_used, cq);
         return;
       }
     }
-    region_fast<R, COUNT, SURR, 1>(G, a, l, layer, lnw, rel0, tile_left, iv, lds_acc, item_first, my_j, cnt, n_used);
+    region_fast<R, COUNT, SURR, 1>(G, a, l, layer, lnw, rel0, tile_left, iv, lds_acc, item_first, my_j, cnt, n_used,
+                                   cq);
     return;
   }
   R acc = R(0);
@@ -807,7 +896,7 @@ __device__ __forceinline__ void band_lines(const Geometry& G, const LevelArgs& a
 // item into region tiles, then into band groups of 64 nodes; node sums meet in
 // LDS and are written once.
 template <typename R, bool COUNT, bool SURR>
-__global__ void __launch_bounds__(256) k_level(Geometry G, LevelArgs a_in) {
+__device__ __forceinline__ void level_body(const Geometry& G, const LevelArgs& a_in) {
   extern __shared__ char smem_raw[];
   R* lds_acc = reinterpret_cast<R*>(smem_raw);
   LevelArgs a = a_in;
@@ -834,6 +923,15 @@ __global__ void __launch_bounds__(256) k_level(Geometry G, LevelArgs a_in) {
   }
   __shared__ int64_t s_item;
   const int wv = threadIdx.x >> 6;
+  CoreQueue cq{nullptr, nullptr, nullptr, nullptr};
+  if constexpr (sizeof(R) == 4 && !COUNT && !SURR) {
+    __shared__ float s_cq[4][kCoreQueue + 128];
+    __shared__ uint8_t s_cqs[4][kCoreQueue];
+    cq.x = s_cq[wv];
+    cq.y = s_cq[wv] + kCoreQueue;
+    cq.amp = s_cq[wv] + kCoreQueue + 64;
+    cq.src = s_cqs[wv];
+  }
   const int lane = threadIdx.x & 63;
   const int64_t total = a.n_tiles * a.n_layers;
   for (;;) {
@@ -862,7 +960,7 @@ __global__ void __launch_bounds__(256) k_level(Geometry G, LevelArgs a_in) {
     const int ntile = (count + (1 << lnw) - 1) >> lnw;
     for (int t = wv; t < ntile; t += 4)
       region_tile<R, COUNT, SURR>(G, a, l, layer, lnw, first + ((int64_t)t << lnw), count - (t << lnw), iv, lds_acc,
-                            first, cnt, n_used);
+                            first, cnt, n_used, cq);
     __syncthreads();
     // residual-band pass
     if (l < kLevels - 1 && iv->n_jump > 0) {
@@ -921,11 +1019,16 @@ __global__ void __launch_bounds__(256) k_level(Geometry G, LevelArgs a_in) {
 
 }  // namespace marfa
 
-// Defines the launcher of one instantiation of k_level.
-#define MARFA_LEVEL_LAUNCHER(NAME, R, COUNT, SURR)                                                \
+// Defines one instantiation of the level kernel and its launcher; WAVES is
+// the occupancy (wavefronts per SIMD) the register allocation must allow.
+#define MARFA_LEVEL_LAUNCHER(TAG, R, COUNT, SURR, WAVES)                                          \
   namespace marfa {                                                                              \
-  void NAME(const Geometry& G, const LevelArgs& a, int grid, hipStream_t s) {                    \
+  __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES)))             \
+      k_level_##TAG(Geometry G, LevelArgs a) {                                                   \
+    level_body<R, COUNT, SURR>(G, a);                                                            \
+  }                                                                                              \
+  void launch_level_##TAG(const Geometry& G, const LevelArgs& a, int grid, hipStream_t s) {      \
     const size_t smem = (size_t)a.max_item * sizeof(R);                                           \
-    k_level<R, COUNT, SURR><<<grid, 256, smem, s>>>(G, a);                                        \
+    k_level_##TAG<<<grid, 256, smem, s>>>(G, a);                                                 \
   }                                                                                              \
   }

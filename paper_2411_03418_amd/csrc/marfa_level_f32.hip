@@ -1,4 +1,4 @@
-// marfa_level_f32.hip -- k_level<float, false, false> and its launcher.
+// marfa_level_f32.hip -- the level kernel <float, false, false> and its launcher.
 #include "marfa_level.h"
 
-MARFA_LEVEL_LAUNCHER(launch_level_f32, float, false, false)
+MARFA_LEVEL_LAUNCHER(f32, float, false, false, 4)

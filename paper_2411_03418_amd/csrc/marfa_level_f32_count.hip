@@ -1,4 +1,4 @@
-// marfa_level_f32_count.hip -- k_level<float, true, false> and its launcher.
+// marfa_level_f32_count.hip -- the level kernel <float, true, false> and its launcher.
 #include "marfa_level.h"
 
-MARFA_LEVEL_LAUNCHER(launch_level_f32_count, float, true, false)
+MARFA_LEVEL_LAUNCHER(f32_count, float, true, false, 1)

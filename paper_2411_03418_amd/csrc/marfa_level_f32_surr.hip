@@ -1,4 +1,4 @@
-// marfa_level_f32_surr.hip -- k_level<float, false, true> and its launcher.
+// marfa_level_f32_surr.hip -- the level kernel <float, false, true> and its launcher.
 #include "marfa_level.h"
 
-MARFA_LEVEL_LAUNCHER(launch_level_f32_surr, float, false, true)
+MARFA_LEVEL_LAUNCHER(f32_surr, float, false, true, 1)
