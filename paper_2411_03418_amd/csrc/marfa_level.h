@@ -94,9 +94,9 @@ __device__ __forceinline__ R core_value(R dcm, R xs, R gam, R amp, const Geometr
 }
 
 // S' F(d) (without chi and the cut-off) for the Voigt shape (Lorentz: ae = 0)
-// outside the core: the asymptotic wing series with a wave-uniform number of
-// terms.  `live` marks lanes whose value is used (they alone steer the term
-// count).  The wing is A Q sum with A = S' gamma_L / pi and
+// outside the core: the asymptotic wing series, each lane stopping at its own
+// term count (so a pair's value does not depend on the pairs that share its
+// wavefront).  `live` marks lanes whose value is used.  The wing is A Q sum with A = S' gamma_L / pi and
 // Q = 1/(d^2 + gamma_L^2).  `core` returns whether the pair is live and in the
 // core (|z| < sqrt(kZ2)), where the returned value is not the line shape.
 template <typename R, bool COUNT>
@@ -118,7 +118,7 @@ __device__ __forceinline__ R shape_wing(R dcm, const typename RecOf<R>::T& L, bo
     if constexpr (sizeof(R) == 4) return e >= Series<float>::thr[k];
     else return R((2 * k + 1) * (2 * k - 1)) * ck_prev * e >= eps;
   };
-  if (__builtin_amdgcn_ballot_w64(wing && more(2, e))) {
+  if (wing && more(2, e)) {
     const R t = U - R(1);
     R Um = R(1), ck = e;
 #pragma unroll
@@ -128,8 +128,8 @@ __device__ __forceinline__ R shape_wing(R dcm, const typename RecOf<R>::T& L, bo
       Um = U;
       U = Un;
       sum += ck * U;
-      if (COUNT && wing) cnt.terms++;
-      if (k + 1 >= Series<R>::kMax || !__builtin_amdgcn_ballot_w64(wing && more(k + 1, ck))) break;
+      if (COUNT) cnt.terms++;
+      if (k + 1 >= Series<R>::kMax || !more(k + 1, ck)) break;
     }
   }
   core_out = live && core;
@@ -145,9 +145,7 @@ __device__ __forceinline__ R shape_fast(R d, const typename RecOf<R>::T& L, cons
   const R dcm = d * R(kH0);
   bool core;
   R f = shape_wing<R, COUNT>(dcm, L, live, cnt, core);
-  if (__builtin_amdgcn_ballot_w64(core)) {
-    if (core) f = core_value<R>(dcm, L.xs, L.gam, R(L.amp), G);
-  }
+  if (core) f = core_value<R>(dcm, L.xs, L.gam, R(L.amp), G);
   return f;
 }
 
@@ -787,7 +785,8 @@ __device__ __forceinline__ void band_chunk(const typename RecOf<R>::T& L, int32_
       const bool tl = ad <= cfine && !(l > ls && ad < b_prev);
       const bool need = use && tl && !in_reg;
       R gl = R(0);
-      if (__builtin_amdgcn_ballot_w64(need))
+      // the learned shape is evaluated by whole wavefronts; the plain one per lane
+      if (SURR ? __builtin_amdgcn_ballot_w64(need) != 0 : need)
         gl = g_band<R, COUNT, SURR>(d, L, sp, jl, G, cfine, need, cnt, a, chi_mode, cc0, cc1);
       const double tt = (double)jj / (double)RHO;
       R interp = R(0);
