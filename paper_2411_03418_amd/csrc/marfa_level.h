@@ -720,6 +720,60 @@ __device__ __forceinline__ void band_group(const Geometry& G, const LevelArgs& a
   if (active) lds_acc[m - G.lo[l] - item_first] += acc;
 }
 
+// Segmented inclusive sum over the lanes of a wavefront, for a key that is
+// non-decreasing over the lanes (a segment = lanes with equal keys), with DPP
+// lane shifts (no LDS round trips): shifts by 1, 2, 4 and 8 inside each row of
+// 16 lanes, then the broadcasts of lane 15 of a row to the next row and of lane
+// 31 to the upper half.  Each step adds the shifted partial sum where its
+// source lane lies in the same segment.  `last` marks the last lane of each
+// segment, which ends with the segment's sum.
+constexpr int kDppRowShr1 = 0x111, kDppRowShr2 = 0x112, kDppRowShr4 = 0x114, kDppRowShr8 = 0x118;
+constexpr int kDppRowBcast15 = 0x142, kDppRowBcast31 = 0x143, kDppWaveShl1 = 0x130;
+struct SegSum {
+  float m[6];   // 1 where step i's source lane is in this lane's segment
+  bool last;
+};
+__device__ __forceinline__ SegSum seg_prepare(int32_t key) {
+  SegSum g;
+  const int32_t none = ~key;   // never equal to key: lanes without a source keep it
+  const int32_t k1 = __builtin_amdgcn_update_dpp(none, key, kDppRowShr1, 0xf, 0xf, false);
+  const int32_t k2 = __builtin_amdgcn_update_dpp(none, key, kDppRowShr2, 0xf, 0xf, false);
+  const int32_t k4 = __builtin_amdgcn_update_dpp(none, key, kDppRowShr4, 0xf, 0xf, false);
+  const int32_t k8 = __builtin_amdgcn_update_dpp(none, key, kDppRowShr8, 0xf, 0xf, false);
+  const int32_t k15 = __builtin_amdgcn_update_dpp(none, key, kDppRowBcast15, 0xa, 0xf, false);
+  const int32_t k31 = __builtin_amdgcn_update_dpp(none, key, kDppRowBcast31, 0xc, 0xf, false);
+  const int32_t kn = __builtin_amdgcn_update_dpp(none, key, kDppWaveShl1, 0xf, 0xf, false);
+  g.m[0] = k1 == key ? 1.0f : 0.0f;
+  g.m[1] = k2 == key ? 1.0f : 0.0f;
+  g.m[2] = k4 == key ? 1.0f : 0.0f;
+  g.m[3] = k8 == key ? 1.0f : 0.0f;
+  g.m[4] = k15 == key ? 1.0f : 0.0f;
+  g.m[5] = k31 == key ? 1.0f : 0.0f;
+  g.last = kn != key;
+  return g;
+}
+template <int CTRL, int RMASK>
+__device__ __forceinline__ float dpp_shift(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, RMASK, 0xf, false));
+}
+template <int CTRL, int RMASK>
+__device__ __forceinline__ double dpp_shift(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, RMASK, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, RMASK, 0xf, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+template <typename R>
+__device__ __forceinline__ R seg_sum(R v, const SegSum& g) {
+  v = fma(dpp_shift<kDppRowShr1, 0xf>(v), R(g.m[0]), v);
+  v = fma(dpp_shift<kDppRowShr2, 0xf>(v), R(g.m[1]), v);
+  v = fma(dpp_shift<kDppRowShr4, 0xf>(v), R(g.m[2]), v);
+  v = fma(dpp_shift<kDppRowShr8, 0xf>(v), R(g.m[3]), v);
+  v = fma(dpp_shift<kDppRowBcast15, 0xa>(v), R(g.m[4]), v);
+  v = fma(dpp_shift<kDppRowBcast31, 0xc>(v), R(g.m[5]), v);
+  return v;
+}
+
 // One chunk of 64 lines of the line-major band pass for one jump and side:
 // NC candidate centres from kc0 with NSP-point stencils (see band_lines).
 template <typename R, bool COUNT, int RHO, bool SURR, int NSP, int NC>
@@ -742,17 +796,10 @@ __device__ __forceinline__ void band_chunk(const typename RecOf<R>::T& L, int32_
     T1[i] = act ? g : R(0);
   }
   // segments of lanes with equal kc0 (non-decreasing over lanes)
-  const int32_t u32 = (int32_t)kc0;
-  uint32_t same = 0;
-#pragma unroll
-  for (int st = 0; st < 6; ++st) {
-    const int32_t uo = __shfl_up(u32, 1 << st);
-    if (lane >= (1 << st) && uo == u32) same |= 1u << st;
-  }
-  const int32_t un = __shfl_down(u32, 1);
-  const bool seg_end = lane == 63 || un != u32;
+  const SegSum seg = seg_prepare((int32_t)kc0);
+  const bool seg_end = seg.last;
   // at fine levels lines are sparse: no two lanes share a centre and the merge is skipped
-  const bool merge = __builtin_amdgcn_ballot_w64(same != 0u) != 0;
+  const bool merge = __builtin_amdgcn_ballot_w64(!seg.last) != 0;
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
     const int64_t kc = kc0 + c;
@@ -794,13 +841,7 @@ __device__ __forceinline__ void band_chunk(const typename RecOf<R>::T& L, int32_
       for (int i = 0; i < NSP; ++i) interp += R(lagrange_w<H>(i - H, tt)) * T1[c + i];
       const R v0 = (need ? gl : R(0)) - interp;
       R v = use ? v0 : R(0);
-      if (merge) {
-#pragma unroll
-        for (int st = 0; st < 6; ++st) {
-          const R vo = __shfl_up(v, 1 << st);
-          if (same & (1u << st)) v += vo;
-        }
-      }
+      if (merge) v = seg_sum<R>(v, seg);
       if (seg_end && own) lds_acc[m - base] += v;
       if (COUNT && use) { n_band++; if (!in_reg) n_used++; }
     }
