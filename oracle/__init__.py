@@ -17,9 +17,16 @@ _SO = os.path.join(_HERE, "liboracle.so")
 _SRC = os.path.join(_HERE, "marfa_oracle.c")
 
 
+_DEPS = [_SRC, os.path.join(_HERE, "marfa_oracle.h"), os.path.join(_HERE, "orc_user.h")]
+
+
 def build() -> str:
-    """Compile the oracle with gcc (IEEE double arithmetic, no fast-math)."""
+    """Compile the oracle with gcc (IEEE double arithmetic, no fast-math).
+    ORC_USER_HEADER=/abs/path.h substitutes the user line shape and chi."""
     cmd = ["gcc", "-O2", "-fPIC", "-shared", "-Wall", "-o", _SO, _SRC, "-lm", "-lpthread"]
+    user = os.environ.get("ORC_USER_HEADER")
+    if user:
+        cmd.insert(1, f'-DORC_USER_HEADER="{user}"')
     subprocess.run(cmd, check=True)
     return _SO
 
@@ -53,7 +60,7 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+        if not os.path.exists(_SO) or os.path.getmtime(_SO) < max(os.path.getmtime(p) for p in _DEPS):
             build()
         L = C.CDLL(_SO)
         d, i64, i32, vp = C.c_double, C.c_int64, C.c_int32, C.c_void_p
@@ -64,9 +71,12 @@ def lib():
         L.orc_voigt_K_vec.argtypes = [i64, vp, vp, vp]
         L.orc_chi.restype = d
         L.orc_chi.argtypes = [i32, d]
+        L.orc_user_chi_breaks.restype = i32
+        L.orc_user_chi_breaks.argtypes = [C.c_void_p, i32]
         L.orc_shape.restype = d
         L.orc_shape.argtypes = [i32, d, d, d]
         L.orc_line_state_of.argtypes = [C.POINTER(_Lines), C.POINTER(_Layer), i64, C.POINTER(_State)]
+        L.orc_line_states.argtypes = [C.POINTER(_Lines), C.POINTER(_Layer), vp, vp, vp, vp]
         L.orc_number_density.restype = d
         L.orc_number_density.argtypes = [C.POINTER(_Layer)]
         L.orc_direct.argtypes = [C.POINTER(_Lines), C.POINTER(_Layer), C.POINTER(_Request), vp, i64,
@@ -125,6 +135,15 @@ def chi(kind: int, absd: float) -> float:
     return lib().orc_chi(int(kind), float(absd))
 
 
+def user_chi_breaks() -> list:
+    """Ascending |d| [cm^-1] where the compiled-in user chi or its slope jumps."""
+    buf = np.zeros(16, np.float64)
+    n = lib().orc_user_chi_breaks(_ptr(buf), 16)
+    if n < 0:
+        raise RuntimeError("orc_user_chi_breaks failed")
+    return [float(v) for v in buf[:n]]
+
+
 def shape(kind: int, d: float, gamma_L: float, alpha_D: float) -> float:
     return lib().orc_shape(int(kind), float(d), float(gamma_L), float(alpha_D))
 
@@ -135,6 +154,16 @@ def line_state(lines, layer, j: int):
     lay = _layer(layer)
     lib().orc_line_state_of(C.byref(k.s), C.byref(lay), int(j), C.byref(st))
     return dict(S=st.S, gamma_L=st.gamma_L, alpha_D=st.alpha_D, nu_t=st.nu_t)
+
+
+def line_states(lines, layer):
+    """line_state for every line: dict of arrays S, gamma_L, alpha_D, nu_t."""
+    k = _Keep(lines)
+    lay = _layer(layer)
+    out = {f: np.empty(lines.n, np.float64) for f in ("S", "gamma_L", "alpha_D", "nu_t")}
+    rc = lib().orc_line_states(C.byref(k.s), C.byref(lay), *[_ptr(out[f]) for f in ("S", "gamma_L", "alpha_D", "nu_t")])
+    assert rc == 0
+    return out
 
 
 def number_density(layer) -> float:

@@ -12,9 +12,10 @@
  *   Eq.(10)      Tonkov chi-factor, Section 2.3
  *   Section 2.4  eleven-grid interpolation technique, 10 cm^-1 intervals,
  *                finest step 10/20480 cm^-1, 3-point interpolation
- * Readings where the paper is silent are listed in the design doc.
+ * Where the paper is silent, each function states the reading it takes.
  */
 #include "marfa_oracle.h"
+#include "orc_user.h"
 
 #include <math.h>
 #include <pthread.h>
@@ -154,8 +155,9 @@ int orc_voigt_K_vec(int64_t n, const double* x, const double* y, double* out) {
   return 0;
 }
 
-/* Tonkov chi-factor, Eq.(10), with the printed inequalities. */
+/* Tonkov chi-factor, Eq.(10), with the printed inequalities; or the user chi. */
 double orc_chi(int32_t chi, double a) {
+  if (chi == ORC_CHI_USER) return orc_user_chi(a);
   if (chi != ORC_CHI_TONKOV) return 1.0;
   if (a >= 3.0 && a <= 150.0) return 1.084 * exp(-0.027 * a);
   if (a > 150.0 && a <= 300.0) return 0.208 * exp(-0.016 * a);
@@ -163,9 +165,17 @@ double orc_chi(int32_t chi, double a) {
   return 1.0;
 }
 
-/* Normalised line shapes of Eq.(4), Eq.(5) and Eq.(7), all centred at the
- * shifted centre; d = nu - nu~0. */
+/* The user chi's break points (ascending, cm^-1); returns their number. */
+int orc_user_chi_breaks(double* out, int cap) {
+  if (cap < ORC_USER_CHI_NBREAK || (ORC_USER_CHI_NBREAK > 0 && !out)) return -1;
+  for (int i = 0; i < ORC_USER_CHI_NBREAK; ++i) out[i] = orc_user_chi_break[i];
+  return ORC_USER_CHI_NBREAK;
+}
+
+/* Normalised line shapes of Eq.(4), Eq.(5) and Eq.(7), or the user shape, all
+ * centred at the shifted centre; d = nu - nu~0. */
 double orc_shape(int32_t shape, double d, double gL, double aD) {
+  if (shape == ORC_SHAPE_USER) return orc_user_shape(d, gL, aD);
   if (shape == ORC_SHAPE_LORENTZ || (shape == ORC_SHAPE_VOIGT && aD <= 0.0))
     return gL / (kPi * (gL * gL + d * d));
   if (shape == ORC_SHAPE_DOPPLER) {
@@ -195,6 +205,21 @@ int orc_line_state_of(const orc_lines* L, const orc_layer* lay, int64_t j, orc_l
                ((double)L->gamma_air[j] * (p - ps) + (double)L->gamma_self[j] * ps);
   o->alpha_D = nu / kLight * sqrt(2.0 * kLn2 * kBoltz * kAvogadro * T / (L->molar_mass * 1e-3));
   o->nu_t = nu + (double)L->delta_air[j] * p;
+  return 0;
+}
+
+/* the line states of every line of the list (arrays of L->n values) */
+int orc_line_states(const orc_lines* L, const orc_layer* lay, double* S, double* gamma_L, double* alpha_D,
+                    double* nu_t) {
+  if (!L || !lay || !S || !gamma_L || !alpha_D || !nu_t) return -1;
+  for (int64_t j = 0; j < L->n; ++j) {
+    orc_line_state st;
+    orc_line_state_of(L, lay, j, &st);
+    S[j] = st.S;
+    gamma_L[j] = st.gamma_L;
+    alpha_D[j] = st.alpha_D;
+    nu_t[j] = st.nu_t;
+  }
   return 0;
 }
 
@@ -463,6 +488,10 @@ static int jumps_of(const grid_geom* G, const gline* ln, int l, double* q) {
     for (int i = 0; i < 3; ++i)
       if (br[i] >= lo && br[i] <= G->c) q[n++] = br[i];
   }
+  _Static_assert(ORC_USER_CHI_NBREAK <= 6, "q holds 8 jumps");
+  if (G->chi == ORC_CHI_USER)
+    for (int i = 0; i < ORC_USER_CHI_NBREAK; ++i)
+      if (orc_user_chi_break[i] >= lo && orc_user_chi_break[i] <= G->c) q[n++] = orc_user_chi_break[i];
   return n;
 }
 

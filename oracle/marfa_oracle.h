@@ -46,8 +46,9 @@ typedef struct {
   double q_ratio;           /* Q(296)/Q(T); <= 0 selects 296/T */
 } orc_layer;
 
-enum { ORC_SHAPE_VOIGT = 0, ORC_SHAPE_LORENTZ = 1, ORC_SHAPE_DOPPLER = 2 };
-enum { ORC_CHI_NONE = 0, ORC_CHI_TONKOV = 1 };
+/* USER: the compiled-in orc_user_shape / orc_user_chi of orc_user.h */
+enum { ORC_SHAPE_VOIGT = 0, ORC_SHAPE_LORENTZ = 1, ORC_SHAPE_DOPPLER = 2, ORC_SHAPE_USER = 3 };
+enum { ORC_CHI_NONE = 0, ORC_CHI_TONKOV = 1, ORC_CHI_USER = 2 };
 enum { ORC_OUT_SIGMA = 0, ORC_OUT_K_KM = 1 };
 
 typedef struct {
@@ -72,10 +73,15 @@ double orc_voigt_K(double x, double y);
 /* element-wise K over n points */
 int orc_voigt_K_vec(int64_t n, const double* x, const double* y, double* out);
 double orc_chi(int32_t chi, double absd);
+/* break points of the user chi (ascending, cm^-1) into out[cap]; their number, or -1 */
+int orc_user_chi_breaks(double* out, int cap);
 /* normalised line shape F(d) [cm], d = nu - nu~0 */
 double orc_shape(int32_t shape, double d, double gamma_L, double alpha_D);
 int orc_line_state_of(const orc_lines* L, const orc_layer* lay, int64_t j, orc_line_state* out);
 /* number density of the absorber [cm^-3] */
+/* orc_line_state_of for every line: S, gamma_L, alpha_D, nu_t arrays of L->n values. */
+int orc_line_states(const orc_lines* L, const orc_layer* lay, double* S, double* gamma_L, double* alpha_D,
+                    double* nu_t);
 double orc_number_density(const orc_layer* lay);
 
 /* Definition (direct sum) at nodes nu = nodes[i] * 2^-11. */

@@ -529,3 +529,68 @@ def test_grid_5point_exact_on_a_line_pair_symmetric():
     L, lay = _one_line(1005.0, 0.07, p=0.3)
     g = O.grid(L, lay, nu_begin=1000.0, nu_end=1010.0, cutoff=25.0, R=12.0, stencil=5)
     assert np.allclose(g, g[::-1], rtol=5e-5, atol=0)
+
+
+# ---------------------------------------------------------- user plug-ins
+# The oracle's compiled-in user line shape (the Thompson-Cox-Hastings
+# pseudo-Voigt) and user chi (a step to 0.95 at 2 cm^-1, then
+# 0.95 exp(-(a - 2) / 30) / (1 + ((a - 2) / 60)^2)), Sections 2.2-2.3.
+
+@pytest.mark.parametrize("gL,aD", [(0.05, 0.0), (0.0, 0.003), (0.01, 0.003), (0.003, 0.01),
+                                   (0.05, 0.05), (1e-4, 2e-3)])
+def test_user_shape_unit_area_and_near_voigt(gL, aD):
+    f = lambda d: O.shape(3, d, gL, aD)
+    W = max(gL, aD)
+    area = 2 * (si.quad(f, 0, 50 * W, limit=500)[0] + si.quad(f, 50 * W, np.inf, limit=500)[0])
+    assert abs(area - 1) < 1e-9
+    d = np.linspace(-10 * W, 10 * W, 801)
+    pv = np.array([f(x) for x in d])
+    v = np.array([O.shape(0 if aD > 0 else 1, x, gL, aD) for x in d])
+    # the TCH fit stays within about 1.2 % of the Voigt peak
+    assert np.abs(pv - v).max() < 0.015 * v.max()
+    assert all(f(x) == f(-x) for x in d)
+
+
+def test_user_shape_pure_limits():
+    """With no Doppler width the mixing is 1.36603 - 0.47719 + 0.11116 = 1 and
+    the width 2 gamma_L: the Lorentz profile; with no Lorentz width the Gauss
+    profile of HWHM alpha_D (Eq.(4), Eq.(5))."""
+    for d in (0.0, 0.013, 0.4, 7.0):
+        assert O.shape(3, d, 0.07, 0.0) == pytest.approx(0.07 / math.pi / (0.07**2 + d * d), rel=1e-12)
+        g = math.sqrt(math.log(2) / math.pi) / 0.004 * math.exp(-math.log(2) * d * d / 0.004**2)
+        assert O.shape(3, d, 0.0, 0.004) == pytest.approx(g, rel=1e-12, abs=1e-300)
+        assert O.shape(3, d, 0.0, 0.004) == pytest.approx(O.shape(2, d, 0.0, 0.004), rel=1e-12, abs=1e-300)
+
+
+def test_user_chi_step_and_decay():
+    assert O.user_chi_breaks() == [2.0]
+    assert O.chi(2, 0.0) == 1.0 and O.chi(2, 2.0) == 1.0
+    assert O.chi(2, 2.0 * (1 + 1e-12)) == pytest.approx(0.95, rel=1e-7)
+    assert O.chi(2, 32.0) == pytest.approx(0.95 / math.e / 1.25, rel=1e-14)
+    assert O.chi(2, 62.0) == pytest.approx(0.95 * math.exp(-2.0) / 2.0, rel=1e-14)
+    a = np.linspace(2.001, 500.0, 1000)
+    v = np.array([O.chi(2, x) for x in a])
+    assert np.all(np.diff(v) < 0)
+
+
+@pytest.mark.parametrize("case", [
+    dict(nu0=1005.0, gamma=0.075, shape=3),
+    dict(nu0=1005.00013, gamma=0.075, shape=3, chi=2, c=40.0),
+    dict(nu0=1003.7, gamma=0.09, p=10.0, chi=2, c=60.0),   # broad line, break inside the range
+    dict(nu0=1001.9, gamma=0.3, chi=2, c=4.0),             # break and cut-off close together
+    dict(nu0=1004.2, gamma=0.06, p=0.4, chi=2, shape=3, lt=1),
+])
+def test_grid_with_user_plugins_matches_definition(case):
+    """The grid method reproduces the definition with the user shape and chi:
+    a break missing from the residual bands would smear the 5 % step at 2 cm^-1."""
+    L, lay = _one_line(case["nu0"], case["gamma"], p=case.get("p", 1.0))
+    err = _grid_vs_direct(L, lay, nu_begin=1000.0, nu_end=1010.0, cutoff=case.get("c", 25.0),
+                          chi=case.get("chi", 0), shape=case.get("shape", 0), level_table=case.get("lt", 0))
+    assert err < 5e-5, err
+
+
+def test_grid_user_chi_many_lines():
+    L = synth.make_lines(100, 990.0, 1020.0, 14, shift=True)
+    for lay in [(0.1, 250.0, 0.1, 0.0), (3.0, 500.0, 3.0, 0.0)]:
+        err = _grid_vs_direct(L, lay, nu_begin=1000.0, nu_end=1010.0, cutoff=25.0, chi=2, shape=3)
+        assert err < 5e-5, (lay, err)
