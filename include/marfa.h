@@ -10,8 +10,12 @@
  * pressure-temperature layer, evaluated with the eleven-grid interpolation
  * technique of Section 2.4 (line centres on the finest grid, wings on ten
  * coarser grids, 3-point interpolation back to the finest grid).  Line shapes:
- * Voigt (default, Eq.(7)-(8)), Lorentz (Eq.(4)), Doppler (Eq.(5)); wing factor:
- * none or Tonkov (Eq.(10), Section 2.3).  Line parameters follow the database
+ * Voigt (default, Eq.(7)-(8)), Lorentz (Eq.(4)), Doppler (Eq.(5)) or a user
+ * shape; wing factor: none, Tonkov (Eq.(10), Section 2.3) or a user chi.  The
+ * user shape and chi are compile-time plug-ins (the user-selectable shape and
+ * chi functions of Sections 2.2-2.3): structs MarfaUserShape / MarfaUserChi in
+ * a header built into the kernels (the shipped example: the Thompson-Cox-
+ * Hastings pseudo-Voigt and a stepped stretched-exponential chi).  Line parameters follow the database
  * record of Appendix B; their temperature/pressure dependences are the HITRAN
  * forms the paper cites (Section 2.2).
  *
@@ -42,8 +46,17 @@ typedef enum {
   MARFA_E_IO = -6            /* a file could not be opened or written */
 } marfa_status;
 
-typedef enum { MARFA_SHAPE_VOIGT = 0, MARFA_SHAPE_LORENTZ = 1, MARFA_SHAPE_DOPPLER = 2 } marfa_shape;
-typedef enum { MARFA_CHI_NONE = 0, MARFA_CHI_TONKOV = 1 } marfa_chi;
+typedef enum {
+  MARFA_SHAPE_VOIGT = 0,
+  MARFA_SHAPE_LORENTZ = 1,
+  MARFA_SHAPE_DOPPLER = 2,
+  MARFA_SHAPE_USER = 3        /* the compiled-in MarfaUserShape */
+} marfa_shape;
+typedef enum {
+  MARFA_CHI_NONE = 0,
+  MARFA_CHI_TONKOV = 1,
+  MARFA_CHI_USER = 2          /* the compiled-in MarfaUserChi, with its declared breaks */
+} marfa_chi;
 typedef enum { MARFA_OUT_SIGMA_CM2 = 0, MARFA_OUT_K_PER_KM = 1 } marfa_output;
 typedef enum { MARFA_EVAL_PLAIN = 0, MARFA_EVAL_SURROGATE = 1 } marfa_eval;
 
@@ -101,21 +114,37 @@ typedef struct {
 
 typedef struct marfa_plan marfa_plan;
 
-/* Per-plan counters from the last marfa_plan_count() (exact (node, line) pairs
- * evaluated, split by level and by line-shape branch). */
+/* Per-plan counters from the last marfa_plan_count(): exact (node, line) pairs
+ * evaluated, split by level and by line-shape branch, and the work they stand
+ * for.  Counted flops are a static count of the single-precision kernel
+ * source per unit of work (fused multiply-add = 2, add / multiply = 1,
+ * reciprocal / exp2 = 1; compares, selects and integer address arithmetic not
+ * counted): flops_per_eval for one line-shape evaluation of the wing form with
+ * its distance, chi factor and accumulation (every evaluation, core ones
+ * included, computes it), flops_per_core for the Taylor core added on top,
+ * flops_per_term per further term of the wing series, flops_per_band per
+ * residual-band correction (the stencil interpolation and the difference),
+ * flops_per_cascade per interpolated node of the cascade.  Algorithmic bytes
+ * count each line record read once per layer and every level and output node
+ * written once. */
 typedef struct {
   int64_t points_per_layer;       /* output nodes per layer */
   int32_t n_layers;
   int64_t lines_total;            /* lines in the plan */
   int64_t lines_kept;             /* sum over layers of lines kept after pruning */
   int64_t pairs_level[11];        /* pairs with a non-zero contribution, per level */
-  int64_t pairs_core;             /* Voigt pairs in the core branch (|z| < 6) */
-  int64_t pairs_wing;             /* pairs in the wing series branch */
+  int64_t pairs_core;             /* Voigt evaluations in the core branch (|z| < 6) */
+  int64_t pairs_wing;             /* evaluations in the wing series branch */
   int64_t pairs_band;             /* pairs carrying a residual-band correction */
-  int64_t wing_terms;             /* sum over wing pairs of series terms beyond the first */
+  int64_t wing_terms;             /* sum over wing evaluations of series terms beyond the first */
   int64_t level_nodes;            /* nodes of levels 1..10 over all layers */
   int64_t iters_level[11];        /* wavefront iterations over line windows, per level */
   int64_t band_iters_level[11];   /* of which ran a residual-band correction */
+  double flops_per_eval, flops_per_core, flops_per_term, flops_per_band, flops_per_cascade;
+  double flops_level;             /* counted flops of the level kernel, all layers */
+  double flops_cascade;           /* counted flops of the cascade, all layers */
+  double bytes_level;             /* algorithmic bytes of the level kernel: records read, level and output nodes written */
+  double bytes_cascade;           /* algorithmic bytes of the cascade: 3 (5) coarse reads and 1 read-modify-write per node */
 } marfa_stats;
 
 /* Create a plan: validates and copies the inputs, sorts lines by nu0, uploads

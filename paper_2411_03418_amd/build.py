@@ -27,7 +27,10 @@ FLAGS = [
 
 def _compile(hipcc, src):
     obj = os.path.join(OBJDIR, os.path.basename(src).replace(".hip", ".o"))
-    cmd = [hipcc, *FLAGS, "-c", "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc"),
+    # MARFA_USER_HEADER=/abs/path.h compiles another user line shape and chi in
+    user = os.environ.get("MARFA_USER_HEADER")
+    extra = [f'-DMARFA_USER_HEADER="{user}"'] if user else []
+    cmd = [hipcc, *FLAGS, *extra, "-c", "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc"),
            "-o", obj, os.path.join(HERE, src)]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:

@@ -9,6 +9,7 @@
 #include <type_traits>
 
 #include "marfa_internal.h"
+#include "marfa_user.h"
 
 namespace marfa {
 
@@ -20,6 +21,7 @@ constexpr double kNA = 6.02214076e23;         // [1/mol]
 constexpr double kCLight = 299792458.0;       // [m/s]
 constexpr double kAtmPa = 101325.0;
 constexpr double kLn2d = 0.693147180559945309417;
+constexpr double kSqrtLn2 = 0.832554611157697756353;
 constexpr double kInvPi = 0.318309886183790671538;
 constexpr double kInvSqrtPi = 0.564189583547756286948;
 constexpr double kH0 = 1.0 / 2048.0;
@@ -147,6 +149,11 @@ struct Counts {
   uint32_t band_iters;   // iterations that ran the band correction
 };
 
+// shapes evaluated pair by pair through line_value (no wing series or core queue)
+__host__ __device__ __forceinline__ bool generic_shape(const Geometry& G) {
+  return G.shape == MARFA_SHAPE_DOPPLER || G.shape == MARFA_SHAPE_USER;
+}
+
 // g(d) = S' F(d) chi(|d|) [|d| <= c], d in fine units
 template <typename R, bool COUNT>
 __device__ __forceinline__ R line_value(R d, const typename RecOf<R>::T& L, R Sp, const Geometry& G, R cfine,
@@ -161,6 +168,10 @@ __device__ __forceinline__ R line_value(R d, const typename RecOf<R>::T& L, R Sp
   } else if (G.shape == MARFA_SHAPE_DOPPLER) {
     R x = R(L.xs) * dcm;
     f = R(L.xs) * R(kInvSqrtPi) * exp(-x * x);
+  } else if (G.shape == MARFA_SHAPE_USER) {
+    // xs = sqrt(ln 2) / alpha_D, and 0 for a line without Doppler width
+    const R aD = L.xs > R(0) ? R(kSqrtLn2) / R(L.xs) : R(0);
+    f = MarfaUserShape::f<R>(dcm, R(L.gam), aD);
   } else {
     R x = R(L.xs) * dcm;
     R y = R(L.xs) * R(L.gam);
@@ -179,7 +190,9 @@ __device__ __forceinline__ R line_value(R d, const typename RecOf<R>::T& L, R Sp
       if (COUNT) cnt.core++;
     }
   }
-  R chi = (G.chi == MARFA_CHI_TONKOV) ? tonkov<R>(ad * R(kH0)) : R(1);
+  R chi = R(1);
+  if (G.chi == MARFA_CHI_TONKOV) chi = tonkov<R>(ad * R(kH0));
+  else if (G.chi == MARFA_CHI_USER) chi = MarfaUserChi::chi<R>(ad * R(kH0));
   return Sp * f * chi;
 }
 

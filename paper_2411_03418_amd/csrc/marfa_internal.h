@@ -24,6 +24,25 @@ constexpr int kTaylorSide = 25;
 constexpr int kTaylorTerms = 9;
 constexpr int kTaylorQuads = 5;
 
+// Counted flops per unit of work of the single-precision level kernel, from a
+// static count of its source (marfa_level.h; FMA = 2, add / mul = 1,
+// rcp / exp2 = 1, compares, selects and integer arithmetic not counted):
+//  eval  one wing-form evaluation in the region scan (scan_fast step): distance
+//        (1) and its scale to cm (1); shape_wing: gamma^2 (1), d^2 + gamma^2
+//        (2), 1/. (1), e (1), -4 gamma^2 (1), U_2 (2), 1 + e U_2 (2), A Q sum
+//        (2); chi by its recurrence (1); the product and the sum into the node
+//        (2) -- 17
+//  core  voigt_core32 on top: x, y (2), their lattice offsets (2 + 4), seven
+//        complex Horner steps (56), the last real step (4), the scale (1) -- 69
+//  term  one more series term: the coefficient (2), U's recurrence (2), the
+//        sum (2) -- 6
+//  band  one residual-band correction: the 3-point (5-point) interpolation
+//        (6, 10), the difference (1), the sum into the node (1) -- 8 (12)
+//  cascade  one interpolated node: 3 (5) weights times values (6, 10), the
+//        sum into the finer level (1) -- 7 (11)
+constexpr int kFlopsEval = 17, kFlopsCore = 69, kFlopsTerm = 6;
+constexpr int kFlopsBand3 = 8, kFlopsBand5 = 12, kFlopsCascade3 = 7, kFlopsCascade5 = 11;
+
 // Coefficient tables of a device, computed on the host at first use of the
 // device and kept until the process ends.
 struct DeviceTables {
@@ -191,6 +210,7 @@ struct LevelArgs {
   float mlp_xmax;        // pairs with |x| above it use the plain shape
   float mlp_inv_c;       // 1 / cut-off [cm]
   MlpDev mlp;
+  float* sq;             // the wavefront's queue of learned-shape pairs (LDS; set inside the kernel)
 };
 
 // the coefficient tables of a device prepared by marfa_use_device (device memory)

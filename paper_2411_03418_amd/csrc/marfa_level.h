@@ -62,9 +62,11 @@ template <> struct Series<float> {
 static_assert(Series<float>::thr[2] > 2.5e-4f && Series<float>::thr[2] < 2.6e-4f, "sqrt(1e-6 / 15)");
 template <> struct Series<double> { static constexpr int kMax = 60; };
 
-// chi of Eq.(10) without branches: exp2(c0 + c1 |d|) with the piece chosen by selects
+// chi of Eq.(10) without branches: exp2(c0 + c1 |d|) with the piece chosen by
+// selects; the user chi through its compiled-in function
 template <typename R>
 __device__ __forceinline__ R chi_any(R ad_fine, const Geometry& G) {
+  if (G.chi == MARFA_CHI_USER) return MarfaUserChi::chi<R>(ad_fine * R(kH0));
   if (G.chi != MARFA_CHI_TONKOV) return R(1);
   const R a = ad_fine * R(kH0);
   R c0 = R(0), c1 = R(0);
@@ -202,7 +204,7 @@ __device__ __forceinline__ void core_batch(const CoreQueue& q, const LineRec32& 
 template <typename R, bool COUNT>
 __device__ __forceinline__ R g_any(R d, const typename RecOf<R>::T& L, const R* __restrict__ sp, int32_t j,
                                    const Geometry& G, R cfine, bool live, Counts& cnt) {
-  if (G.shape == MARFA_SHAPE_DOPPLER) return live ? line_value<R, COUNT>(d, L, sp[j], G, cfine, cnt) : R(0);
+  if (generic_shape(G)) return live ? line_value<R, COUNT>(d, L, sp[j], G, cfine, cnt) : R(0);
   const R ad = fabs(d);
   const R v = shape_fast<R, COUNT>(d, L, sp, j, G, live && ad <= cfine, cnt) * chi_any<R>(ad, G);
   return ad <= cfine ? v : R(0);
@@ -232,13 +234,61 @@ __device__ float g_surr(float d, const LineRec32& L, const float* __restrict__ s
   return v;
 }
 
+// Wave-local queue of learned-shape pairs: every lane pushes the pairs it
+// needs (up to kSurrQueue per wavefront), the network then runs on 64 queued
+// pairs at a time, and each lane reads its values back in its own order.
+// Per entry: |x|, y, |d| in cm, and the scale S' sqrt(pi) xs^2 / pi gamma_L
+// ... written A sqrt(pi) xs^2 with A = S' gamma_L / pi; the value replaces the
+// scale.  Layout of a wavefront's queue: four arrays of kSurrQueue floats.
+constexpr int kSurrQueue = 256;
+
+// Push `want` pairs of the calling lanes; returns the slot of each, `n` the
+// wave's running count (uniform).
+__device__ __forceinline__ int surr_push(float* q, bool want, int& n, float x, float y, float ad, float amp) {
+  const uint64_t m = __builtin_amdgcn_ballot_w64(want);
+  const int pos = n + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+  if (want) {
+    q[pos] = fabsf(x);
+    q[kSurrQueue + pos] = y;
+    q[2 * kSurrQueue + pos] = ad;
+    q[3 * kSurrQueue + pos] = amp;
+  }
+  n += __builtin_popcountll(m);
+  return pos;
+}
+
+// Evaluate the n queued pairs (n uniform): S' F(d) chi(|d|) = A sqrt(pi) xs^2 / y Kb(x, y) e^t.
+__device__ __forceinline__ void surr_batch(float* q, int n, const LevelArgs& a) {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  const int lane = threadIdx.x & 63;
+  for (int r = 0; r < n; r += 64) {
+    const int i = r + lane;
+    const bool ok = i < n;
+    const float x = ok ? q[i] : 1.0f;
+    const float y = ok ? q[kSurrQueue + i] : 1.0f;
+    const float ad = ok ? q[2 * kSurrQueue + i] : 0.0f;
+    float f1, f2, f3;
+    mlp_features(x, y, ad, a.mlp_inv_c, f1, f2, f3);
+    const float t = mlp_forward_wave(a.mlp, f1, f2, f3);
+    if (ok) q[3 * kSurrQueue + i] = q[3 * kSurrQueue + i] * __builtin_amdgcn_rcpf(y) * mlp_base(x, y) * __expf(t);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+}
+
+// the learned shape's inputs of one pair: whether it lies in the trained domain
+__device__ __forceinline__ bool surr_domain(float d, const LineRec32& L, const LevelArgs& a, float& x, float& y) {
+  x = L.xs * (d * float(kH0));
+  y = L.xs * L.gam;
+  return y >= kMlpYMin && y <= kMlpYMax && fabsf(x) <= a.mlp_xmax;
+}
+
 // g(d) with the cut-off for the band pass, chi given for the jump's
 // neighbourhood (mode 0: 1, 1: one piece exp2(c0 + c1 |d|), 2: any piece)
 template <typename R, bool COUNT, bool SURR>
 __device__ __forceinline__ R g_band(R d, const typename RecOf<R>::T& L, const R* __restrict__ sp, int32_t j,
                                     const Geometry& G, R cfine, bool live, Counts& cnt, const LevelArgs& a,
                                     int chi_mode, R c0, R c1) {
-  if (SURR || G.shape == MARFA_SHAPE_DOPPLER) return g_eval<R, COUNT, SURR>(d, L, sp, j, G, cfine, live, cnt, a);
+  if (SURR || generic_shape(G)) return g_eval<R, COUNT, SURR>(d, L, sp, j, G, cfine, live, cnt, a);
   const R ad = fabs(d);
   const R f = shape_fast<R, COUNT>(d, L, sp, j, G, live && ad <= cfine, cnt);
   R chi;
@@ -272,7 +322,7 @@ __device__ __forceinline__ void scan_region(const typename RecOf<R>::T* __restri
                                             R b_prev, R b_cur, R& acc, Counts& cnt, uint32_t& n_used,
                                             const LevelArgs& a) {
   using Rec = typename RecOf<R>::T;
-  const bool generic_shape = G.shape == MARFA_SHAPE_DOPPLER;
+  const bool generic = generic_shape(G);
   int32_t jn = j0 + slice;
   Rec Lnext = load_rec(rec, jn < j1 ? jn : j1 - 1);
   for (int32_t J = j0; J < j1; J += S) {
@@ -290,10 +340,10 @@ __device__ __forceinline__ void scan_region(const typename RecOf<R>::T* __restri
     const bool in_reg = in_win && ls <= l && ad >= rlo && ad < b_cur && ad <= cfine;
     R val;
     if constexpr (SURR) {
-      (void)generic_shape;
+      (void)generic;
       const float g = g_surr<COUNT>(d, L, sp, j, G, a, in_reg, cnt);
       val = in_reg ? g : R(0);
-    } else if (!generic_shape) {
+    } else if (!generic) {
       const R g = shape_fast<R, COUNT>(d, L, sp, j, G, in_reg, cnt);
       R chi;
       if (chi_one) chi = R(1);
@@ -386,6 +436,38 @@ __device__ __forceinline__ void scan_fast(const typename RecOf<R>::T* __restrict
         const R chi = chi_of(k, d[k], chi_run);
         acc[k] += reg[k] ? f[k] * chi : R(0);
       }
+      return;
+    }
+    if constexpr (SURR && !COUNT) {
+      // learned shape: pairs in the trained domain through the wave's queue,
+      // the others by the plain shape
+      float f[K];
+      bool reg[K], queued[K];
+      int pos[K];
+      int n = 0;
+      const float amp = L.A * 1.7724538509055160f * L.xs * L.xs;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const float d = float(n0 + k * rl) - fr;
+        bool in_reg;
+        if (SGN > 0) in_reg = d >= ra && d < rbx;
+        else if (SGN < 0) in_reg = d <= -ra && d > -rbx;
+        else in_reg = fabsf(d) < rbx;
+        reg[k] = in_reg && lok && ((act >> k) & 1u);
+        float x, y;
+        const bool dom = surr_domain(d, L, a, x, y);
+        queued[k] = reg[k] && dom;
+        f[k] = 0.0f;
+        if (reg[k] && !dom) f[k] = shape_fast<float, false>(d, L, sp, j, G, true, cnt) * chi_any<float>(fabsf(d), G);
+        pos[k] = surr_push(a.sq, queued[k], n, x, y, fabsf(d * float(kH0)), amp);
+      }
+      if (n > 0) surr_batch(a.sq, n, a);
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        if (queued[k]) f[k] = a.sq[3 * kSurrQueue + pos[k]];
+        acc[k] += reg[k] ? f[k] : 0.0f;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
       return;
     }
 #pragma unroll
@@ -584,11 +666,11 @@ __device__ __forceinline__ void region_tile(const Geometry& G, const LevelArgs& 
     }
   }
   const int32_t my_j = (lane < 2 * nws) ? bk[my_bucket] : 0;
-  if (iv->fast_ok && G.shape != MARFA_SHAPE_DOPPLER) {
+  if (iv->fast_ok && !generic_shape(G)) {
     // K nodes per lane (up to 4, fewer for narrow tiles) in the single-
     // precision plain kernel; one elsewhere (the counting, learned-shape and
     // double-precision kernels are not timed and stay small)
-    if constexpr (sizeof(R) == 4 && !COUNT && !SURR) {
+    if constexpr (sizeof(R) == 4 && !COUNT) {
       if (lnw >= 2) {
         region_fast<R, COUNT, SURR, 4>(G, a, l, layer, lnw, rel0, tile_left, iv, lds_acc, item_first, my_j, cnt,
                                        n_used, cq);
@@ -787,28 +869,54 @@ __device__ __forceinline__ void band_chunk(const typename RecOf<R>::T& L, int32_
   constexpr int H = NSP / 2;
   // T_(l+1) at level-(l+1) nodes kc0-H .. kc0+NC-1+H
   R dd[NC + 2 * H], T1[NC + 2 * H];
+  if constexpr (SURR && !COUNT) {
+    // learned shape: the stencil values through the wave's queue
+    int pos[NC + 2 * H];
+    bool queued[NC + 2 * H];
+    int n = 0;
+    const float amp = L.A * 1.7724538509055160f * L.xs * L.xs;
 #pragma unroll
-  for (int i = 0; i < NC + 2 * H; ++i) {
-    dd[i] = R((int32_t)((kc0 - H + i) * r1) - L.k0) - R(L.frac);
-    const R adi = fabs(dd[i]);
-    const bool act = ok && adi <= cfine && !(l + 1 > ls && adi < b_cur);
-    const R g = g_band<R, COUNT, SURR>(dd[i], L, sp, jl, G, cfine, act, cnt, a, chi_mode, cc0, cc1);
-    T1[i] = act ? g : R(0);
+    for (int i = 0; i < NC + 2 * H; ++i) {
+      dd[i] = float((int32_t)((kc0 - H + i) * r1) - L.k0) - L.frac;
+      const float adi = fabsf(dd[i]);
+      const bool act = ok && adi <= cfine && !(l + 1 > ls && adi < b_cur);
+      float x, y;
+      const bool dom = surr_domain(dd[i], L, a, x, y);
+      queued[i] = act && dom;
+      T1[i] = 0.0f;
+      if (act && !dom) T1[i] = g_any<float, false>(dd[i], L, sp, jl, G, cfine, true, cnt);
+      pos[i] = surr_push(a.sq, queued[i], n, x, y, adi * float(kH0), amp);
+    }
+    if (n > 0) surr_batch(a.sq, n, a);
+#pragma unroll
+    for (int i = 0; i < NC + 2 * H; ++i)
+      if (queued[i]) T1[i] = a.sq[3 * kSurrQueue + pos[i]];
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  } else {
+#pragma unroll
+    for (int i = 0; i < NC + 2 * H; ++i) {
+      dd[i] = R((int32_t)((kc0 - H + i) * r1) - L.k0) - R(L.frac);
+      const R adi = fabs(dd[i]);
+      const bool act = ok && adi <= cfine && !(l + 1 > ls && adi < b_cur);
+      const R g = g_band<R, COUNT, SURR>(dd[i], L, sp, jl, G, cfine, act, cnt, a, chi_mode, cc0, cc1);
+      T1[i] = act ? g : R(0);
+    }
   }
   // segments of lanes with equal kc0 (non-decreasing over lanes)
   const SegSum seg = seg_prepare((int32_t)kc0);
   const bool seg_end = seg.last;
   // at fine levels lines are sparse: no two lanes share a centre and the merge is skipped
   const bool merge = __builtin_amdgcn_ballot_w64(!seg.last) != 0;
+  // does the stencil hull of centre kc0 + c straddle this jump (the smallest
+  // straddled one of the line's class)?
+  bool strad_c[NC];
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
-    const int64_t kc = kc0 + c;
     const R d0 = dd[c], d2 = dd[c + 2 * H];
     const R lo = (d0 * d2 <= R(0)) ? R(0) : fmin(fabs(d0), fabs(d2));
     const R hi = fmax(fabs(d0), fabs(d2));
-    bool strad;
     if (iso) {
-      strad = ok && rq >= lo && rq <= hi;
+      strad_c[c] = ok && rq >= lo && rq <= hi;
     } else {
       R qmin = R(INFINITY);
       const int nj = uniform(iv->n_jump);
@@ -816,25 +924,72 @@ __device__ __forceinline__ void band_chunk(const typename RecOf<R>::T& L, int32_
         const R qi = R(iv->jq[i]);
         if ((iv->jmask[i] & cls) && qi >= lo && qi <= hi) qmin = fmin(qmin, qi);
       }
-      strad = ok && qmin == rq;
+      strad_c[c] = ok && qmin == rq;
     }
+  }
+  // the candidate node m = (kc0 + c) RHO + jj of a lane: distance, whether its
+  // correction is used, and whether it needs the line's own value there
+  auto node = [&](int c, int jj, R& d, bool& use, bool& need, bool& in_reg, bool& own) {
+    const int64_t m = (kc0 + c) * RHO + jj;
+    d = R((int32_t)(m * rl) - L.k0) - R(L.frac);
+    const bool side_ok = side == 0 ? d > R(0) : !(d > R(0));
+    own = m >= m_a && m <= m_b;
+    use = strad_c[c] && own && side_ok;
+    const R ad = fabs(d);
+    const R rlo = (l == ls) ? R(0) : b_prev;
+    in_reg = ls <= l && ad >= rlo && ad < b_cur && ad <= cfine;
+    const bool tl = ad <= cfine && !(l > ls && ad < b_prev);
+    need = use && tl && !in_reg;
+  };
+  R glv[NC][RHO];
+  if constexpr (SURR && !COUNT) {
+    // learned shape: the line's own values at the candidate nodes through the queue
+    int pos[NC][RHO];
+    bool queued[NC][RHO];
+    int n = 0;
+    const float amp = L.A * 1.7724538509055160f * L.xs * L.xs;
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int jj = -RHO / 2 + 1; jj <= RHO / 2; ++jj) {
+        const int ji = jj + RHO / 2 - 1;
+        queued[c][ji] = false;
+        pos[c][ji] = 0;
+        glv[c][ji] = 0.0f;
+        if (jj == 0) continue;
+        R d;
+        bool use, need, in_reg, own;
+        node(c, jj, d, use, need, in_reg, own);
+        float x, y;
+        const bool dom = surr_domain(d, L, a, x, y);
+        queued[c][ji] = need && dom;
+        if (need && !dom) glv[c][ji] = g_any<float, false>(d, L, sp, jl, G, cfine, true, cnt);
+        pos[c][ji] = surr_push(a.sq, queued[c][ji], n, x, y, fabsf(d) * float(kH0), amp);
+      }
+    if (n > 0) surr_batch(a.sq, n, a);
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int ji = 0; ji < RHO; ++ji)
+        if (queued[c][ji]) glv[c][ji] = a.sq[3 * kSurrQueue + pos[c][ji]];
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  }
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
 #pragma unroll
     for (int jj = -RHO / 2 + 1; jj <= RHO / 2; ++jj) {
       if (jj == 0) continue;
-      const int64_t m = kc * RHO + jj;
-      const R d = R((int32_t)(m * rl) - L.k0) - R(L.frac);
-      const bool side_ok = side == 0 ? d > R(0) : !(d > R(0));
-      const bool own = m >= m_a && m <= m_b;
-      const bool use = strad && own && side_ok;
-      const R ad = fabs(d);
-      const R rlo = (l == ls) ? R(0) : b_prev;
-      const bool in_reg = ls <= l && ad >= rlo && ad < b_cur && ad <= cfine;
-      const bool tl = ad <= cfine && !(l > ls && ad < b_prev);
-      const bool need = use && tl && !in_reg;
+      const int64_t m = (kc0 + c) * RHO + jj;
+      R d;
+      bool use, need, in_reg, own;
+      node(c, jj, d, use, need, in_reg, own);
       R gl = R(0);
-      // the learned shape is evaluated by whole wavefronts; the plain one per lane
-      if (SURR ? __builtin_amdgcn_ballot_w64(need) != 0 : need)
-        gl = g_band<R, COUNT, SURR>(d, L, sp, jl, G, cfine, need, cnt, a, chi_mode, cc0, cc1);
+      if constexpr (SURR && !COUNT) {
+        gl = glv[c][jj + RHO / 2 - 1];
+      } else {
+        (void)glv;
+        if (need) gl = g_band<R, COUNT, SURR>(d, L, sp, jl, G, cfine, need, cnt, a, chi_mode, cc0, cc1);
+      }
       const double tt = (double)jj / (double)RHO;
       R interp = R(0);
 #pragma unroll
@@ -846,7 +1001,6 @@ __device__ __forceinline__ void band_chunk(const typename RecOf<R>::T& L, int32_
       if (COUNT && use) { n_band++; if (!in_reg) n_used++; }
     }
   }
-
 }
 
 // Residual-band pass, line-major form, for one wavefront owning the item's
@@ -963,6 +1117,10 @@ __device__ __forceinline__ void level_body(const Geometry& G, const LevelArgs& a
   }
   __shared__ int64_t s_item;
   const int wv = threadIdx.x >> 6;
+  if constexpr (SURR) {
+    __shared__ float s_sq[4][4 * kSurrQueue];
+    a.sq = s_sq[wv];
+  }
   CoreQueue cq{nullptr, nullptr, nullptr, nullptr};
   if constexpr (sizeof(R) == 4 && !COUNT && !SURR) {
     __shared__ float s_cq[4][kCoreQueue + 128];

@@ -20,7 +20,7 @@
 
 #include "marfa.h"
 #include "marfa_internal.h"
-
+#include "marfa_user.h"
 
 using namespace marfa;
 
@@ -254,16 +254,19 @@ static void make_geometry(const marfa_request& rq, double nu_max, Geometry& G) {
   G.b[kLevels - 1] = INFINITY;
   G.hb[kLevels - 1] = 0.0;
   G.c_fine = c;
-  const double br[3] = {3.0 * 2048.0, 150.0 * 2048.0, 300.0 * 2048.0};
+  // |d| where chi jumps (fine units): Eq.(10)'s piece ends, or the user chi's breaks
+  std::vector<double> br;
+  if (rq.chi == MARFA_CHI_TONKOV) br = {3.0 * 2048.0, 150.0 * 2048.0, 300.0 * 2048.0};
+  if (rq.chi == MARFA_CHI_USER)
+    for (int i = 0; i < MarfaUserChi::kBreaks; ++i) br.push_back(MarfaUserChi::kBreak[i] * 2048.0);
   for (int l = 0; l < kLevels; ++l) {
     G.nq1[l] = G.nq2[l] = 0;
     if (l == kLevels - 1) continue;
     // lines starting at or below l: T_(l+1) = g on [b_l, c]
     if (G.b[l] <= c) {
       std::vector<double> q{G.b[l], c};
-      if (rq.chi == MARFA_CHI_TONKOV)
-        for (double v : br)
-          if (v >= G.b[l] && v <= c) q.push_back(v);
+      for (double v : br)
+        if (v >= G.b[l] && v <= c) q.push_back(v);
       std::sort(q.begin(), q.end());
       q.erase(std::unique(q.begin(), q.end()), q.end());
       for (size_t i = 0; i < q.size(); ++i) G.q1[l][i] = q[i];
@@ -271,9 +274,8 @@ static void make_geometry(const marfa_request& rq, double nu_max, Geometry& G) {
     }
     // lines starting above l: T_(l+1) = g on [0, c]
     std::vector<double> q2{c};
-    if (rq.chi == MARFA_CHI_TONKOV)
-      for (double v : br)
-        if (v <= c) q2.push_back(v);
+    for (double v : br)
+      if (v <= c) q2.push_back(v);
     std::sort(q2.begin(), q2.end());
     q2.erase(std::unique(q2.begin(), q2.end()), q2.end());
     for (size_t i = 0; i < q2.size(); ++i) G.q2[l][i] = q2[i];
@@ -337,6 +339,8 @@ static bool make_intervals(const Geometry& G, int chi, std::vector<IntervalSet>&
             S.chi_c0[i] = G.chi_c0[piece_a - 1];
             S.chi_c1[i] = G.chi_c1[piece_a - 1] / 2048.0;
           }
+        } else if (chi == MARFA_CHI_USER) {
+          S.chi_mixed[i] = 1;  // no separable form known: evaluated pair by pair
         }
       }
       // fast region test: every line with a region here starts below l (one
@@ -379,6 +383,8 @@ static bool make_intervals(const Geometry& G, int chi, std::vector<IntervalSet>&
             S.fc0 = G.chi_c0[pa - 1];
             S.fc1 = G.chi_c1[pa - 1] / 2048.0;
           }
+        } else if (chi == MARFA_CHI_USER) {
+          S.fchi_mixed = 1;
         }
       }
       // jumps of T_(l+1) for the classes present, merged by value
@@ -408,7 +414,11 @@ static bool make_intervals(const Geometry& G, int chi, std::vector<IntervalSet>&
         S.jchi_mode[k] = 0;
         S.jchi_c0[k] = 0.0;
         S.jchi_c1[k] = 0.0;
-        if (chi != MARFA_CHI_TONKOV || top) continue;
+        if (chi == MARFA_CHI_NONE || top) continue;
+        if (chi == MARFA_CHI_USER) {
+          S.jchi_mode[k] = 2;
+          continue;
+        }
         const double reach = G.ns * G.r[l + 1] + 4.0;
         const double lo = std::max(0.0, qs[k].first - reach) / 2048.0, hi = (qs[k].first + reach) / 2048.0;
         auto piece = [](double x) { return x < 3.0 ? 0 : (x <= 150.0 ? 1 : (x <= 300.0 ? 2 : 3)); };
@@ -519,8 +529,8 @@ static marfa_status validate(const marfa_lines* L, const marfa_layer* lay, int32
     return fail(MARFA_E_INVALID, "cutoff must be in (0, 1e5]");
   if (!(rq->R >= 4.0) || rq->R > 4096.0 || std::floor(rq->R) != rq->R)
     return fail(MARFA_E_INVALID, "R must be an integer in [4, 4096]");
-  if (rq->shape < 0 || rq->shape > 2) return fail(MARFA_E_INVALID, "shape");
-  if (rq->chi < 0 || rq->chi > 1) return fail(MARFA_E_INVALID, "chi");
+  if (rq->shape < 0 || rq->shape > 3) return fail(MARFA_E_INVALID, "shape");
+  if (rq->chi < 0 || rq->chi > 2) return fail(MARFA_E_INVALID, "chi");
   if (rq->out_kind < 0 || rq->out_kind > 1) return fail(MARFA_E_INVALID, "out_kind");
   if (rq->eval < 0 || rq->eval > 1) return fail(MARFA_E_INVALID, "eval");
   if (rq->level_table < 0 || rq->level_table > 1) return fail(MARFA_E_INVALID, "level_table");
@@ -940,6 +950,27 @@ extern "C" marfa_status marfa_plan_count(marfa_plan* p, marfa_stats* out) {
   int64_t ln = 0;
   for (int l = 1; l < kLevels; ++l) ln += p->G.n[l];
   out->level_nodes = ln * p->n_layers;
+  const bool five = p->G.ns == 5;
+  out->flops_per_eval = kFlopsEval;
+  out->flops_per_core = kFlopsCore;
+  out->flops_per_term = kFlopsTerm;
+  out->flops_per_band = five ? kFlopsBand5 : kFlopsBand3;
+  out->flops_per_cascade = five ? kFlopsCascade5 : kFlopsCascade3;
+  out->flops_level = out->flops_per_eval * (double)(out->pairs_wing + out->pairs_core) +
+                     out->flops_per_core * (double)out->pairs_core + out->flops_per_term * (double)out->wing_terms +
+                     out->flops_per_band * (double)out->pairs_band;
+  // cascade: every node of levels 0..9 not coinciding with a coarser node is
+  // interpolated (injection at coinciding nodes is a copy)
+  double interp_nodes = 0.0;
+  for (int l = 0; l < kLevels - 1; ++l) {
+    const double rho = (double)(p->G.r[l + 1] / p->G.r[l]);
+    interp_nodes += (double)p->G.n[l] * (rho - 1.0) / rho;
+  }
+  out->flops_cascade = out->flops_per_cascade * interp_nodes * p->n_layers;
+  const double real_b = p->req.fp64 ? 8.0 : 4.0;
+  const double rec_b = p->req.fp64 ? (double)sizeof(LineRec64) : (double)sizeof(LineRec32);
+  out->bytes_level = rec_b * (double)kept + real_b * (double)(out->level_nodes + out->points_per_layer * p->n_layers);
+  out->bytes_cascade = real_b * (double)(out->level_nodes + out->points_per_layer * p->n_layers) * (five ? 7.0 : 5.0);
   return MARFA_OK;
 }
 

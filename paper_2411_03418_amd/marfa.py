@@ -18,9 +18,9 @@ LIB_PATH = os.path.join(_HERE, "libmarfa.so")
 OK, E_INVALID, E_NOMEM, E_DEVICE, E_UNSUPPORTED, E_STATE, E_IO = 0, -1, -2, -3, -4, -5, -6
 PTBIN_NT = 20481          # values per PT-table record (Appendix A)
 PTBIN_TRUNCATE = 1
-SHAPES = {"voigt": 0, "lorentz": 1, "doppler": 2}
+SHAPES = {"voigt": 0, "lorentz": 1, "doppler": 2, "user": 3}
 EVALS = {"plain": 0, "surrogate": 1}
-CHIS = {"none": 0, "tonkov": 1}
+CHIS = {"none": 0, "tonkov": 1, "user": 2}
 OUTS = {"sigma": 0, "k": 1}
 
 
@@ -52,7 +52,10 @@ class Stats(C.Structure):
                 ("lines_kept", C.c_int64), ("pairs_level", C.c_int64 * 11), ("pairs_core", C.c_int64),
                 ("pairs_wing", C.c_int64), ("pairs_band", C.c_int64), ("wing_terms", C.c_int64),
                 ("level_nodes", C.c_int64), ("iters_level", C.c_int64 * 11),
-                ("band_iters_level", C.c_int64 * 11)]
+                ("band_iters_level", C.c_int64 * 11), ("flops_per_eval", C.c_double),
+                ("flops_per_core", C.c_double), ("flops_per_term", C.c_double), ("flops_per_band", C.c_double),
+                ("flops_per_cascade", C.c_double), ("flops_level", C.c_double), ("flops_cascade", C.c_double),
+                ("bytes_level", C.c_double), ("bytes_cascade", C.c_double)]
 
 
 class Timing(C.Structure):
@@ -232,7 +235,11 @@ class Plan:
                     lines_kept=s.lines_kept, pairs_level=list(s.pairs_level), pairs_core=s.pairs_core,
                     pairs_wing=s.pairs_wing, pairs_band=s.pairs_band, wing_terms=s.wing_terms,
                     level_nodes=s.level_nodes, iters_level=list(s.iters_level),
-                    band_iters_level=list(s.band_iters_level))
+                    band_iters_level=list(s.band_iters_level), flops_per_eval=s.flops_per_eval,
+                    flops_per_core=s.flops_per_core, flops_per_term=s.flops_per_term,
+                    flops_per_band=s.flops_per_band, flops_per_cascade=s.flops_per_cascade,
+                    flops_level=s.flops_level, flops_cascade=s.flops_cascade, bytes_level=s.bytes_level,
+                    bytes_cascade=s.bytes_cascade)
 
     def execute_timed(self, out=None, stream=None):
         """Run all layers as three stage graphs with HIP events between them on

@@ -69,7 +69,7 @@ def pt_table(n_layers: int = 100, p_lo: float = 1e-5, p_hi: float = 90.0,
     return np.stack([p, T, p, np.zeros_like(p)], axis=1)
 
 
-# workload recipes ("Inputs")
+# workload recipes: synthetic line lists and layers shaped like the paper's workloads
 WORKLOADS = {
     # single layer, 1000 lines, Voigt, 25 cm^-1 cut-off, 1000-1010 cm^-1
     "single_1k": dict(lines=(1000, 975.0, 1035.0, 1, False), layers=[(1.0, 296.0, 1.0, 0.0)],
