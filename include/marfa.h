@@ -298,6 +298,20 @@ marfa_status marfa_surrogate_forward(marfa_surrogate* s, const float* X_dev, int
  * weights the forward pass uses; loss and grad are host outputs.  Synchronous. */
 marfa_status marfa_surrogate_loss_grad(marfa_surrogate* s, const float* X_dev, const float* T_dev, int64_t n,
                                        float* loss, float* grad);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, allocation-free training or serving loops): the computation of
+ * marfa_surrogate_loss_grad with no allocation at all.  Its partial
+ * gradients live in a fixed array of the library, one per device, 128
+ * workgroups x 12802 floats (6.6 MB), held until the process ends.
+ * n: 1 <= n <= 4096 samples (MARFA_E_INVALID beyond).  X_dev [n][3], T_dev [n]
+ * as for marfa_surrogate_loss_grad; out_dev: caller-owned device float[12802]
+ * on the surrogate's device, receiving the gradient of the mean squared
+ * error in [0, 12801) and that error in [12801] -- the same values, bit for
+ * bit, that marfa_surrogate_loss_grad returns.  Asynchronous on hip_stream.
+ * Every call on one device shares that device's array: calls that overlap
+ * on one device race (issue them on one stream). */
+marfa_status marfa_surrogate_loss_grad_noalloc(marfa_surrogate* s, const float* X_dev, const float* T_dev, int64_t n,
+                                               float* out_dev, void* hip_stream);
 /* n training samples on the device (features X_dev [n][3], targets T_dev
  * [n]) with targets from the double-precision device line shape.
  * Asynchronous on hip_stream. */

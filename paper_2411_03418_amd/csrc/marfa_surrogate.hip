@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <vector>
 
@@ -287,12 +288,12 @@ struct AdamArgs {
 };
 
 __global__ void k_mlp_reduce_adam(const float* __restrict__ partial, int n_parts, float* __restrict__ grad,
-                                  float* master, float* m, float* v, AdamArgs a, MlpBuffers B) {
+                                  float* master, float* m, float* v, AdamArgs a, MlpBuffers B, float last_div) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p > kMlpParams) return;
   float g = 0.f;
   for (int w = 0; w < n_parts; ++w) g += partial[(size_t)w * (kMlpParams + 1) + p];
-  grad[p] = g;
+  grad[p] = p == kMlpParams ? g / last_div : g;
   if (!a.apply || p == kMlpParams) return;
   const float mm = a.beta1 * m[p] + (1.f - a.beta1) * g;
   const float vv = a.beta2 * v[p] + (1.f - a.beta2) * g * g;
@@ -310,6 +311,16 @@ using namespace marfa;
 // ------------------------------------------------------------------
 // host object
 // ------------------------------------------------------------------
+// Partial gradients of marfa_surrogate_loss_grad_noalloc: a fixed array of
+// the library (one copy per device, alive until the process ends), so that
+// entry point allocates nothing.  Host code reaches it only through the
+// address hipGetSymbolAddress returns on each device.
+constexpr int kNoAllocGroups = 128;
+constexpr int64_t kNoAllocMaxSamples = (int64_t)kNoAllocGroups * kGradSamples;  // 4096
+static __device__ __align__(256) float scratch[kNoAllocGroups * (kMlpParams + 1)];
+static std::mutex g_scratch_mu;
+static float* g_scratch_ptr[64];
+
 struct marfa_surrogate {
   int device = 0;
   int32_t chi = 0;
@@ -323,6 +334,7 @@ struct marfa_surrogate {
   MlpBuffers eb;
   float* partial = nullptr;
   int64_t partial_cap = 0;  // workgroups
+  float* noalloc_partial = nullptr;  // this device's copy of `scratch`
   hipStream_t stream = nullptr;
 };
 
@@ -401,7 +413,7 @@ marfa_status run_grad(marfa_surrogate* s, const float* X, const float* T, int64_
   k_mlp_grad<<<(unsigned)groups, 64, 0, s->stream>>>(dev_view(s), X, T, n_all, first, n, pa, pb, gscale, pow4,
                                                      s->partial);
   k_mlp_reduce_adam<<<(kMlpParams + 1 + 255) / 256, 256, 0, s->stream>>>(s->partial, (int)groups, s->grad, s->master,
-                                                                         s->m, s->v, ad, s->eb);
+                                                                         s->m, s->v, ad, s->eb, 1.f);
   SHIP(hipGetLastError());
   return MARFA_OK;
 }
@@ -409,6 +421,21 @@ marfa_status run_grad(marfa_surrogate* s, const float* X, const float* T, int64_
 marfa_status publish(marfa_surrogate* s) {
   k_mlp_publish<<<(kMlpParams + 255) / 256, 256, 0, s->stream>>>(s->master, s->eb);
   SHIP(hipGetLastError());
+  return MARFA_OK;
+}
+
+// This device's address of `scratch` (the device must be current): looked up
+// once per device, at the first surrogate created on it.
+marfa_status noalloc_scratch(int device, float** out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (device < 0 || device >= 64) return sfail(MARFA_E_INVALID, "device index out of range");
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return sfail(MARFA_E_DEVICE, "hipGetSymbolAddress(scratch) failed");
+    g_scratch_ptr[device] = static_cast<float*>(p);
+  }
+  *out = g_scratch_ptr[device];
   return MARFA_OK;
 }
 
@@ -445,6 +472,11 @@ extern "C" marfa_status marfa_surrogate_create(marfa_surrogate** out, int32_t ch
   if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess) {
     free_surrogate(s);
     return sfail(MARFA_E_DEVICE, "stream create");
+  }
+  st = noalloc_scratch(device, &s->noalloc_partial);
+  if (st != MARFA_OK) {
+    free_surrogate(s);
+    return st;
   }
   // Glorot-uniform weights from a counter-based generator, zero biases
   std::vector<float> P(kMlpParams, 0.0f);
@@ -521,6 +553,26 @@ extern "C" marfa_status marfa_surrogate_loss_grad(marfa_surrogate* s, const floa
   SHIP(hipStreamSynchronize(s->stream));
   std::memcpy(grad, g.data(), kMlpParams * sizeof(float));
   *loss = g[kMlpParams] / (float)n;
+  return MARFA_OK;
+}
+
+extern "C" marfa_status marfa_surrogate_loss_grad_noalloc(marfa_surrogate* s, const float* X, const float* T,
+                                                          int64_t n, float* out, void* stream) {
+  if (!s || !X || !T || !out) return sfail(MARFA_E_INVALID, "null argument");
+  if (n < 1 || n > kNoAllocMaxSamples)
+    return sfail(MARFA_E_INVALID, "n must be in [1, 4096]: the fixed partial-gradient array holds 128 workgroups");
+  if (!s->noalloc_partial) return sfail(MARFA_E_STATE, "no partial-gradient array on this device");
+  SHIP(hipSetDevice(s->device));
+  const hipStream_t hs = static_cast<hipStream_t>(stream);
+  const int64_t groups = (n + kGradSamples - 1) / kGradSamples;
+  // the same kernels and fixed summation order as marfa_surrogate_loss_grad;
+  // every read row of the array is written first by this call's k_mlp_grad
+  k_mlp_grad<<<(unsigned)groups, 64, 0, hs>>>(dev_view(s), X, T, n, 0, n, 1, 0, 2.0f / (float)n, 0,
+                                              s->noalloc_partial);
+  AdamArgs ad{0.f, 0.f, 0.f, 0.f, 1.f, 1.f, 0};
+  k_mlp_reduce_adam<<<(kMlpParams + 1 + 255) / 256, 256, 0, hs>>>(s->noalloc_partial, (int)groups, out, s->master,
+                                                                   s->m, s->v, ad, s->eb, (float)n);
+  SHIP(hipGetLastError());
   return MARFA_OK;
 }
 

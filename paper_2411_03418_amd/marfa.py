@@ -121,6 +121,7 @@ def lib():
         L.marfa_surrogate_get_params.argtypes = [vp, vp, i64]
         L.marfa_surrogate_forward.argtypes = [vp, vp, i64, vp, vp]
         L.marfa_surrogate_loss_grad.argtypes = [vp, vp, vp, i64, f32p, vp]
+        L.marfa_surrogate_loss_grad_noalloc.argtypes = [vp, vp, vp, i64, vp, vp]
         L.marfa_surrogate_make_samples.argtypes = [vp, C.POINTER(SampleCfg), u64, i64, vp, vp, vp]
         L.marfa_surrogate_train.argtypes = [vp, C.POINTER(SampleCfg), C.POINTER(TrainCfg), C.POINTER(TrainReport)]
         L.marfa_surrogate_destroy.argtypes = [vp]
@@ -132,7 +133,8 @@ def lib():
         L.marfa_linedb_read.argtypes = [C.c_char_p, i64, i64, vp, vp, vp, vp, vp, vp, vp, vp]
         L.marfa_linedb_write.argtypes = [C.c_char_p, C.POINTER(Lines)]
         for f in ("marfa_surrogate_create", "marfa_surrogate_set_params", "marfa_surrogate_get_params",
-                  "marfa_surrogate_forward", "marfa_surrogate_loss_grad", "marfa_surrogate_make_samples",
+                  "marfa_surrogate_forward", "marfa_surrogate_loss_grad", "marfa_surrogate_loss_grad_noalloc",
+                  "marfa_surrogate_make_samples",
                   "marfa_surrogate_train", "marfa_plan_set_surrogate", "marfa_plan_set_eval"):
             getattr(L, f).restype = C.c_int32
         for f in ("marfa_plan_create", "marfa_plan_points", "marfa_execute", "marfa_execute_layers",
@@ -342,6 +344,19 @@ class Surrogate:
         _check(lib().marfa_surrogate_loss_grad(self._h, C.c_void_p(X.data_ptr()), C.c_void_p(T.data_ptr()),
                                                X.shape[0], C.byref(loss), _ptr(g)))
         return float(loss.value), g
+
+    def loss_grad_noalloc(self, X, T, out, stream=None):
+        """Gradient and loss into the caller's device tensor out (float32,
+        N_PARAMS + 1 values: the gradient, then the mean squared error);
+        allocates nothing, asynchronous on `stream`; n <= 4096 samples."""
+        if not (X.is_contiguous() and T.is_contiguous() and out.is_contiguous()):
+            raise ValueError("X, T and out must be contiguous")
+        if str(out.dtype) != "torch.float32" or out.numel() != N_PARAMS + 1:
+            raise ValueError("out must be float32 with N_PARAMS + 1 elements")
+        _check(lib().marfa_surrogate_loss_grad_noalloc(self._h, C.c_void_p(X.data_ptr()), C.c_void_p(T.data_ptr()),
+                                                       X.shape[0], C.c_void_p(out.data_ptr()),
+                                                       _stream_handle(stream, self.device)))
+        return out
 
     def make_samples(self, n, seed, nu_lo=375.0, nu_hi=2625.0, T_lo=150.0, T_hi=740.0, molar_mass=44.0,
                      stream=None):

@@ -118,3 +118,4 @@ def test_null_handles_are_rejected():
     assert L.marfa_surrogate_set_params(None, None, 0) == marfa.E_INVALID
     assert L.marfa_surrogate_train(None, None, None, None) == marfa.E_INVALID
     assert L.marfa_plan_tune(None, None, 0, None) == marfa.E_INVALID
+    assert L.marfa_surrogate_loss_grad_noalloc(None, None, None, 1, None, None) == marfa.E_INVALID
