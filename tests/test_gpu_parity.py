@@ -2,22 +2,28 @@
 
 Gates (relative, on nodes where the direct sum is >= 1e-8 of the layer max):
 GPU single precision vs the definition <= 1e-4; vs the oracle's eleven-grid
-result <= FP32_VS_GRID (implementation error only); GPU double precision vs
-the oracle's eleven-grid result <= FP64_VS_GRID.
+result <= FP32_VS_GRID = 1e-5 (implementation error only); GPU double
+precision vs the oracle's eleven-grid result <= FP64_VS_GRID = 1e-12.
 
-FP32_VS_GRID = 3e-5: the eleven-grid result at a weak node next to a strong
-line's cut-off is a coarse-level sum holding that line's wing minus a band
-correction of the same size, so single-precision rounding of the coarse sums
-(about 1e-7 of their value) is amplified by their ratio to the node value;
-with summation orders from other tile shapes this reaches 1.5e-5 at nodes
-near 1e-8 of the layer max.
+Two documented node classes have a bound of their own:
 
-FP64_VS_GRID = 2e-10: the double-precision device Voigt function takes
-K = Re w(z) from a rational approximation of the Faddeeva function w; for
-y << 1 and |x| of 5 to 8, Re w is smaller than |w| by about y / |x|, so
-double rounding of w leaves K a relative error near |x| eps / y (7.8e-11 at
-y = 1e-5 on the device-K grid below).  Lines of a layer at 1e-5 atm reach it
-at nodes a few Doppler widths from their centres.
+* Jump edges in single precision.  The device decides region membership, the
+  chi piece and the cut-off on the single-precision distance to a line's
+  centre; where a node lies within that distance's rounding of a jump of the
+  line's part (|d| within 2^-22 |d| of the cut-off, a chi break or a region
+  edge b_l, but not exactly on it), the pair can fall on the other side than
+  in the oracle's double precision.  The node's error is then that line's jump there: its whole value
+  at the cut-off, the relative step of chi at a break, at a region edge the
+  difference of two valid decompositions (the scheme's interpolation error,
+  taken as 1e-4 of the line's value), carried by the cascade to the fine
+  nodes within reach of the coarsest level whose node the jump point is.
+  edge_tolerance() finds these pairs from the oracle's double-precision line
+  centres and adds the bound to the node's gate.
+* FP64_VS_GRID_THIN = 1e-10, layers below 1e-4 atm: the double-precision
+  device Voigt function takes K = Re w(z) from a rational approximation of
+  the Faddeeva function w; for y << 1 and |x| of 5 to 8, Re w is smaller than
+  |w| by about y / |x|, so rounding of w leaves K a relative error near
+  |x| eps / y (7.8e-11 at y = 1e-5 on the device-K grid below).
 """
 import os
 
@@ -31,8 +37,86 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 THREADS = min(16, os.cpu_count() or 1)
-FP32_VS_GRID = 3e-5
-FP64_VS_GRID = 2e-10
+FP32_VS_GRID = 1e-5
+FP64_VS_GRID = 1e-12
+FP64_VS_GRID_THIN = 1e-10
+EDGE_REL = 2.0 ** -22     # relative reach of single-precision distance rounding
+
+
+def fp64_gate(layer):
+    return FP64_VS_GRID if layer[0] >= 1e-4 else FP64_VS_GRID_THIN
+
+
+def _chi_breaks(kind):
+    return {0: [], 1: [3.0, 150.0, 300.0], 2: O.user_chi_breaks()}[kind]
+
+
+def edge_tolerance(lines, layer, req, nodes, ref):
+    """Extra relative tolerance of each node for the single-precision jump-edge
+    class (see the module docstring), from the oracle's line states.  A jump
+    point that lies within rounding of a fine node m* coincides with the nodes
+    of every level whose step divides m*; a pair there can change level or side
+    on the coarsest of them, and the cascade carries the difference to the fine
+    nodes within (stencil half-width + 1) coarser steps of m*."""
+    o = _oreq(req)
+    c = o["cutoff"]
+    st = O.line_states(lines, layer)
+    keep = st["S"] >= o["prune"] * st["S"].max() if o["prune"] > 0 else np.ones(lines.n, bool)
+    idx = np.flatnonzero(keep)
+    nu = st["nu_t"][idx]
+    R, lt = o["R"], o["level_table"]
+    steps = [1 << l for l in range(11)] if lt == 1 else [1] + [1 << (l + 1) for l in range(1, 11)]
+    half = int(o["stencil"]) // 2 + 1
+    jumps = [(c, "cut")] + [(R * steps[l + 1] / 2048.0, "edge") for l in range(10) if R * steps[l + 1] / 2048.0 < c]
+    jumps += [(q, "chi") for q in _chi_breaks(o["chi"]) if q <= c]
+    extra = np.zeros(nodes.size)
+    n0 = int(nodes[0])
+    for q, kind in jumps:
+        for sgn in (1.0, -1.0):
+            target = nu + sgn * q
+            m = np.rint(target * 2048.0).astype(np.int64)
+            # an exact coincidence (a centre on a node, a jump on the lattice)
+            # leaves the single-precision distance exact: no flip there
+            dist = np.abs(m / 2048.0 - target)
+            near = (dist <= EDGE_REL * q) & (dist > 0)
+            for j, mm in zip(idx[near], m[near]):
+                top = max(l for l in range(11) if mm % steps[l] == 0)
+                reach = half * steps[min(top + 1, 10)]
+                lo, hi = max(int(mm) - reach, n0), min(int(mm) + reach, int(nodes[-1]))
+                if lo > hi:
+                    continue
+                win = np.arange(lo, hi + 1, dtype=np.int64)
+                # the line's own value on the window (beyond a cut-off: its
+                # value just inside it, the size of the jump)
+                g = O.direct(lines.subset([j]), layer, win, threads=1, **dict(o, prune=0.0, cutoff=c * (1 + 1e-6)))
+                if kind == "cut":
+                    f = 1.0
+                elif kind == "chi":
+                    f = abs(O.chi(o["chi"], q * (1 + 1e-9)) / O.chi(o["chi"], q) - 1.0)
+                else:
+                    f = 1e-4
+                r = ref[win - n0]
+                extra[win - n0] += np.where(r > 0, f * g / np.where(r > 0, r, 1.0), 0.0)
+    return extra
+
+
+def grid_check(got, ref_g, lines, layer, req, fp64):
+    """Relative error against the oracle's eleven-grid result, asserted at the
+    gate of the precision (single precision: plus the jump-edge allowance)."""
+    m = ref_g >= 1e-8 * ref_g.max()
+    err = np.zeros_like(ref_g)
+    err[m] = np.abs(got[m] - ref_g[m]) / ref_g[m]
+    if fp64:
+        assert err.max() < fp64_gate(layer), err.max()
+        return float(err.max())
+    nodes = np.arange(int(round(req["nu_begin"] * 2048)), int(round(req["nu_end"] * 2048)) + 1)
+    extra = edge_tolerance(lines, layer, req, nodes, ref_g)
+    n_edge = int(np.count_nonzero(extra[m]))
+    bad = err > FP32_VS_GRID + extra
+    plain = float(err[m & (extra == 0)].max()) if np.any(m & (extra == 0)) else 0.0
+    print(f"  vs grid: {plain:.2e} off the edge class; {n_edge} edge-class nodes, max {err[extra > 0].max() if n_edge else 0:.2e}")
+    assert not np.any(bad & m), (np.flatnonzero(bad & m)[:10], err[bad & m][:10], extra[bad & m][:10])
+    return float(err.max())
 
 
 def marfa():
@@ -54,8 +138,8 @@ def run(lines, layers, fp64=False, **req):
 
 def _oreq(req):
     o = dict(nu_begin=req["nu_begin"], nu_end=req["nu_end"], cutoff=req["cutoff"])
-    o["chi"] = {"none": 0, "tonkov": 1}[req.get("chi", "none")]
-    o["shape"] = {"voigt": 0, "lorentz": 1, "doppler": 2}[req.get("shape", "voigt")]
+    o["chi"] = {"none": 0, "tonkov": 1, "user": 2}[req.get("chi", "none")]
+    o["shape"] = {"voigt": 0, "lorentz": 1, "doppler": 2, "user": 3}[req.get("shape", "voigt")]
     o["prune"] = req.get("prune", 0.0)
     o["level_table"] = req.get("level_table", 0)
     o["out_kind"] = {"sigma": 0, "k": 1}[req.get("out", "sigma")]
@@ -129,6 +213,11 @@ ONE_LINE = [
     dict(nu0=1005.0, gamma=0.06, p=0.2, shape="doppler"),
     dict(nu0=1004.2, gamma=0.06, p=0.4, lt=1),
     dict(nu0=1004.4, gamma=0.07, p=1e-4, T=150.0),
+    # the compiled-in user shape and chi (Sections 2.2-2.3)
+    dict(nu0=1005.00013, gamma=0.075, shape="user"),
+    dict(nu0=1003.7, gamma=0.09, p=10.0, chi="user", c=60.0),
+    dict(nu0=1001.9, gamma=0.3, chi="user", c=4.0),
+    dict(nu0=1004.2, gamma=0.06, p=0.4, chi="user", shape="user", lt=1),
 ]
 
 
@@ -145,7 +234,7 @@ def test_one_line_parity(case, fp64):
     eg, ed = rel_err(got, ref_g), rel_err(got, ref_d)
     print(f"vs grid {eg:.2e}  vs direct {ed:.2e}")
     assert ed < 1e-4
-    assert eg < (FP64_VS_GRID if fp64 else FP32_VS_GRID)
+    grid_check(got, ref_g, L, lay, req, fp64)
 
 
 # ------------------------------------------------------------------ workloads
@@ -161,7 +250,7 @@ def test_single_1k_workload(fp64):
     eg, ed = rel_err(got, ref_g), rel_err(got, ref_d)
     print(f"single_1k fp64={fp64}: vs grid {eg:.2e} vs direct {ed:.2e}")
     assert ed < 1e-4
-    assert eg < (FP64_VS_GRID if fp64 else FP32_VS_GRID)
+    grid_check(got, ref_g, lines, layers[0], req, fp64)
 
 
 def test_multi_layer_pruned_ragged():
@@ -177,7 +266,27 @@ def test_multi_layer_pruned_ragged():
         eg, ed = rel_err(got[i], ref_g), rel_err(got[i], ref_d)
         print(f"layer {i}: vs grid {eg:.2e} vs direct {ed:.2e}")
         assert ed < 1e-4
-        assert eg < FP32_VS_GRID
+        grid_check(got[i], ref_g, lines, layers[i], req, False)
+
+
+@pytest.mark.parametrize("fp64", [False, True])
+@pytest.mark.parametrize("stencil", [3, 5])
+def test_user_plugins_many_lines(fp64, stencil):
+    # the compiled-in user shape and chi through every level, both band
+    # passes and the learned-shape-free generic pair path, on several layers
+    lines = synth.make_lines(2000, 940.0, 1080.0, 41, shift=True)
+    layers = synth.pt_table(7)[[0, 3, 6]]
+    req = dict(nu_begin=1000.0, nu_end=1012.0, cutoff=60.0, chi="user", shape="user", prune=1e-6,
+               stencil=stencil, R=48 if stencil == 3 else 12)
+    got = run(lines, layers, fp64=fp64, **req)
+    o = _oreq(req)
+    for i in range(layers.shape[0]):
+        ref_g = O.grid(lines, layers[i], threads=THREADS, **o)
+        ref_d = O.direct(lines, layers[i], all_nodes(req), threads=THREADS, **o)
+        eg, ed = rel_err(got[i], ref_g), rel_err(got[i], ref_d)
+        print(f"user plug-ins layer {i} fp64={fp64} stencil={stencil}: vs grid {eg:.2e} vs direct {ed:.2e}")
+        assert ed < 1e-4
+        grid_check(got[i], ref_g, lines, layers[i], req, fp64)
 
 
 @pytest.mark.parametrize("fp64", [False, True])
@@ -194,7 +303,7 @@ def test_small_cutoff_node_major_band(fp64):
     eg, ed = rel_err(got, ref_g), rel_err(got, ref_d)
     print(f"small cut-off fp64={fp64}: vs grid {eg:.2e} vs direct {ed:.2e}")
     assert ed < 1e-4
-    assert eg < (FP64_VS_GRID if fp64 else FP32_VS_GRID)
+    grid_check(got, ref_g, lines, lay, req, fp64)
 
 
 @pytest.mark.parametrize("fp64", [False, True])
@@ -211,7 +320,7 @@ def test_long_cutoff_all_tonkov_pieces(fp64):
     eg, ed = rel_err(got, ref_g), rel_err(got, ref_d)
     print(f"cut-off 400 fp64={fp64}: vs grid {eg:.2e} vs direct {ed:.2e}")
     assert ed < 1e-4
-    assert eg < (FP64_VS_GRID if fp64 else FP32_VS_GRID)
+    grid_check(got, ref_g, lines, lay, req, fp64)
 
 
 @pytest.mark.parametrize("fp64", [False, True])
@@ -228,7 +337,7 @@ def test_region_edge_next_to_chi_break(fp64):
     eg, ed = rel_err(got, ref_g), rel_err(got, ref_d)
     print(f"R=47 fp64={fp64}: vs grid {eg:.2e} vs direct {ed:.2e}")
     assert ed < 1e-4
-    assert eg < (FP64_VS_GRID if fp64 else FP32_VS_GRID)
+    grid_check(got, ref_g, lines, lay, req, fp64)
 
 
 # ------------------------------------------------------------------ rounding at region edges
@@ -264,7 +373,7 @@ def test_centres_within_rounding_of_a_node(tiles):
     eg, ed = rel_err(got, ref_g), rel_err(got, ref_d)
     print(f"tiles {tiles}: vs grid {eg:.2e} vs direct {ed:.2e}")
     assert ed < 1e-4
-    assert eg < FP32_VS_GRID
+    grid_check(got, ref_g, L, lay, req, False)
 
 
 # ------------------------------------------------------------------ 5-point stencil
@@ -287,7 +396,7 @@ def test_one_line_parity_5pt(case, fp64):
     eg, ed = rel_err(got, ref_g), rel_err(got, ref_d)
     print(f"5-point: vs grid {eg:.2e}  vs direct {ed:.2e}")
     assert ed < 1e-4
-    assert eg < (FP64_VS_GRID if fp64 else FP32_VS_GRID)
+    grid_check(got, ref_g, L, lay, req, fp64)
 
 
 @pytest.mark.parametrize("fp64", [False, True])
@@ -303,7 +412,7 @@ def test_multi_layer_5pt(fp64):
         eg, ed = rel_err(got[i], ref_g), rel_err(got[i], ref_d)
         print(f"5-point layer {i} fp64={fp64}: vs grid {eg:.2e} vs direct {ed:.2e}")
         assert ed < 1e-4
-        assert eg < (FP64_VS_GRID if fp64 else FP32_VS_GRID)
+        grid_check(got[i], ref_g, lines, layers[i], req, fp64)
 
 
 @pytest.mark.parametrize("fp64", [False, True])
@@ -320,7 +429,7 @@ def test_small_cutoff_node_major_band_5pt(fp64):
     eg, ed = rel_err(got, ref_g), rel_err(got, ref_d)
     print(f"5-point small cut-off fp64={fp64}: vs grid {eg:.2e} vs direct {ed:.2e}")
     assert ed < 1e-4
-    assert eg < (FP64_VS_GRID if fp64 else FP32_VS_GRID)
+    grid_check(got, ref_g, lines, lay, req, fp64)
 
 
 @pytest.mark.parametrize("fp64", [False, True])
@@ -335,7 +444,7 @@ def test_long_cutoff_5pt(fp64):
     eg, ed = rel_err(got, ref_g), rel_err(got, ref_d)
     print(f"5-point cut-off 400 fp64={fp64}: vs grid {eg:.2e} vs direct {ed:.2e}")
     assert ed < 1e-4
-    assert eg < (FP64_VS_GRID if fp64 else FP32_VS_GRID)
+    grid_check(got, ref_g, lines, lay, req, fp64)
 
 
 def test_autotune_keeps_parity_5pt():
@@ -355,7 +464,7 @@ def test_autotune_keeps_parity_5pt():
         ref_g = O.grid(lines, layers[i], threads=THREADS, **o)
         eg = rel_err(got[i], ref_g)
         print(f"5-point tuned {tiles['wave_nodes']} layer {i}: vs grid {eg:.2e}")
-        assert eg < FP32_VS_GRID
+        grid_check(got[i], ref_g, lines, layers[i], req, False)
 
 
 def test_absorption_coefficient_output():
@@ -384,7 +493,7 @@ def test_range_starting_at_zero():
     ref_d = O.direct(lines, lay, all_nodes(req), threads=THREADS, **o)
     ref_g = O.grid(lines, lay, threads=THREADS, **o)
     assert rel_err(got, ref_d) < 1e-4
-    assert rel_err(got, ref_g) < FP32_VS_GRID
+    grid_check(got, ref_g, lines, lay, req, False)
 
 
 def test_deterministic_and_graph_replay():
@@ -439,7 +548,9 @@ def test_autotune_keeps_parity():
     o = _oreq(req)
     for i in range(layers.shape[0]):
         ref_g = O.grid(lines, layers[i], threads=THREADS, **o)
-        assert rel_err(got[i], ref_g) < FP32_VS_GRID
+        eg = rel_err(got[i], ref_g)
+        print(f"tuned layer {i}: vs grid {eg:.2e}")
+        grid_check(got[i], ref_g, lines, layers[i], req, False)
 
 
 def test_single_200k_sampled():
@@ -457,49 +568,3 @@ def test_single_200k_sampled():
     e = float(np.max(np.abs(g - ref) / ref))
     print(f"single_200k sampled ({nodes.size} nodes): max rel err {e:.2e}")
     assert e < 1e-4
-
-
-def _table_sampled(workload, n_layers_sampled, n_nodes, extra, seed):
-    """The whole PT table in the benchmark's launch configuration (tuned tiles,
-    one graph launch for all layers), checked against the direct sum on
-    sampled nodes of sampled layers, plus listed (layer, node) pairs."""
-    lines, layers, rq = synth.workload(workload)
-    req = dict(nu_begin=rq["nu_begin"], nu_end=rq["nu_end"], cutoff=rq["cutoff"], chi="tonkov", prune=rq["prune"])
-    M = marfa()
-    print(f"[gpu] {workload}: {lines.n} lines, {layers.shape[0]} layers", flush=True)
-    plan = M.Plan(lines, layers, device=0, **req)
-    out = torch.empty((plan.n_layers, plan.points), dtype=torch.float32, device="cuda:0")
-    plan.tune(out=out)
-    plan.execute(out=out)
-    torch.cuda.synchronize()
-    plan.close()
-    m0 = int(round(req["nu_begin"] * 2048))
-    rng = np.random.default_rng(seed)
-    picks = {}
-    for i in rng.choice(layers.shape[0], n_layers_sampled, replace=False):
-        picks[int(i)] = list(rng.integers(0, out.shape[1], n_nodes))
-    for i, m in extra:
-        picks.setdefault(i, []).append(m - m0)
-    worst = 0.0
-    o = _oreq(req)
-    for i, idx in sorted(picks.items()):
-        idx = np.unique(np.asarray(idx, np.int64))
-        ref = O.direct(lines, layers[i], idx + m0, threads=THREADS, **o)
-        got = out[i, torch.as_tensor(idx, device="cuda:0")].double().cpu().numpy()
-        lay_max = float(out[i].max())
-        keep = ref >= 1e-8 * lay_max
-        e = float(np.max(np.abs(got[keep] - ref[keep]) / ref[keep])) if keep.any() else 0.0
-        worst = max(worst, e)
-    print(f"{workload}: {sum(len(v) for v in picks.values())} sampled nodes, max rel err vs direct {worst:.2e}")
-    return worst
-
-
-def test_pt100_2m_table_sampled():
-    # nodes where a single-precision distance rounded onto a region edge
-    # from outside once dropped a (node, line) pair (3.9e-3, 3.6e-3, 2.7e-3)
-    extra = [(83, 19843138), (83, 19843140), (54, 16509289), (79, 1013602), (73, 4823522)]
-    assert _table_sampled("pt100_2m", 12, 250, extra, 11) < 1e-4
-
-
-def test_pt100_200k_table_sampled():
-    assert _table_sampled("pt100_200k", 20, 250, [], 12) < 1e-4

@@ -185,3 +185,35 @@ def test_double_precision_output_rounds_to_float32_records(tmp_path):
     plan.close()
     for i, p in enumerate(paths):
         assert np.array_equal(read_record(p, 100), host[i].astype(np.float32))
+
+
+@pytest.mark.gpu
+def test_linedb_file_through_the_gpu_path(tmp_path):
+    """Appendix B end to end: the 1,000-line single-layer workload written as a
+    36-byte-record database file, read back by the library's reader, computed
+    on the GPU, and compared with the oracle at every output node."""
+    torch = pytest.importorskip("torch")
+    import oracle as O
+    from paper_2411_03418_amd import synth
+    lines, layers, rq = synth.workload("single_1k")
+    path = str(tmp_path / "lines.db")
+    M.write_line_db(path, lines)
+    assert os.path.getsize(path) == 36 * lines.n
+    back = M.read_line_db(path, molar_mass=lines.molar_mass)
+    for f in ("nu0", "S296", "gamma_air", "gamma_self", "E_lower", "n_air", "mol_iso", "delta_air"):
+        assert np.array_equal(getattr(back, f), getattr(lines, f)), f
+    req = dict(nu_begin=rq["nu_begin"], nu_end=rq["nu_end"], cutoff=rq["cutoff"])
+    plan = M.Plan(back, layers, device=0, **req)
+    got = plan.execute()
+    torch.cuda.synchronize()
+    got = got[0].double().cpu().numpy()
+    plan.close()
+    o = dict(req, chi=0, shape=0, prune=0.0)
+    nodes = np.arange(int(req["nu_begin"] * 2048), int(req["nu_end"] * 2048) + 1)
+    ref_d = O.direct(lines, layers[0], nodes, threads=8, **o)
+    ref_g = O.grid(lines, layers[0], threads=8, **o)
+    m = ref_d >= 1e-8 * ref_d.max()
+    ed = float(np.max(np.abs(got[m] - ref_d[m]) / ref_d[m]))
+    eg = float(np.max(np.abs(got[m] - ref_g[m]) / ref_g[m]))
+    print(f"database file: vs direct {ed:.2e}, vs grid {eg:.2e} over {m.sum()} nodes")
+    assert ed < 1e-4 and eg < 1e-5
