@@ -279,7 +279,9 @@ typedef struct {
 
 /* New network for (chi, cutoff) on `device`: Glorot-uniform weights from a
  * counter-based generator seeded by `seed`, zero biases.  Errors:
- * MARFA_E_INVALID (unknown chi, cutoff <= 0), MARFA_E_DEVICE, MARFA_E_NOMEM. */
+ * MARFA_E_INVALID (unknown chi, cutoff <= 0), MARFA_E_UNSUPPORTED (the user chi:
+ * the network's distance feature starts at the Tonkov chi's first break),
+ * MARFA_E_DEVICE, MARFA_E_NOMEM. */
 marfa_status marfa_surrogate_create(marfa_surrogate** out, int32_t chi, double cutoff, uint64_t seed,
                                     int32_t device);
 /* Replace / read the FP32 parameters (host arrays of n = 12801 values);

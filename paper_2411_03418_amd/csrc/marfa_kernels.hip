@@ -365,7 +365,7 @@ __device__ __forceinline__ double uniform01(uint64_t seed, uint64_t ctr) {
 // [0, c], uniform over the Doppler core (x in [0, 8]), and the transition
 // from core to wing (x in [0, 4] with y in [0.01, 10]).  Inputs are the
 // network features; the target is log(K chi) - log(Kb) with K from the
-// double-precision device line shape and chi from Eq.(10) (or the user chi).
+// double-precision device line shape and chi from Eq.(10).
 __global__ void k_mlp_samples(MlpSampleCfg c, uint64_t seed, int64_t n, float* __restrict__ X,
                               float* __restrict__ T, const DeviceTables* __restrict__ tabs) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -388,9 +388,7 @@ __global__ void k_mlp_samples(MlpSampleCfg c, uint64_t seed, int64_t n, float* _
   }
   const double x = sq * ad / aD;
   const double K = device_K<double>(x, y, tabs);
-  const double chi = c.chi == MARFA_CHI_TONKOV ? tonkov<double>(ad)
-                   : c.chi == MARFA_CHI_USER ? MarfaUserChi::chi<double>(ad)
-                                             : 1.0;
+  const double chi = c.chi == MARFA_CHI_TONKOV ? tonkov<double>(ad) : 1.0;
   const double x2 = x * x, r = x2 + y * y, up = 1.0 + 1.7724538509055160 * y;
   const double kb = y * (1.0 + (3.0 * x2 - y * y) / (2.0 * r * r + 1.0)) / (1.7724538509055160 * (r + 0.5 * exp(-r))) +
                     exp(-x2) / (up * up);

@@ -235,29 +235,30 @@ __device__ float g_surr(float d, const LineRec32& L, const float* __restrict__ s
 }
 
 // Wave-local queue of learned-shape pairs: every lane pushes the pairs it
-// needs (up to kSurrQueue per wavefront), the network then runs on 64 queued
-// pairs at a time, and each lane reads its values back in its own order.
-// Per entry: |x|, y, |d| in cm, and the scale S' sqrt(pi) xs^2 / pi gamma_L
-// ... written A sqrt(pi) xs^2 with A = S' gamma_L / pi; the value replaces the
-// scale.  Layout of a wavefront's queue: four arrays of kSurrQueue floats.
-constexpr int kSurrQueue = 256;
+// needs in one session, the network then runs on 64 queued pairs at a time,
+// and each lane reads its values back by slot in its own order.  Per entry:
+// |x|, y and |d| in cm; the batch overwrites |x| with Kb(x, y) e^t / y, and
+// the lane scales it by its line's S' sqrt(pi) xs^2 (= A sqrt(pi) xs^2 with
+// A = S' gamma_L / pi).  A session pushes at most kSurrSlots pairs per lane
+// (the band pass's candidate nodes), so the queue never overflows.
+constexpr int kSurrSlots = 15;
+constexpr int kSurrQueue = 64 * kSurrSlots;   // entries per wavefront: three arrays of this many floats
 
 // Push `want` pairs of the calling lanes; returns the slot of each, `n` the
 // wave's running count (uniform).
-__device__ __forceinline__ int surr_push(float* q, bool want, int& n, float x, float y, float ad, float amp) {
+__device__ __forceinline__ int surr_push(float* q, bool want, int& n, float x, float y, float ad) {
   const uint64_t m = __builtin_amdgcn_ballot_w64(want);
   const int pos = n + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
   if (want) {
     q[pos] = fabsf(x);
     q[kSurrQueue + pos] = y;
     q[2 * kSurrQueue + pos] = ad;
-    q[3 * kSurrQueue + pos] = amp;
   }
   n += __builtin_popcountll(m);
   return pos;
 }
 
-// Evaluate the n queued pairs (n uniform): S' F(d) chi(|d|) = A sqrt(pi) xs^2 / y Kb(x, y) e^t.
+// Evaluate the n queued pairs (n uniform): Kb(x, y) e^t / y into the |x| slot.
 __device__ __forceinline__ void surr_batch(float* q, int n, const LevelArgs& a) {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   const int lane = threadIdx.x & 63;
@@ -270,7 +271,7 @@ __device__ __forceinline__ void surr_batch(float* q, int n, const LevelArgs& a) 
     float f1, f2, f3;
     mlp_features(x, y, ad, a.mlp_inv_c, f1, f2, f3);
     const float t = mlp_forward_wave(a.mlp, f1, f2, f3);
-    if (ok) q[3 * kSurrQueue + i] = q[3 * kSurrQueue + i] * __builtin_amdgcn_rcpf(y) * mlp_base(x, y) * __expf(t);
+    if (ok) q[i] = __builtin_amdgcn_rcpf(y) * mlp_base(x, y) * __expf(t);
   }
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 }
@@ -441,6 +442,7 @@ __device__ __forceinline__ void scan_fast(const typename RecOf<R>::T* __restrict
     if constexpr (SURR && !COUNT) {
       // learned shape: pairs in the trained domain through the wave's queue,
       // the others by the plain shape
+      static_assert(K <= kSurrSlots, "one queue session holds a lane's nodes");
       float f[K];
       bool reg[K], queued[K];
       int pos[K];
@@ -459,12 +461,12 @@ __device__ __forceinline__ void scan_fast(const typename RecOf<R>::T* __restrict
         queued[k] = reg[k] && dom;
         f[k] = 0.0f;
         if (reg[k] && !dom) f[k] = shape_fast<float, false>(d, L, sp, j, G, true, cnt) * chi_any<float>(fabsf(d), G);
-        pos[k] = surr_push(a.sq, queued[k], n, x, y, fabsf(d * float(kH0)), amp);
+        pos[k] = surr_push(a.sq, queued[k], n, x, y, fabsf(d * float(kH0)));
       }
       if (n > 0) surr_batch(a.sq, n, a);
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        if (queued[k]) f[k] = a.sq[3 * kSurrQueue + pos[k]];
+        if (queued[k]) f[k] = amp * a.sq[pos[k]];
         acc[k] += reg[k] ? f[k] : 0.0f;
       }
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -511,7 +513,9 @@ __device__ __forceinline__ void scan_fast_chi(const typename RecOf<R>::T* __rest
                                               uint32_t act, R ra, R rbx, int smax, bool chi_none, bool chi_mixed,
                                               R c0, R c1, const Geometry& G, R* acc, Counts& cnt, uint32_t& n_used,
                                               const LevelArgs& a, const CoreQueue& cq) {
-  if (chi_mixed)
+  // the learned shape carries chi itself (its plain fallback uses chi_any):
+  // one instantiation serves every chi mode
+  if (SURR || chi_mixed)
     scan_fast<R, COUNT, SGN, SURR, 2, K>(rec, sp, j0, j1, S, slice, X0, rl, act, ra, rbx, smax, c0, c1, G, acc, cnt,
                                          n_used, a, cq);
   else if (chi_none)
@@ -870,9 +874,10 @@ __device__ __forceinline__ void band_chunk(const typename RecOf<R>::T& L, int32_
   // T_(l+1) at level-(l+1) nodes kc0-H .. kc0+NC-1+H
   R dd[NC + 2 * H], T1[NC + 2 * H];
   if constexpr (SURR && !COUNT) {
-    // learned shape: the stencil values through the wave's queue
-    int pos[NC + 2 * H];
-    bool queued[NC + 2 * H];
+    // learned shape: the stencil values through the wave's queue; a queued
+    // slot holds its queue position (bit i of qmask) until the batch returns
+    static_assert(NC + 2 * H <= kSurrSlots, "one queue session holds the stencil values");
+    uint32_t qmask = 0;
     int n = 0;
     const float amp = L.A * 1.7724538509055160f * L.xs * L.xs;
 #pragma unroll
@@ -882,15 +887,19 @@ __device__ __forceinline__ void band_chunk(const typename RecOf<R>::T& L, int32_
       const bool act = ok && adi <= cfine && !(l + 1 > ls && adi < b_cur);
       float x, y;
       const bool dom = surr_domain(dd[i], L, a, x, y);
-      queued[i] = act && dom;
+      const bool queued = act && dom;
       T1[i] = 0.0f;
       if (act && !dom) T1[i] = g_any<float, false>(dd[i], L, sp, jl, G, cfine, true, cnt);
-      pos[i] = surr_push(a.sq, queued[i], n, x, y, adi * float(kH0), amp);
+      const int pos = surr_push(a.sq, queued, n, x, y, adi * float(kH0));
+      if (queued) {
+        T1[i] = __int_as_float(pos);
+        qmask |= 1u << i;
+      }
     }
     if (n > 0) surr_batch(a.sq, n, a);
 #pragma unroll
     for (int i = 0; i < NC + 2 * H; ++i)
-      if (queued[i]) T1[i] = a.sq[3 * kSurrQueue + pos[i]];
+      if ((qmask >> i) & 1u) T1[i] = amp * a.sq[__float_as_int(T1[i])];
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   } else {
 #pragma unroll
@@ -943,9 +952,11 @@ __device__ __forceinline__ void band_chunk(const typename RecOf<R>::T& L, int32_
   };
   R glv[NC][RHO];
   if constexpr (SURR && !COUNT) {
-    // learned shape: the line's own values at the candidate nodes through the queue
-    int pos[NC][RHO];
-    bool queued[NC][RHO];
+    // learned shape: the line's own values at the candidate nodes through the
+    // queue (queued slots hold their position, bit c RHO + ji of qmask)
+    static_assert(NC * RHO <= 32, "one mask bit per candidate node");
+    static_assert(NC * (RHO - 1) <= kSurrSlots, "one queue session holds the candidate nodes");
+    uint32_t qmask = 0;
     int n = 0;
     const float amp = L.A * 1.7724538509055160f * L.xs * L.xs;
 #pragma unroll
@@ -953,8 +964,6 @@ __device__ __forceinline__ void band_chunk(const typename RecOf<R>::T& L, int32_
 #pragma unroll
       for (int jj = -RHO / 2 + 1; jj <= RHO / 2; ++jj) {
         const int ji = jj + RHO / 2 - 1;
-        queued[c][ji] = false;
-        pos[c][ji] = 0;
         glv[c][ji] = 0.0f;
         if (jj == 0) continue;
         R d;
@@ -962,16 +971,20 @@ __device__ __forceinline__ void band_chunk(const typename RecOf<R>::T& L, int32_
         node(c, jj, d, use, need, in_reg, own);
         float x, y;
         const bool dom = surr_domain(d, L, a, x, y);
-        queued[c][ji] = need && dom;
+        const bool queued = need && dom;
         if (need && !dom) glv[c][ji] = g_any<float, false>(d, L, sp, jl, G, cfine, true, cnt);
-        pos[c][ji] = surr_push(a.sq, queued[c][ji], n, x, y, fabsf(d) * float(kH0), amp);
+        const int pos = surr_push(a.sq, queued, n, x, y, fabsf(d) * float(kH0));
+        if (queued) {
+          glv[c][ji] = __int_as_float(pos);
+          qmask |= 1u << (c * RHO + ji);
+        }
       }
     if (n > 0) surr_batch(a.sq, n, a);
 #pragma unroll
     for (int c = 0; c < NC; ++c)
 #pragma unroll
       for (int ji = 0; ji < RHO; ++ji)
-        if (queued[c][ji]) glv[c][ji] = a.sq[3 * kSurrQueue + pos[c][ji]];
+        if ((qmask >> (c * RHO + ji)) & 1u) glv[c][ji] = amp * a.sq[__float_as_int(glv[c][ji])];
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   }
 #pragma unroll
@@ -1118,7 +1131,7 @@ __device__ __forceinline__ void level_body(const Geometry& G, const LevelArgs& a
   __shared__ int64_t s_item;
   const int wv = threadIdx.x >> 6;
   if constexpr (SURR) {
-    __shared__ float s_sq[4][4 * kSurrQueue];
+    __shared__ float s_sq[4][3 * kSurrQueue];
     a.sq = s_sq[wv];
   }
   CoreQueue cq{nullptr, nullptr, nullptr, nullptr};

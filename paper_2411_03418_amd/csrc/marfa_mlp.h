@@ -159,6 +159,9 @@ __device__ __forceinline__ float mlp_forward_wave(const MlpDev& W, float f1, flo
   float result = 0.0f;
 #pragma unroll 1
   for (int s = 0; s < 4; ++s) {
+    // keeps the weight loads inside the loop: hoisted to the callers' loops
+    // they would hold ~100 registers for the whole kernel
+    asm volatile("" ::: "memory");
     const int src = 16 * s + col;
     const float g1 = __shfl(f1, src), g2 = __shfl(f2, src), g3 = __shfl(f3, src);
     float h[16], z[16];

@@ -445,7 +445,9 @@ extern "C" marfa_status marfa_surrogate_create(marfa_surrogate** out, int32_t ch
                                                int32_t device) {
   if (!out) return sfail(MARFA_E_INVALID, "null argument");
   *out = nullptr;
-  if (chi < MARFA_CHI_NONE || chi > MARFA_CHI_USER) return sfail(MARFA_E_INVALID, "unknown chi");
+  if (chi == MARFA_CHI_USER)
+    return sfail(MARFA_E_UNSUPPORTED, "the learned shape's distance feature is built on the Tonkov chi's first break");
+  if (chi != MARFA_CHI_NONE && chi != MARFA_CHI_TONKOV) return sfail(MARFA_E_INVALID, "unknown chi");
   if (!(cutoff > 0.0) || !std::isfinite(cutoff)) return sfail(MARFA_E_INVALID, "cutoff must be > 0");
   marfa_status st = marfa_use_device(device);
   if (st != MARFA_OK) return st;

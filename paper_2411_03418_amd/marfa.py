@@ -13,7 +13,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libmarfa.so")
+# MARFA_LIB selects another build of the library (e.g. one with a different user line shape)
+LIB_PATH = os.environ.get("MARFA_LIB") or os.path.join(_HERE, "libmarfa.so")
 
 OK, E_INVALID, E_NOMEM, E_DEVICE, E_UNSUPPORTED, E_STATE, E_IO = 0, -1, -2, -3, -4, -5, -6
 PTBIN_NT = 20481          # values per PT-table record (Appendix A)

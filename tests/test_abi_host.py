@@ -109,6 +109,13 @@ def test_surrogate_create_rejects_bad_configuration(chi, cutoff):
     assert not h.value
 
 
+def test_surrogate_refuses_the_user_chi():
+    L = marfa.lib()
+    h = C.c_void_p()
+    assert L.marfa_surrogate_create(C.byref(h), marfa.CHIS["user"], 125.0, 1, 0) == marfa.E_UNSUPPORTED
+    assert not h.value
+
+
 def test_null_handles_are_rejected():
     L = marfa.lib()
     t = marfa.Tiles()
