@@ -33,14 +33,6 @@ PEAK_BF16_MFMA_TFLOPS = 2500.0  # MI355X published dense BF16 matrix peak
 # 64->64 layers (2*64*64 each), 64->1 (2*64); the split-BF16 activations run
 # the hidden layers twice on the matrix cores, which is not counted here
 FLOP_MLP = 2 * 3 * 64 + 64 + 3 * 2 * 64 * 64 + 2 * 64
-
-# Algorithmic flops per unit of work, counted from the kernel source
-# (FMA = 2, add / mul = 1, rcp / exp2 = 1; compares, selects and integer
-# address arithmetic are not counted):
-FLOP_WING = 18        # d, d^2+g^2, 1/., e, U, 1+eU, A Q sum, chi = exp2(c0+c1 d), acc += g chi
-FLOP_TERM = 6         # one more term of the asymptotic wing series
-FLOP_CORE = 2 * 230   # rational core in FP64 (27 complex Horner steps + setup); FP64 counts double
-FLOP_BAND = 6         # three stencil weights times coarse values, per band pair
 STENCIL5_R = 24      # 5-point R with the cost of the 3-point R = 48 table and ~40x lower interpolation error
 
 
@@ -58,7 +50,8 @@ def profiled_traffic(workload):
             k, v = ln.split(":", 1)
             rec[k] = v.strip()
     h = hashlib.sha256()
-    for src in ("marfa_kernels.hip", "marfa_internal.h", "marfa_mlp.h"):
+    for src in ("marfa_level_f32.hip", "marfa_level.h", "marfa_device.h", "marfa_internal.h", "marfa_mlp.h",
+                "marfa_user.h"):
         with open(os.path.join(ROOT, "paper_2411_03418_amd", "csrc", src), "rb") as f:
             h.update(f.read())
     if rec.get("kernel_source_sha256") != h.hexdigest():
@@ -66,32 +59,58 @@ def profiled_traffic(workload):
     return float(rec["traffic_bytes_per_launch"])
 
 
-def counted_flops(st):
-    """Counted FP32-equivalent flops of one level-kernel launch over all layers."""
-    return float(FLOP_WING * st["pairs_wing"] + FLOP_TERM * st["wing_terms"] + FLOP_CORE * st["pairs_core"]
-                 + FLOP_BAND * st["pairs_band"])
+def _cpu_model():
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def cpu_baseline(lines, layers, req, budget_s):
-    """The FP64 oracle's eleven-grid program on a bounded sample of the workload:
-    one layer, a sub-interval of the spectrum grown until the budget is used."""
+    """The FP64 oracle on bounded samples of the workload, on this host's cores:
+    the eleven-grid program on every core available to the process and on one
+    core, and the direct sum per sampled node.  The budget is split between the
+    three legs; each leg grows its sample until it uses its share."""
     import oracle as O
-    threads = min(os.cpu_count() or 1, 16)
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
     L = layers[len(layers) // 2]
     o = dict(cutoff=req["cutoff"], chi=req["chi"], prune=req["prune"])
-    width = 0.25
-    lo = 0.5 * (req["nu_begin"] + req["nu_end"])
+    mid = 0.5 * (req["nu_begin"] + req["nu_end"])
+
+    def grid_rate(threads, share):
+        width = 0.25
+        while True:
+            t0 = time.perf_counter()
+            out = O.grid(lines, L, threads=threads, nu_begin=mid, nu_end=mid + width, **o)
+            dt = time.perf_counter() - t0
+            if dt > share / 3 or width >= 4096:
+                return out.size, dt, width
+            width *= 2 if dt > 0.2 * share / 3 else 4
+
+    pts, dt, width = grid_rate(cores, 0.5 * budget_s)
+    pts1, dt1, width1 = grid_rate(1, 0.25 * budget_s)
+    n = 64
+    m0 = int(round(mid * 2048))
     while True:
+        nodes = m0 + np.arange(n, dtype=np.int64) * 97
         t0 = time.perf_counter()
-        out = O.grid(lines, L, threads=threads, nu_begin=lo, nu_end=lo + width, **o)
-        dt = time.perf_counter() - t0
-        if dt > budget_s / 3 or width >= 4096:
+        O.direct(lines, L, nodes, threads=cores, nu_begin=req["nu_begin"], nu_end=req["nu_end"], **o)
+        dtd = time.perf_counter() - t0
+        if dtd > 0.25 * budget_s / 3 or n >= 1 << 20:
             break
-        width *= 2 if dt > 0.2 * budget_s / 3 else 4
-    pts = out.size
-    return dict(value=pts / dt, unit="points/s", cores=threads, kind="oracle",
-                sample=f"eleven-grid oracle (FP64), layer {len(layers) // 2} (p={L[0]:.3g} atm, T={L[1]:.0f} K), "
-                       f"{width:g} cm^-1 at {lo:g} cm^-1 = {pts} points, {dt:.2f} s")
+        n *= 4 if dtd < 0.05 * budget_s / 3 else 2
+    lay = f"layer {len(layers) // 2} (p={L[0]:.3g} atm, T={L[1]:.0f} K)"
+    return dict(value=pts / dt, unit="points/s", cores=cores, kind="oracle",
+                sample=f"eleven-grid oracle (FP64), {lay}, {width:g} cm^-1 at {mid:g} cm^-1 = {pts} points "
+                       f"in {dt:.2f} s on {cores} threads",
+                grid_1core=dict(value=pts1 / dt1, unit="points/s", cores=1,
+                                sample=f"{width1:g} cm^-1 = {pts1} points in {dt1:.2f} s"),
+                direct=dict(value=n / dtd, unit="points/s", cores=cores,
+                            sample=f"direct sum at {n} nodes (every 97th from {mid:g} cm^-1) in {dtd:.2f} s"),
+                host=dict(nproc=os.cpu_count(), cpu_model=_cpu_model(), threads_available=cores))
 
 
 def timed_steps(plan, out, steps, warmup):
@@ -107,13 +126,21 @@ def timed_steps(plan, out, steps, warmup):
 
 
 def rel_dev(a, b):
-    """max over layers and nodes with a >= 1e-8 of the layer max of |b - a| / a."""
+    """max over layers and nodes with a >= 1e-8 of the layer max of |b - a| / a
+    (infinite when b holds a non-finite value)."""
     worst = 0.0
     for i in range(a.shape[0]):
         x, y = a[i].double(), b[i].double()
+        if not bool(torch_isfinite_all(y)):
+            return float("inf")
         m = x >= 1e-8 * x.max()
         worst = max(worst, float(((y[m] - x[m]).abs() / x[m]).max()))
     return worst
+
+
+def torch_isfinite_all(t):
+    import torch
+    return torch.isfinite(t).all()
 
 
 def stencil5_leg(lines, layers, req, plain, steps):
@@ -139,6 +166,33 @@ def stencil5_leg(lines, layers, req, plain, steps):
     return dict(value=points / (ms * 1e-3), unit="points/s", ms_per_step=ms, level_ms=float(np.mean(lv)),
                 steps=steps, stencil=5, R=STENCIL5_R, pairs=int(sum(st["pairs_level"])),
                 band_pairs=int(st["pairs_band"]), max_rel_dev_from_3point=dev, tiles=tiles)
+
+
+def surrogate_table_leg(plan, out, lines, layers, chi, cutoff, workload):
+    """The learned line shape on the benchmark's own table, trained for its
+    line and temperature ranges; one timed step (the deviation from the plain
+    output of the same plan is over every node of every layer)."""
+    import torch
+    from paper_2411_03418_amd import marfa
+    S = marfa.Surrogate(chi=chi, cutoff=cutoff, seed=1)
+    nu = lines.nu0[lines.nu0 > 0]
+    rep = S.fit(nu_lo=float(nu.min()), nu_hi=float(nu.max()), T_lo=float(layers[:, 1].min()),
+                T_hi=float(layers[:, 1].max()))
+    print(f"[bench] {workload} surrogate trained: {rep}", file=sys.stderr, flush=True)
+    plain = out.clone()
+    plan.set_surrogate(S)
+    plan.set_eval("surrogate")
+    ms = timed_steps(plan, out, 1, 0)
+    dev = rel_dev(plain, out)
+    plan.set_eval("plain")
+    out.copy_(plain)   # later legs compare against the plain output
+    del plain
+    torch.cuda.empty_cache()
+    S.close()
+    points = plan.points * plan.n_layers
+    print(f"[bench] {workload} surrogate {ms:.1f} ms/step; max dev from plain {dev:.2e}", file=sys.stderr, flush=True)
+    return dict(workload=workload, value=points / (ms * 1e-3), unit="points/s", ms_per_step=ms, steps=1, warmup=0,
+                max_rel_dev_from_plain=dev, train_ms=rep["ms"], val_max_abs_t=rep["val_max_abs"])
 
 
 def surrogate_leg(args):
@@ -187,9 +241,11 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="pt100_2m")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--no-surrogate-table", action="store_true",
+                    help="skip the learned shape on the benchmark's own table (one step)")
     ap.add_argument("--no-stencil5", action="store_true", help="skip the 5-point stencil leg")
     ap.add_argument("--surrogate-steps", type=int, default=2)
     ap.add_argument("--no-tune", action="store_true", help="keep the density-based tiles")
@@ -233,9 +289,9 @@ def main():
         tiles = plan.tiles()
     print(f"[bench] tiles {tiles}", file=sys.stderr, flush=True)
     st = plan.count()
-    flops = counted_flops(st)
-    print(f"[bench] pairs {sum(st['pairs_level']):.3e}, core {st['pairs_core']:.3e}, band {st['pairs_band']:.3e}",
-          file=sys.stderr, flush=True)
+    flops = st["flops_level"]
+    print(f"[bench] pairs {sum(st['pairs_level']):.3e}, core {st['pairs_core']:.3e}, band {st['pairs_band']:.3e}, "
+          f"counted {flops:.3e} flop per level launch", file=sys.stderr, flush=True)
     ms = timed_steps(plan, out, args.steps, args.warmup)
     points = plan.points * plan.n_layers
     # dominant kernel: the level stage, timed by HIP events on the launch stream
@@ -247,6 +303,10 @@ def main():
     achieved = flops / (level_ms * 1e-3) / 1e12
     print(f"[bench] {ms:.2f} ms/step; level {level_ms:.2f} ms, prep {np.mean(prep):.2f} ms, "
           f"cascade {np.mean(cas):.2f} ms", file=sys.stderr, flush=True)
+    s_big = None
+    if not args.no_surrogate and not args.no_surrogate_table:
+        s_big = surrogate_table_leg(plan, out, lines, layers, chi, req["cutoff"], args.workload)
+        s_big["speed_vs_plain"] = ms / s_big["ms_per_step"]
     plan.close()
     s5 = None
     if not args.no_stencil5:
@@ -273,7 +333,11 @@ def main():
                    "path": "plain", "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_VALU_TFLOPS, "traffic": profiled_traffic(args.workload),
-                     "kernel": "k_level", "kernel_ms": level_ms, "counted_tflop_per_launch": flops / 1e12},
+                     "kernel": "k_level_f32", "kernel_ms": level_ms, "counted_tflop_per_launch": flops / 1e12,
+                     "flops_per_unit": {k: st[k] for k in ("flops_per_eval", "flops_per_core", "flops_per_term",
+                                                           "flops_per_band")},
+                     "algorithmic_bytes_per_launch": st["bytes_level"],
+                     "algorithmic_gbs": st["bytes_level"] / (level_ms * 1e-3) / 1e9},
         "stages_ms": {"prep": float(np.mean(prep)), "level": level_ms, "cascade": float(np.mean(cas)),
                       "graph_total": float(np.mean(tot))},
         "pairs": {"total": int(sum(st["pairs_level"])), "core": int(st["pairs_core"]),
@@ -288,6 +352,8 @@ def main():
         line["stencil5"] = s5
     if not args.no_surrogate:
         line["surrogate"] = surrogate_leg(args)
+    if s_big is not None:
+        line["surrogate_table"] = s_big
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(lines, layers, dict(req, chi=rq["chi"]), args.cpu_seconds)
     print(json.dumps(line))

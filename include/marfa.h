@@ -203,8 +203,9 @@ marfa_status marfa_plan_set_tiles(marfa_plan* plan, const marfa_tiles* tiles);
 /* Autotuner: runs line preparation, then times the level kernel on the
  * device for candidate tile parameters with the plan's own lines and layers
  * and keeps the fastest -- per level the region tile (wave_nodes 1, 2, 4,
- * ..., 64), then the work-item size
- * (128, 256, 512) and the persistent grid (4, 8, 16 workgroups per CU).
+ * ..., 64), then the work-item size (128, 256, 512) and the persistent
+ * grid (4, 8, 16 workgroups per CU), then one pass over the levels trying
+ * each tile's two neighbouring widths with the whole stage timed.
  * scratch_out_dev is an output buffer as for marfa_execute (overwritten).
  * Synchronous on hip_stream; captured graphs are rebuilt on the next
  * execute.  Tile shapes change the summation order, so results may change

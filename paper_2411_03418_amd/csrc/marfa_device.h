@@ -11,6 +11,14 @@
 #include "marfa_internal.h"
 #include "marfa_user.h"
 
+// Whether this translation unit's kernels evaluate the user line shape and
+// chi.  The level kernels are built twice: without them (the kernels every
+// other plan runs, free of their code) and with them (plans that select the
+// user shape or chi).
+#ifndef MARFA_USER_PLUGINS
+#define MARFA_USER_PLUGINS 1
+#endif
+
 namespace marfa {
 
 // physical constants (CODATA 2018) and HITRAN reference temperature
@@ -168,7 +176,7 @@ __device__ __forceinline__ R line_value(R d, const typename RecOf<R>::T& L, R Sp
   } else if (G.shape == MARFA_SHAPE_DOPPLER) {
     R x = R(L.xs) * dcm;
     f = R(L.xs) * R(kInvSqrtPi) * exp(-x * x);
-  } else if (G.shape == MARFA_SHAPE_USER) {
+  } else if (MARFA_USER_PLUGINS && G.shape == MARFA_SHAPE_USER) {
     // xs = sqrt(ln 2) / alpha_D, and 0 for a line without Doppler width
     const R aD = L.xs > R(0) ? R(kSqrtLn2) / R(L.xs) : R(0);
     f = MarfaUserShape::f<R>(dcm, R(L.gam), aD);
@@ -192,7 +200,7 @@ __device__ __forceinline__ R line_value(R d, const typename RecOf<R>::T& L, R Sp
   }
   R chi = R(1);
   if (G.chi == MARFA_CHI_TONKOV) chi = tonkov<R>(ad * R(kH0));
-  else if (G.chi == MARFA_CHI_USER) chi = MarfaUserChi::chi<R>(ad * R(kH0));
+  else if (MARFA_USER_PLUGINS && G.chi == MARFA_CHI_USER) chi = MarfaUserChi::chi<R>(ad * R(kH0));
   return Sp * f * chi;
 }
 

@@ -435,14 +435,21 @@ void launch_level_f32_count(const Geometry& G, const LevelArgs& a, int grid, hip
 void launch_level_f32_surr(const Geometry& G, const LevelArgs& a, int grid, hipStream_t s);
 void launch_level_f64(const Geometry& G, const LevelArgs& a, int grid, hipStream_t s);
 void launch_level_f64_count(const Geometry& G, const LevelArgs& a, int grid, hipStream_t s);
+void launch_level_f32_user(const Geometry& G, const LevelArgs& a, int grid, hipStream_t s);
+void launch_level_f64_user(const Geometry& G, const LevelArgs& a, int grid, hipStream_t s);
 
+// Plans with the user line shape or chi run the kernels built with them; the
+// pair-counting kernels never evaluate a shape's value.
 void launch_level(const Geometry& G, const LevelArgs& a, int grid, bool fp64, bool count, hipStream_t s) {
+  const bool user = G.shape == MARFA_SHAPE_USER || G.chi == MARFA_CHI_USER;
   if (fp64) {
     if (count) launch_level_f64_count(G, a, grid, s);
+    else if (user) launch_level_f64_user(G, a, grid, s);
     else launch_level_f64(G, a, grid, s);
   } else {
     if (count) launch_level_f32_count(G, a, grid, s);
     else if (a.surr) launch_level_f32_surr(G, a, grid, s);
+    else if (user) launch_level_f32_user(G, a, grid, s);
     else launch_level_f32(G, a, grid, s);
   }
 }

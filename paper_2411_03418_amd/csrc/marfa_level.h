@@ -66,7 +66,7 @@ template <> struct Series<double> { static constexpr int kMax = 60; };
 // selects; the user chi through its compiled-in function
 template <typename R>
 __device__ __forceinline__ R chi_any(R ad_fine, const Geometry& G) {
-  if (G.chi == MARFA_CHI_USER) return MarfaUserChi::chi<R>(ad_fine * R(kH0));
+  if (MARFA_USER_PLUGINS && G.chi == MARFA_CHI_USER) return MarfaUserChi::chi<R>(ad_fine * R(kH0));
   if (G.chi != MARFA_CHI_TONKOV) return R(1);
   const R a = ad_fine * R(kH0);
   R c0 = R(0), c1 = R(0);

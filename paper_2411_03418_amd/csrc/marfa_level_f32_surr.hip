@@ -1,4 +1,5 @@
-// marfa_level_f32_surr.hip -- the level kernel <float, false, true> and its launcher.
+// marfa_level_f32_surr.hip -- the level kernel <float, false, true> without the user line shape and chi, and its launcher.
+#define MARFA_USER_PLUGINS 0
 #include "marfa_level.h"
 
 MARFA_LEVEL_LAUNCHER(f32_surr, float, false, true, 3)

@@ -1102,11 +1102,30 @@ extern "C" marfa_status marfa_plan_tune(marfa_plan* p, void* out, int64_t stride
   }
   std::vector<Tile> tl;
   make_tiles(p->G, tl, best_base);
-  for (int bpc : {4, 16}) {
+  for (int bpc : {4, 8, 16}) {
+    if (bpc == best_bpc) continue;
     float ms = 0.f;
     st = time_level(p, tl, p->cu_count * bpc, out, stride, s, &ms);
     if (st != MARFA_OK) return st;
     if (ms < best) { best = ms; best_bpc = bpc; }
+  }
+  // 3. one pass over the levels with the whole stage timed: a level's tile
+  // chosen alone can interact with the others' (the persistent grid's tail
+  // and the mix of levels on a CU), so each width's neighbours are retried
+  for (int l = 0; l < kLevels; ++l) {
+    const int cur = p->G.lnw[l];
+    for (int c : {cur - 1, cur + 1}) {
+      if (c < 0 || c > 6) continue;
+      p->G.lnw[l] = c;
+      float ms = 0.f;
+      st = time_level(p, tl, p->cu_count * best_bpc, out, stride, s, &ms);
+      if (st != MARFA_OK) { p->G.lnw[l] = cur; return st; }
+      if (ms < 0.995f * best) {
+        best = ms;
+        break;   // keep c
+      }
+      p->G.lnw[l] = cur;
+    }
   }
   p->base_nodes = best_base;
   p->blocks_per_cu = best_bpc;
