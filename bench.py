@@ -38,10 +38,10 @@ STENCIL5_R = 24      # 5-point R with the cost of the 3-point R = 48 table and ~
 
 def profiled_traffic(workload):
     """HBM bytes per k_level launch measured with rocprofv3 counters for this
-    workload (profiles/k_level_<workload>.md), or None when there is no such
+    workload (profiles/k_level_f32_<workload>.md), or None when there is no such
     profile or the kernel sources changed since it was taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", f"k_level_{workload}.md")
+    path = os.path.join(ROOT, "profiles", f"k_level_f32_{workload}.md")
     if not os.path.exists(path):
         return None
     rec = {}
