@@ -83,7 +83,12 @@ __device__ __forceinline__ uint32_t mlp_bf16_bits(float v) {
 __device__ __forceinline__ float mlp_bf16_round(float v) { return __uint_as_float(mlp_bf16_bits(v) << 16); }
 
 // B operand (8 BF16) of chunk c from the lane's 16 activations h[t*4+i],
-// split into hi and lo parts
+// split into hi and lo parts, both rounded to nearest even: in integer
+// arithmetic (training), or with v_cvt_pk_bf16_f32 (inference; the same
+// values in a quarter of the instructions)
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+template <bool HW = false>
 __device__ __forceinline__ void mlp_pack_b(const float* h, int c, bf16x8& hi, bf16x8& lo) {
   uint32_t wh[4], wl[4];
 #pragma unroll
@@ -92,10 +97,20 @@ __device__ __forceinline__ void mlp_pack_b(const float* h, int c, bf16x8& hi, bf
     const int e0 = 2 * p, e1 = 2 * p + 1;
     const float v0 = h[(2 * c + e0 / 4) * 4 + (e0 % 4)];
     const float v1 = h[(2 * c + e1 / 4) * 4 + (e1 % 4)];
-    const uint32_t h0 = mlp_bf16_bits(v0), h1 = mlp_bf16_bits(v1);
-    const float r0 = v0 - __uint_as_float(h0 << 16), r1 = v1 - __uint_as_float(h1 << 16);
-    wh[p] = h0 | (h1 << 16);
-    wl[p] = mlp_bf16_bits(r0) | (mlp_bf16_bits(r1) << 16);
+    if constexpr (HW) {
+      const bf16x2 hp = __builtin_convertvector((f32x2){v0, v1}, bf16x2);
+      uint32_t u;
+      __builtin_memcpy(&u, &hp, 4);
+      const f32x2 r = {v0 - __uint_as_float(u << 16), v1 - __uint_as_float(u & 0xffff0000u)};
+      const bf16x2 lp = __builtin_convertvector(r, bf16x2);
+      wh[p] = u;
+      __builtin_memcpy(&wl[p], &lp, 4);
+    } else {
+      const uint32_t h0 = mlp_bf16_bits(v0), h1 = mlp_bf16_bits(v1);
+      const float r0 = v0 - __uint_as_float(h0 << 16), r1 = v1 - __uint_as_float(h1 << 16);
+      wh[p] = h0 | (h1 << 16);
+      wl[p] = mlp_bf16_bits(r0) | (mlp_bf16_bits(r1) << 16);
+    }
   }
   __builtin_memcpy(&hi, wh, 16);
   __builtin_memcpy(&lo, wl, 16);
@@ -108,12 +123,13 @@ __device__ __forceinline__ bf16x8 mlp_as_bf16x8(uint4 v) {
 }
 
 // One hidden layer for one sample tile: z_out[r*4+i] = b[16r+4q+i] + sum_in W[..][in] h_in[in]
+template <bool HW = false>
 __device__ __forceinline__ void mlp_hidden(const uint4* __restrict__ wp_layer, const float* __restrict__ bias,
                                            const float* h, float* z, int lane) {
   const int q = lane >> 4;
   bf16x8 bh[2], bl[2];
-  mlp_pack_b(h, 0, bh[0], bl[0]);
-  mlp_pack_b(h, 1, bh[1], bl[1]);
+  mlp_pack_b<HW>(h, 0, bh[0], bl[0]);
+  mlp_pack_b<HW>(h, 1, bh[1], bl[1]);
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     f32x4 acc;
@@ -174,7 +190,7 @@ __device__ __forceinline__ float mlp_forward_wave(const MlpDev& W, float f1, flo
       }
 #pragma unroll 1
     for (int k = 0; k < kMlpHidLayers; ++k) {
-      mlp_hidden(W.wp + k * 8 * 64, W.bh + k * 64, h, z, lane);
+      mlp_hidden<true>(W.wp + k * 8 * 64, W.bh + k * 64, h, z, lane);
 #pragma unroll
       for (int v = 0; v < 16; ++v) h[v] = mlp_silu(z[v]);
     }
