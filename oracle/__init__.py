@@ -73,6 +73,8 @@ def lib():
         L.orc_chi.argtypes = [i32, d]
         L.orc_user_chi_breaks.restype = i32
         L.orc_user_chi_breaks.argtypes = [C.c_void_p, i32]
+        L.orc_stencil_of.restype = i32
+        L.orc_stencil_of.argtypes = [C.POINTER(_Request), i32, i64, vp, vp]
         L.orc_shape.restype = d
         L.orc_shape.argtypes = [i32, d, d, d]
         L.orc_line_state_of.argtypes = [C.POINTER(_Lines), C.POINTER(_Layer), i64, C.POINTER(_State)]
@@ -142,6 +144,17 @@ def user_chi_breaks() -> list:
     if n < 0:
         raise RuntimeError("orc_user_chi_breaks failed")
     return [float(v) for v in buf[:n]]
+
+
+def stencil_of(l: int, m: int, stencil: int = 3, level_table: int = 0):
+    """Coarse node indices and weights interpolating level-l node m from level l+1."""
+    rq = _request(0.0, 1.0, 25.0, level_table=level_table, stencil=stencil)
+    k = np.zeros(5, np.int64)
+    w = np.zeros(5, np.float64)
+    n = lib().orc_stencil_of(C.byref(rq), int(l), int(m), _ptr(k), _ptr(w))
+    if n < 0:
+        raise ValueError("invalid stencil request")
+    return k[:n].copy(), w[:n].copy()
 
 
 def shape(kind: int, d: float, gamma_L: float, alpha_D: float) -> float:

@@ -240,7 +240,7 @@ static int validate(const orc_lines* L, const orc_layer* lay, const orc_request*
   if (floor(rq->nu_end * 2048.0) != rq->nu_end * 2048.0) return -1;
   if (!(rq->cutoff > 0.0) || !finite_d(rq->cutoff)) return -1;
   if (!(rq->R >= 4.0) || !finite_d(rq->R)) return -1;
-  if (rq->stencil != 0 && rq->stencil != 3 && rq->stencil != 5) return -1;
+  if (rq->stencil != 0 && rq->stencil != 3 && rq->stencil != 4 && rq->stencil != 5) return -1;
   if (!(lay->T_K > 0.0) || !(lay->p_atm >= 0.0) || !(lay->p_self_atm >= 0.0) ||
       lay->p_self_atm > lay->p_atm || !finite_d(lay->T_K) || !finite_d(lay->p_atm))
     return -1;
@@ -398,7 +398,7 @@ int orc_direct(const orc_lines* L, const orc_layer* lay, const orc_request* rq,
 #define NLEV 11
 
 typedef struct {
-  int ns;                   /* stencil points, 3 or 5 */
+  int ns;                   /* stencil points, 3, 4 or 5 */
   int64_t r[NLEV];          /* level step in finest steps */
   double h[NLEV];           /* level step [cm^-1] */
   double b[NLEV];           /* b_l = R h_(l+1), l = 0..9 */
@@ -416,8 +416,8 @@ static int64_t floor_div(int64_t a, int64_t b) {
 }
 
 static void make_geom(const orc_request* rq, grid_geom* G) {
-  G->ns = rq->stencil == 5 ? 5 : 3;
-  const int half = G->ns / 2;
+  G->ns = rq->stencil == 0 ? 3 : rq->stencil;
+  const int half = G->ns == 3 ? 1 : 2;   /* coarse nodes a stencil reaches beyond its interval */
   for (int l = 0; l < NLEV; ++l) {
     if (rq->level_table == 1) G->r[l] = (int64_t)1 << l;
     else G->r[l] = l == 0 ? 1 : ((int64_t)1 << (l + 1));
@@ -495,11 +495,15 @@ static int jumps_of(const grid_geom* G, const gline* ln, int l, double* q) {
   return n;
 }
 
-/* Stencil of level-l node m on level l+1: the ns coarse nodes centred on
- * the nearest one kc (a tie goes to the lower), k[i] = kc - ns/2 + i, with
- * Lagrange weights w_i(t) = prod_{j != i} (t - j') / (i' - j') over the
- * offsets i', j' in -ns/2 .. ns/2, t = u - kc; one node with weight 1 where
- * m coincides with a coarse node. */
+/* Stencil of level-l node m on level l+1, u = m r_l / r_(l+1) in coarse
+ * steps: one node with weight 1 where m coincides with a coarse node;
+ * otherwise Lagrange weights w_i(t) = prod_{j != i} (t - j') / (i' - j') over
+ * the stencil's offsets i', j'.
+ *  3 or 5 points: the ns coarse nodes centred on the nearest one kc (a tie
+ *    goes to the lower), k[i] = kc - ns/2 + i, offsets -ns/2 .. ns/2, t = u - kc;
+ *  4 points: the two coarse nodes on each side of u, k[i] = q - 1 + i with
+ *    q = floor(u), offsets -1 .. 2, t = u - q (at a midpoint the weights are
+ *    (-1, 9, 9, -1)/16). */
 static int stencil(const grid_geom* G, int l, int64_t m, int64_t* k, double* w) {
   int64_t rho = G->r[l + 1] / G->r[l];
   int64_t q = floor_div(m, rho);
@@ -509,6 +513,16 @@ static int stencil(const grid_geom* G, int l, int64_t m, int64_t* k, double* w) 
     return 1;
   }
   double f = (double)rem / (double)rho, t;
+  if (G->ns == 4) {
+    for (int i = -1; i <= 2; ++i) {
+      double v = 1.0;
+      for (int j = -1; j <= 2; ++j)
+        if (j != i) v *= (f - j) / (double)(i - j);
+      k[i + 1] = q + i;
+      w[i + 1] = v;
+    }
+    return 4;
+  }
   int64_t kc;
   if (f <= 0.5) { kc = q; t = f; } else { kc = q + 1; t = f - 1.0; }
   const int half = G->ns / 2;
@@ -520,6 +534,15 @@ static int stencil(const grid_geom* G, int l, int64_t m, int64_t* k, double* w) 
     w[i + half] = v;
   }
   return G->ns;
+}
+
+int orc_stencil_of(const orc_request* rq, int32_t l, int64_t m, int64_t* k, double* w) {
+  if (!rq || !k || !w || l < 0 || l >= NLEV - 1) return -1;
+  if (rq->stencil != 0 && rq->stencil != 3 && rq->stencil != 4 && rq->stencil != 5) return -1;
+  grid_geom G;
+  memset(&G, 0, sizeof G);
+  make_geom(rq, &G);
+  return stencil(&G, l, m, k, w);
 }
 
 /* Does the stencil of node m (level l) straddle a jump of T_(l+1)?

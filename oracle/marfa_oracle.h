@@ -58,7 +58,7 @@ typedef struct {
   int32_t level_table;      /* 0: steps 2^-11, 2^-9 .. 1; 1: 2^-11 .. 2^-1 */
   double prune_rel;         /* keep S >= prune_rel * max S; 0 keeps all */
   double R;                 /* region multiple of the level step */
-  int32_t stencil;          /* interpolation points between levels: 3 (default, 0 = 3) or 5 */
+  int32_t stencil;          /* interpolation points between levels: 3 (default, 0 = 3), 4 or 5 */
 } orc_request;
 
 typedef struct {
@@ -73,6 +73,10 @@ double orc_voigt_K(double x, double y);
 /* element-wise K over n points */
 int orc_voigt_K_vec(int64_t n, const double* x, const double* y, double* out);
 double orc_chi(int32_t chi, double absd);
+/* coarse nodes k[] and weights w[] (up to 5 each) of the interpolation of
+ * level-l node m from level l + 1 under rq's level table and stencil;
+ * returns their number, or -1 */
+int orc_stencil_of(const orc_request* rq, int32_t l, int64_t m, int64_t* k, double* w);
 /* break points of the user chi (ascending, cm^-1) into out[cap]; their number, or -1 */
 int orc_user_chi_breaks(double* out, int cap);
 /* normalised line shape F(d) [cm], d = nu - nu~0 */

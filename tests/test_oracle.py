@@ -531,6 +531,72 @@ def test_grid_5point_exact_on_a_line_pair_symmetric():
     assert np.allclose(g, g[::-1], rtol=5e-5, atol=0)
 
 
+# ------------------------------------------------- 4-point midpoint rule
+
+def test_4point_stencil_weights_closed_forms():
+    """The symmetric 4-point rule: at a midpoint of a ratio-2 level the
+    weights are (-1, 9, 9, -1)/16 on the two coarse nodes on each side; at
+    quarter points of the ratio-4 step they are the cubic Lagrange weights
+    (-7, 105, 35, -5)/128 and their mirror image."""
+    for m in (1, 7, 1023, -5):
+        k, w = O.stencil_of(2, m, stencil=4, level_table=1)
+        q = (m - 1) // 2
+        assert list(k) == [q - 1, q, q + 1, q + 2]
+        assert np.array_equal(w, np.array([-1, 9, 9, -1]) / 16.0)
+    k, w = O.stencil_of(0, 9, stencil=4, level_table=0)   # u = 9/4
+    assert list(k) == [1, 2, 3, 4] and np.array_equal(w, np.array([-7, 105, 35, -5]) / 128.0)
+    k, w = O.stencil_of(0, 11, stencil=4, level_table=0)  # u = 11/4
+    assert list(k) == [1, 2, 3, 4] and np.array_equal(w, np.array([-5, 35, 105, -7]) / 128.0)
+    k, w = O.stencil_of(3, 12, stencil=4, level_table=0)  # coinciding node: injection
+    assert list(k) == [6] and list(w) == [1.0]
+
+
+@pytest.mark.parametrize("stencil,order", [(3, 2), (4, 3), (5, 4)])
+def test_stencils_exact_on_polynomials_of_their_order(stencil, order):
+    """Lagrange interpolation through n nodes reproduces every polynomial of
+    degree n - 1 and no polynomial of degree n."""
+    rng = np.random.default_rng(5)
+    for lt, l in ((0, 0), (0, 4), (1, 2)):
+        rho = 4 if (lt == 0 and l == 0) else 2
+        for m in (5, 6, 7, 13):
+            k, w = O.stencil_of(l, m, stencil=stencil, level_table=lt)
+            if len(k) == 1:
+                continue
+            u = m / rho
+            c = rng.normal(size=order + 2)
+            p_exact = np.polynomial.Polynomial(c[:order + 1])
+            p_next = np.polynomial.Polynomial(c)
+            assert abs(np.dot(w, p_exact(k)) - p_exact(u)) < 1e-9 * np.abs(c).sum() * 10 ** order
+            assert abs(np.dot(w, p_next(k)) - p_next(u)) > 1e-6
+
+
+@pytest.mark.parametrize("case", [
+    dict(nu0=1005.0, gamma=0.075),
+    dict(nu0=1005.3, gamma=0.075, chi=1, c=125.0),
+    dict(nu0=1002.1234, gamma=0.3, c=4.0, chi=1),
+    dict(nu0=1007.7, gamma=0.09, p=10.0),
+    dict(nu0=1004.2, gamma=0.06, p=0.4, lt=1),
+])
+def test_grid_4point_matches_definition_one_line(case):
+    L, lay = _one_line(case["nu0"], case["gamma"], p=case.get("p", 1.0))
+    err = _grid_vs_direct(L, lay, nu_begin=1000.0, nu_end=1010.0, cutoff=case.get("c", 25.0),
+                          chi=case.get("chi", 0), level_table=case.get("lt", 0), R=24.0, stencil=4)
+    assert err < 1e-5, err
+
+
+def test_grid_4point_error_between_3_and_5_points():
+    # the smooth-part error falls like R^-4: R 12 -> 24 more than tenfold
+    L = synth.make_lines(100, 990.0, 1020.0, 13, shift=True)
+    lay = (0.1, 250.0, 0.1, 0.0)
+    kw = dict(nu_begin=1000.0, nu_end=1010.0, cutoff=25.0, chi=1)
+    e3 = _grid_vs_direct(L, lay, R=12.0, stencil=3, **kw)
+    e4 = _grid_vs_direct(L, lay, R=12.0, stencil=4, **kw)
+    e5 = _grid_vs_direct(L, lay, R=12.0, stencil=5, **kw)
+    e4b = _grid_vs_direct(L, lay, R=24.0, stencil=4, **kw)
+    assert e5 < e4 < e3 / 5, (e3, e4, e5)
+    assert e4b < e4 / 10, (e4, e4b)
+
+
 # ---------------------------------------------------------- user plug-ins
 # The oracle's compiled-in user line shape (the Thompson-Cox-Hastings
 # pseudo-Voigt) and user chi (a step to 0.95 at 2 cm^-1, then
