@@ -89,7 +89,7 @@ typedef struct {
  * level_table 0 (steps 2^-11, 2^-9, ..., 1 cm^-1) or 1 (2^-11, ..., 2^-1);
  * prune_rel in [0, 1): lines with S(T) < prune_rel * max_j S_j(T) are dropped
  * per layer (max over the whole list); fp64 = 1 runs the device path in double
- * precision (output then FP64); stencil 0, 3 or 5.  Zero-initialise reserved
+ * precision (output then FP64); stencil 0, 3, 4 or 5.  Zero-initialise reserved
  * fields. */
 typedef struct {
   double nu_begin, nu_end;
@@ -106,9 +106,13 @@ typedef struct {
   double R;
   int32_t level_table;
   int32_t fp64;
-  int32_t stencil;            /* interpolation points between levels, 3 (0 = 3) or 5
-                                 (Section 2.4 names both; 5 points lower the
-                                 interpolation error tens of times at equal R) */
+  int32_t stencil;            /* interpolation points between levels: 3 (0 = 3) or 5,
+                                 centred on the nearest coarse node (Section 2.4
+                                 names both; 5 points lower the interpolation error
+                                 tens of times at equal R), or 4, the symmetric rule
+                                 on the two coarse nodes on each side ((-1, 9, 9, -1)/16
+                                 at a midpoint), between them in error and cost.  The
+                                 learned shape runs with 3 or 5 points. */
   int32_t reserved[3];
 } marfa_request;
 
@@ -144,7 +148,7 @@ typedef struct {
   double flops_level;             /* counted flops of the level kernel, all layers */
   double flops_cascade;           /* counted flops of the cascade, all layers */
   double bytes_level;             /* algorithmic bytes of the level kernel: records read, level and output nodes written */
-  double bytes_cascade;           /* algorithmic bytes of the cascade: 3 (5) coarse reads and 1 read-modify-write per node */
+  double bytes_cascade;           /* algorithmic bytes of the cascade: 3 (4, 5) coarse reads and 1 read-modify-write per node */
 } marfa_stats;
 
 /* Create a plan: validates and copies the inputs, sorts lines by nu0, uploads

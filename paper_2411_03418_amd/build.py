@@ -13,9 +13,9 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SOURCES = ["csrc/marfa_kernels.hip", "csrc/marfa_level_f32.hip", "csrc/marfa_level_f32_count.hip",
-           "csrc/marfa_level_f32_surr.hip", "csrc/marfa_level_f32_user.hip", "csrc/marfa_level_f64.hip",
-           "csrc/marfa_level_f64_count.hip", "csrc/marfa_level_f64_user.hip",
-           "csrc/marfa_plan.hip", "csrc/marfa_surrogate.hip", "csrc/marfa_io.hip"]
+           "csrc/marfa_level_f32_surr.hip", "csrc/marfa_level_f32_user.hip", "csrc/marfa_level_f32_s4.hip",
+           "csrc/marfa_level_f64.hip", "csrc/marfa_level_f64_count.hip", "csrc/marfa_level_f64_user.hip",
+           "csrc/marfa_level_f64_s4.hip", "csrc/marfa_plan.hip", "csrc/marfa_surrogate.hip", "csrc/marfa_io.hip"]
 OUT = os.path.join(HERE, "libmarfa.so")
 OBJDIR = os.path.join(HERE, "_build")
 

@@ -225,5 +225,16 @@ __host__ __device__ __forceinline__ constexpr double lagrange_w(int i, double t)
     if (j != i) v *= (t - j);
   return v * (1.0 / lagrange_den<H>(i));
 }
+// Weight of node i (-1 .. 2) at t for the symmetric 4-point rule on the nodes
+// -1, 0, 1, 2 (at t = 1/2: (-1, 9, 9, -1)/16)
+__host__ __device__ __forceinline__ constexpr double lagrange_w4(int i, double t) {
+  double v = 1.0, den = 1.0;
+  for (int j = -1; j <= 2; ++j)
+    if (j != i) {
+      v *= (t - j);
+      den *= (double)(i - j);
+    }
+  return v / den;
+}
 
 }  // namespace marfa

@@ -36,12 +36,13 @@ constexpr int kTaylorQuads = 5;
 //        complex Horner steps (56), the last real step (4), the scale (1) -- 69
 //  term  one more series term: the coefficient (2), U's recurrence (2), the
 //        sum (2) -- 6
-//  band  one residual-band correction: the 3-point (5-point) interpolation
-//        (6, 10), the difference (1), the sum into the node (1) -- 8 (12)
-//  cascade  one interpolated node: 3 (5) weights times values (6, 10), the
-//        sum into the finer level (1) -- 7 (11)
+//  band  one residual-band correction: the 3-point (4-, 5-point) interpolation
+//        (6, 8, 10), the difference (1), the sum into the node (1) -- 8 (10, 12)
+//  cascade  one interpolated node: 3 (4, 5) weights times values (6, 8, 10),
+//        the sum into the finer level (1) -- 7 (9, 11)
 constexpr int kFlopsEval = 17, kFlopsCore = 69, kFlopsTerm = 6;
-constexpr int kFlopsBand3 = 8, kFlopsBand5 = 12, kFlopsCascade3 = 7, kFlopsCascade5 = 11;
+constexpr int kFlopsBand3 = 8, kFlopsBand4 = 10, kFlopsBand5 = 12;
+constexpr int kFlopsCascade3 = 7, kFlopsCascade4 = 9, kFlopsCascade5 = 11;
 
 // Coefficient tables of a device, computed on the host at first use of the
 // device and kept until the process ends.

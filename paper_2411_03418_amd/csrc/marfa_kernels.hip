@@ -21,7 +21,7 @@
 //   k_level           persistent work queue over (layer, level, node tile):
 //                     each lane owns one level node and sums the contributions
 //                     of the lines in its windows (wave-uniform line loads)
-//   k_cascade         3-point interpolation from level l+1 into level l;
+//   k_cascade         3-, 4- or 5-point interpolation from level l+1 into level l;
 //                     the level-0 pass applies the layer scale and writes out.
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -297,6 +297,12 @@ __global__ void k_cascade(Geometry G, int l, R* A, R* out, int64_t stride, const
   R v;
   if (rem == 0) {
     v = Ac[q];
+  } else if (G.ns == 4) {
+    // the two coarse nodes on each side, q - 1 .. q + 2
+    const double f = (double)rem / (double)rho;
+    v = R(0);
+#pragma unroll
+    for (int k = -1; k <= 2; ++k) v += R(lagrange_w4(k, f)) * Ac[q + k];
   } else {
     double f = (double)rem / (double)rho, t;
     int64_t kc;
@@ -437,19 +443,26 @@ void launch_level_f64(const Geometry& G, const LevelArgs& a, int grid, hipStream
 void launch_level_f64_count(const Geometry& G, const LevelArgs& a, int grid, hipStream_t s);
 void launch_level_f32_user(const Geometry& G, const LevelArgs& a, int grid, hipStream_t s);
 void launch_level_f64_user(const Geometry& G, const LevelArgs& a, int grid, hipStream_t s);
+void launch_level_f32_s4(const Geometry& G, const LevelArgs& a, int grid, hipStream_t s);
+void launch_level_f64_s4(const Geometry& G, const LevelArgs& a, int grid, hipStream_t s);
 
-// Plans with the user line shape or chi run the kernels built with them; the
-// pair-counting kernels never evaluate a shape's value.
+// Plans with the user line shape or chi run the kernels built with them (and
+// every stencil); 4-point plans run kernels built for that stencil alone; the
+// pair-counting kernels never evaluate a shape's value and hold every stencil.
+// The learned shape serves 3- and 5-point plans only.
 void launch_level(const Geometry& G, const LevelArgs& a, int grid, bool fp64, bool count, hipStream_t s) {
   const bool user = G.shape == MARFA_SHAPE_USER || G.chi == MARFA_CHI_USER;
+  const bool four = G.ns == 4;
   if (fp64) {
     if (count) launch_level_f64_count(G, a, grid, s);
     else if (user) launch_level_f64_user(G, a, grid, s);
+    else if (four) launch_level_f64_s4(G, a, grid, s);
     else launch_level_f64(G, a, grid, s);
   } else {
     if (count) launch_level_f32_count(G, a, grid, s);
     else if (a.surr) launch_level_f32_surr(G, a, grid, s);
     else if (user) launch_level_f32_user(G, a, grid, s);
+    else if (four) launch_level_f32_s4(G, a, grid, s);
     else launch_level_f32(G, a, grid, s);
   }
 }

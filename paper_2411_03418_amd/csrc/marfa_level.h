@@ -594,8 +594,9 @@ __device__ __forceinline__ int64_t bucket_of(double nu, const Geometry& G) {
 }
 
 // Stencil of level-l node m on level l+1 (positions in fine units): G.ns
-// coarse nodes centred on the nearest one (a tie goes to the lower); one
-// node where m coincides with a coarse node
+// coarse nodes centred on the nearest one (a tie goes to the lower) for 3
+// and 5 points, the two on each side for 4 points; one node where m
+// coincides with a coarse node
 template <typename R>
 __device__ __forceinline__ int stencil_of(const Geometry& G, int l, int64_t m, int32_t* Xs, R* ws) {
   const int64_t rl = G.r[l];
@@ -605,6 +606,15 @@ __device__ __forceinline__ int stencil_of(const Geometry& G, int l, int64_t m, i
   const int64_t r1 = G.r[l + 1];
   // at rem == 0 the stencil at t = 0 has weights (.., 0, 1, 0, ..) exactly
   const double f = (double)rem / (double)rho;
+  if (G.ns == 4) {
+    // the two coarse nodes on each side: q - 1 .. q + 2 at t = f
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+      Xs[i] = (int32_t)((q - 1 + (i < 4 ? i : 3)) * r1);
+      ws[i] = R(i < 4 ? lagrange_w4(i - 1, f) : 0.0);
+    }
+    return rem == 0 ? 1 : 4;
+  }
   double tt;
   int64_t kc;
   if (f <= 0.5) { kc = q; tt = f; } else { kc = q + 1; tt = f - 1.0; }
@@ -861,7 +871,26 @@ __device__ __forceinline__ R seg_sum(R v, const SegSum& g) {
 }
 
 // One chunk of 64 lines of the line-major band pass for one jump and side:
-// NC candidate centres from kc0 with NSP-point stencils (see band_lines).
+// Layout of an NSP-point stencil on level l+1 for the RHO - 1 level-l nodes
+// between coarse nodes: offsets -kLeft .. kRight from the stencil's base
+// node -- the nearest coarse node for 3 and 5 points, the one below for the
+// symmetric 4-point rule -- and the level-l offsets jj (kJlo .. kJhi, jj = 0
+// coinciding) that the base serves.
+template <int NSP, int RHO>
+struct StencilShape {
+  static constexpr bool kCentred = NSP != 4;
+  static constexpr int kLeft = kCentred ? NSP / 2 : 1;
+  static constexpr int kRight = kCentred ? NSP / 2 : 2;
+  static constexpr int kJlo = kCentred ? -RHO / 2 + 1 : 1;
+  static constexpr int kJhi = kCentred ? RHO / 2 : RHO - 1;
+  // weight of stencil point i (0 .. NSP-1) for level-l offset jj
+  static constexpr double weight(int i, int jj) {
+    return kCentred ? lagrange_w<NSP / 2>(i - NSP / 2, (double)jj / (double)RHO)
+                    : lagrange_w4(i - 1, (double)jj / (double)RHO);
+  }
+};
+
+// NC candidate base nodes from kc0 with NSP-point stencils (see band_lines).
 template <typename R, bool COUNT, int RHO, bool SURR, int NSP, int NC>
 __device__ __forceinline__ void band_chunk(const typename RecOf<R>::T& L, int32_t jl, int ls, int cls, bool ok,
                                            int64_t kc0, int side, R rq, bool iso, const IntervalSet* iv,
@@ -870,18 +899,20 @@ __device__ __forceinline__ void band_chunk(const typename RecOf<R>::T& L, int32_
                                            const R* __restrict__ sp, const Geometry& G, const LevelArgs& a,
                                            R* lds_acc, Counts& cnt, uint32_t& n_used, uint32_t& n_band) {
   const int lane = threadIdx.x & 63;
-  constexpr int H = NSP / 2;
-  // T_(l+1) at level-(l+1) nodes kc0-H .. kc0+NC-1+H
-  R dd[NC + 2 * H], T1[NC + 2 * H];
+  using SS = StencilShape<NSP, RHO>;
+  constexpr int H = SS::kLeft;   // first stencil node: kc0 - H
+  constexpr int NT = NC + NSP - 1;
+  // T_(l+1) at level-(l+1) nodes kc0-H .. kc0+NC-1+kRight
+  R dd[NT], T1[NT];
   if constexpr (SURR && !COUNT) {
     // learned shape: the stencil values through the wave's queue; a queued
     // slot holds its queue position (bit i of qmask) until the batch returns
-    static_assert(NC + 2 * H <= kSurrSlots, "one queue session holds the stencil values");
+    static_assert(NT <= kSurrSlots, "one queue session holds the stencil values");
     uint32_t qmask = 0;
     int n = 0;
     const float amp = L.A * 1.7724538509055160f * L.xs * L.xs;
 #pragma unroll
-    for (int i = 0; i < NC + 2 * H; ++i) {
+    for (int i = 0; i < NT; ++i) {
       dd[i] = float((int32_t)((kc0 - H + i) * r1) - L.k0) - L.frac;
       const float adi = fabsf(dd[i]);
       const bool act = ok && adi <= cfine && !(l + 1 > ls && adi < b_cur);
@@ -898,12 +929,12 @@ __device__ __forceinline__ void band_chunk(const typename RecOf<R>::T& L, int32_
     }
     if (n > 0) surr_batch(a.sq, n, a);
 #pragma unroll
-    for (int i = 0; i < NC + 2 * H; ++i)
+    for (int i = 0; i < NT; ++i)
       if ((qmask >> i) & 1u) T1[i] = amp * a.sq[__float_as_int(T1[i])];
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   } else {
 #pragma unroll
-    for (int i = 0; i < NC + 2 * H; ++i) {
+    for (int i = 0; i < NT; ++i) {
       dd[i] = R((int32_t)((kc0 - H + i) * r1) - L.k0) - R(L.frac);
       const R adi = fabs(dd[i]);
       const bool act = ok && adi <= cfine && !(l + 1 > ls && adi < b_cur);
@@ -921,7 +952,7 @@ __device__ __forceinline__ void band_chunk(const typename RecOf<R>::T& L, int32_
   bool strad_c[NC];
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
-    const R d0 = dd[c], d2 = dd[c + 2 * H];
+    const R d0 = dd[c], d2 = dd[c + NSP - 1];
     const R lo = (d0 * d2 <= R(0)) ? R(0) : fmin(fabs(d0), fabs(d2));
     const R hi = fmax(fabs(d0), fabs(d2));
     if (iso) {
@@ -955,15 +986,15 @@ __device__ __forceinline__ void band_chunk(const typename RecOf<R>::T& L, int32_
     // learned shape: the line's own values at the candidate nodes through the
     // queue (queued slots hold their position, bit c RHO + ji of qmask)
     static_assert(NC * RHO <= 32, "one mask bit per candidate node");
-    static_assert(NC * (RHO - 1) <= kSurrSlots, "one queue session holds the candidate nodes");
+    static_assert(NC * (SS::kJhi - SS::kJlo) <= kSurrSlots, "one queue session holds the candidate nodes");
     uint32_t qmask = 0;
     int n = 0;
     const float amp = L.A * 1.7724538509055160f * L.xs * L.xs;
 #pragma unroll
     for (int c = 0; c < NC; ++c)
 #pragma unroll
-      for (int jj = -RHO / 2 + 1; jj <= RHO / 2; ++jj) {
-        const int ji = jj + RHO / 2 - 1;
+      for (int jj = SS::kJlo; jj <= SS::kJhi; ++jj) {
+        const int ji = jj - SS::kJlo;
         glv[c][ji] = 0.0f;
         if (jj == 0) continue;
         R d;
@@ -990,7 +1021,7 @@ __device__ __forceinline__ void band_chunk(const typename RecOf<R>::T& L, int32_
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
 #pragma unroll
-    for (int jj = -RHO / 2 + 1; jj <= RHO / 2; ++jj) {
+    for (int jj = SS::kJlo; jj <= SS::kJhi; ++jj) {
       if (jj == 0) continue;
       const int64_t m = (kc0 + c) * RHO + jj;
       R d;
@@ -998,15 +1029,14 @@ __device__ __forceinline__ void band_chunk(const typename RecOf<R>::T& L, int32_
       node(c, jj, d, use, need, in_reg, own);
       R gl = R(0);
       if constexpr (SURR && !COUNT) {
-        gl = glv[c][jj + RHO / 2 - 1];
+        gl = glv[c][jj - SS::kJlo];
       } else {
         (void)glv;
         if (need) gl = g_band<R, COUNT, SURR>(d, L, sp, jl, G, cfine, need, cnt, a, chi_mode, cc0, cc1);
       }
-      const double tt = (double)jj / (double)RHO;
       R interp = R(0);
 #pragma unroll
-      for (int i = 0; i < NSP; ++i) interp += R(lagrange_w<H>(i - H, tt)) * T1[c + i];
+      for (int i = 0; i < NSP; ++i) interp += R(SS::weight(i, jj)) * T1[c + i];
       const R v0 = (need ? gl : R(0)) - interp;
       R v = use ? v0 : R(0);
       if (merge) v = seg_sum<R>(v, seg);
@@ -1079,24 +1109,31 @@ __device__ __forceinline__ void band_lines(const Geometry& G, const LevelArgs& a
         // 2H centres from floor(P/r1) - H + 1; otherwise 2H + 1, from
         // floor(P/r1 + eps) - H.  The wavefront takes the wider set when any
         // of its used lanes needs it.
-        constexpr int H = NSP / 2;
+        // (4 points: base nodes k with [k - 1, k + 2] holding P / r1, i.e. the
+        // kLeft + kRight = 3 bases from floor(P / r1) - 1, or 4 from
+        // floor(P / r1 + eps) - 2.)
+        constexpr int KL = StencilShape<NSP, RHO>::kLeft, KR = StencilShape<NSP, RHO>::kRight;
         const double Pr = P * inv_r1;
         const double fl = floor(Pr);
         const bool edge = (Pr - fl) < eps || (Pr - fl) > 1.0 - eps;
         if (__builtin_amdgcn_ballot_w64(ok && edge))
-          band_chunk<R, COUNT, RHO, SURR, NSP, 2 * H + 1>(L, jl, ls, cls, ok, (int64_t)floor(Pr + eps) - H, side, rq,
-                                                          iso, iv, chi_mode, cc0, cc1, l, rl, r1, cfine, b_prev,
-                                                          b_cur, m_a, m_b, base, sp, G, a, lds_acc, cnt, n_used,
-                                                          n_band);
+          band_chunk<R, COUNT, RHO, SURR, NSP, KL + KR + 1>(L, jl, ls, cls, ok, (int64_t)floor(Pr + eps) - KR, side,
+                                                            rq, iso, iv, chi_mode, cc0, cc1, l, rl, r1, cfine, b_prev,
+                                                            b_cur, m_a, m_b, base, sp, G, a, lds_acc, cnt, n_used,
+                                                            n_band);
         else
-          band_chunk<R, COUNT, RHO, SURR, NSP, 2 * H>(L, jl, ls, cls, ok, (int64_t)fl - H + 1, side, rq, iso, iv,
-                                                      chi_mode, cc0, cc1, l, rl, r1, cfine, b_prev, b_cur, m_a, m_b,
-                                                      base, sp, G, a, lds_acc, cnt, n_used, n_band);
+          band_chunk<R, COUNT, RHO, SURR, NSP, KL + KR>(L, jl, ls, cls, ok, (int64_t)fl - KR + 1, side, rq, iso, iv,
+                                                        chi_mode, cc0, cc1, l, rl, r1, cfine, b_prev, b_cur, m_a, m_b,
+                                                        base, sp, G, a, lds_acc, cnt, n_used, n_band);
         if (COUNT && lane == 0) cnt.band_iters++;
       }
     }
   }
 }
+
+#ifndef MARFA_STENCILS
+#define MARFA_STENCILS 7
+#endif
 
 // Persistent work queue: each workgroup takes items (consecutive nodes of one
 // level of one layer, heaviest levels first).  Its four wavefronts split the
@@ -1180,12 +1217,19 @@ __device__ __forceinline__ void level_body(const Geometry& G, const LevelArgs& a
         const int own_lo = (int)(((int64_t)count * wv) >> 2);
         const int own_hi = (int)(((int64_t)count * (wv + 1)) >> 2);
         const bool two = G.r[l + 1] == 2 * G.r[l];
-        if (G.ns == 5) {
+        // the stencils this kernel is built with (MARFA_STENCILS: bit 0 the
+        // 3-point, bit 1 the 4-point, bit 2 the 5-point rule)
+        if ((MARFA_STENCILS & 4) && G.ns == 5) {
           if (two)
             band_lines<R, COUNT, 2, SURR, 5>(G, a, l, layer, first, own_lo, own_hi, iv, lds_acc, cnt, n_used, n_band);
           else
             band_lines<R, COUNT, 4, SURR, 5>(G, a, l, layer, first, own_lo, own_hi, iv, lds_acc, cnt, n_used, n_band);
-        } else {
+        } else if ((MARFA_STENCILS & 2) && G.ns == 4) {
+          if (two)
+            band_lines<R, COUNT, 2, SURR, 4>(G, a, l, layer, first, own_lo, own_hi, iv, lds_acc, cnt, n_used, n_band);
+          else
+            band_lines<R, COUNT, 4, SURR, 4>(G, a, l, layer, first, own_lo, own_hi, iv, lds_acc, cnt, n_used, n_band);
+        } else if (MARFA_STENCILS & 1) {
           if (two)
             band_lines<R, COUNT, 2, SURR, 3>(G, a, l, layer, first, own_lo, own_hi, iv, lds_acc, cnt, n_used, n_band);
           else

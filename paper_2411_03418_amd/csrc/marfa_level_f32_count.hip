@@ -1,5 +1,6 @@
-// marfa_level_f32_count.hip -- the level kernel <float, true, false> without the user line shape and chi, and its launcher.
+// marfa_level_f32_count.hip -- the level kernel <float, true, false> without the user line shape and chi, every stencil, and its launcher.
 #define MARFA_USER_PLUGINS 0
+#define MARFA_STENCILS 7
 #include "marfa_level.h"
 
 MARFA_LEVEL_LAUNCHER(f32_count, float, true, false, 1)

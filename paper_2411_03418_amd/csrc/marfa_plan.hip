@@ -220,8 +220,8 @@ static int64_t fdiv(int64_t a, int64_t b) {
 static int default_lnw(int l) { return l == 0 ? 6 : 4; }
 
 static void make_geometry(const marfa_request& rq, double nu_max, Geometry& G) {
-  G.ns = rq.stencil == 5 ? 5 : 3;
-  const int half = G.ns / 2;
+  G.ns = rq.stencil == 0 ? 3 : rq.stencil;
+  const int half = G.ns / 2;   // coarse nodes a stencil reaches beyond its interval: 1, 2, 2
   for (int l = 0; l < kLevels; ++l) {
     if (rq.level_table == 1) G.r[l] = 1 << l;
     else G.r[l] = l == 0 ? 1 : (1 << (l + 1));
@@ -534,7 +534,8 @@ static marfa_status validate(const marfa_lines* L, const marfa_layer* lay, int32
   if (rq->out_kind < 0 || rq->out_kind > 1) return fail(MARFA_E_INVALID, "out_kind");
   if (rq->eval < 0 || rq->eval > 1) return fail(MARFA_E_INVALID, "eval");
   if (rq->level_table < 0 || rq->level_table > 1) return fail(MARFA_E_INVALID, "level_table");
-  if (rq->stencil != 0 && rq->stencil != 3 && rq->stencil != 5) return fail(MARFA_E_INVALID, "stencil must be 3 or 5");
+  if (rq->stencil != 0 && rq->stencil != 3 && rq->stencil != 4 && rq->stencil != 5)
+    return fail(MARFA_E_INVALID, "stencil must be 3, 4 or 5");
   if (rq->fp64 < 0 || rq->fp64 > 1) return fail(MARFA_E_INVALID, "fp64");
   if (!(rq->prune_rel >= 0.0) || !(rq->prune_rel < 1.0)) return fail(MARFA_E_INVALID, "prune_rel in [0,1)");
   return MARFA_OK;
@@ -954,8 +955,9 @@ extern "C" marfa_status marfa_plan_count(marfa_plan* p, marfa_stats* out) {
   out->flops_per_eval = kFlopsEval;
   out->flops_per_core = kFlopsCore;
   out->flops_per_term = kFlopsTerm;
-  out->flops_per_band = five ? kFlopsBand5 : kFlopsBand3;
-  out->flops_per_cascade = five ? kFlopsCascade5 : kFlopsCascade3;
+  const bool four = p->G.ns == 4;
+  out->flops_per_band = five ? kFlopsBand5 : (four ? kFlopsBand4 : kFlopsBand3);
+  out->flops_per_cascade = five ? kFlopsCascade5 : (four ? kFlopsCascade4 : kFlopsCascade3);
   out->flops_level = out->flops_per_eval * (double)(out->pairs_wing + out->pairs_core) +
                      out->flops_per_core * (double)out->pairs_core + out->flops_per_term * (double)out->wing_terms +
                      out->flops_per_band * (double)out->pairs_band;
@@ -970,7 +972,7 @@ extern "C" marfa_status marfa_plan_count(marfa_plan* p, marfa_stats* out) {
   const double real_b = p->req.fp64 ? 8.0 : 4.0;
   const double rec_b = p->req.fp64 ? (double)sizeof(LineRec64) : (double)sizeof(LineRec32);
   out->bytes_level = rec_b * (double)kept + real_b * (double)(out->level_nodes + out->points_per_layer * p->n_layers);
-  out->bytes_cascade = real_b * (double)(out->level_nodes + out->points_per_layer * p->n_layers) * (five ? 7.0 : 5.0);
+  out->bytes_cascade = real_b * (double)(out->level_nodes + out->points_per_layer * p->n_layers) * (double)(p->G.ns + 2);
   return MARFA_OK;
 }
 
@@ -1154,6 +1156,7 @@ extern "C" marfa_status marfa_plan_set_surrogate(marfa_plan* p, const marfa_surr
   if (dev != p->device) return fail(MARFA_E_INVALID, "surrogate on device %d, plan on %d", dev, p->device);
   if (p->req.fp64 || p->req.shape != MARFA_SHAPE_VOIGT)
     return fail(MARFA_E_INVALID, "the surrogate serves single-precision Voigt plans");
+  if (p->G.ns == 4) return fail(MARFA_E_UNSUPPORTED, "the learned shape runs with 3- or 5-point plans");
   if (chi != p->req.chi || cutoff != p->req.cutoff)
     return fail(MARFA_E_INVALID, "surrogate trained for chi %d, cut-off %g; plan has chi %d, cut-off %g", chi, cutoff,
                 p->req.chi, p->req.cutoff);

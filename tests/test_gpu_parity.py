@@ -270,14 +270,14 @@ def test_multi_layer_pruned_ragged():
 
 
 @pytest.mark.parametrize("fp64", [False, True])
-@pytest.mark.parametrize("stencil", [3, 5])
+@pytest.mark.parametrize("stencil", [3, 4, 5])
 def test_user_plugins_many_lines(fp64, stencil):
     # the compiled-in user shape and chi through every level, both band
     # passes and the learned-shape-free generic pair path, on several layers
     lines = synth.make_lines(2000, 940.0, 1080.0, 41, shift=True)
     layers = synth.pt_table(7)[[0, 3, 6]]
     req = dict(nu_begin=1000.0, nu_end=1012.0, cutoff=60.0, chi="user", shape="user", prune=1e-6,
-               stencil=stencil, R=48 if stencil == 3 else 12)
+               stencil=stencil, R={3: 48, 4: 24, 5: 12}[stencil])
     got = run(lines, layers, fp64=fp64, **req)
     o = _oreq(req)
     for i in range(layers.shape[0]):
@@ -464,6 +464,82 @@ def test_autotune_keeps_parity_5pt():
         ref_g = O.grid(lines, layers[i], threads=THREADS, **o)
         eg = rel_err(got[i], ref_g)
         print(f"5-point tuned {tiles['wave_nodes']} layer {i}: vs grid {eg:.2e}")
+        grid_check(got[i], ref_g, lines, layers[i], req, False)
+
+
+# ------------------------------------------------------ 4-point midpoint rule
+
+# the symmetric rule on the two coarse nodes on each side; its error falls
+# like R^-4, so R = 24 keeps single lines within 1e-5 of the definition
+FOUR = dict(stencil=4, R=24)
+
+
+@pytest.mark.parametrize("case", ONE_LINE)
+@pytest.mark.parametrize("fp64", [False, True])
+def test_one_line_parity_4pt(case, fp64):
+    L, lay = _one(case["nu0"], case["gamma"], p=case.get("p", 1.0), T=case.get("T", 296.0))
+    req = dict(nu_begin=case.get("nb", 1000.0), nu_end=case.get("ne", 1010.0), cutoff=case.get("c", 25.0),
+               chi=case.get("chi", "none"), shape=case.get("shape", "voigt"), level_table=case.get("lt", 0), **FOUR)
+    got = run(L, [lay], fp64=fp64, **req)[0]
+    o = _oreq(req)
+    ref_g = O.grid(L, lay, threads=THREADS, **o)
+    ref_d = O.direct(L, lay, all_nodes(req), threads=THREADS, **o)
+    eg, ed = rel_err(got, ref_g), rel_err(got, ref_d)
+    print(f"4-point: vs grid {eg:.2e}  vs direct {ed:.2e}")
+    assert ed < 1e-4
+    grid_check(got, ref_g, L, lay, req, fp64)
+
+
+@pytest.mark.parametrize("fp64", [False, True])
+def test_multi_layer_4pt(fp64):
+    lines = synth.make_lines(3000, 930.0, 1090.0, 31, shift=True)
+    layers = synth.pt_table(5)
+    req = dict(nu_begin=1000.0, nu_end=1013.5, cutoff=60.0, chi="tonkov", prune=1e-6, **FOUR)
+    got = run(lines, layers, fp64=fp64, **req)
+    o = _oreq(req)
+    for i in range(layers.shape[0]):
+        ref_g = O.grid(lines, layers[i], threads=THREADS, **o)
+        ref_d = O.direct(lines, layers[i], all_nodes(req), threads=THREADS, **o)
+        eg, ed = rel_err(got[i], ref_g), rel_err(got[i], ref_d)
+        print(f"4-point layer {i} fp64={fp64}: vs grid {eg:.2e} vs direct {ed:.2e}")
+        assert ed < 1e-4
+        grid_check(got[i], ref_g, lines, layers[i], req, fp64)
+
+
+@pytest.mark.parametrize("fp64", [False, True])
+def test_small_cutoff_node_major_band_4pt(fp64):
+    lines = synth.make_lines(500, 995.0, 1015.0, 35, shift=True)
+    lay = [0.3, 260.0, 0.05, 0.0]
+    req = dict(nu_begin=1000.0, nu_end=1010.0, cutoff=1.5, **FOUR)
+    got = run(lines, [lay], fp64=fp64, **req)[0]
+    o = _oreq(req)
+    ref_d = O.direct(lines, lay, all_nodes(req), threads=THREADS, **o)
+    ref_g = O.grid(lines, lay, threads=THREADS, **o)
+    eg, ed = rel_err(got, ref_g), rel_err(got, ref_d)
+    print(f"4-point small cut-off fp64={fp64}: vs grid {eg:.2e} vs direct {ed:.2e}")
+    assert ed < 1e-4
+    grid_check(got, ref_g, lines, lay, req, fp64)
+
+
+def test_autotune_keeps_parity_4pt():
+    lines = synth.make_lines(3000, 930.0, 1090.0, 31, shift=True)
+    layers = synth.pt_table(3)
+    req = dict(nu_begin=1000.0, nu_end=1013.5, cutoff=60.0, chi="tonkov", prune=1e-6, **FOUR)
+    M = marfa()
+    plan = M.Plan(lines, layers, device=0, **req)
+    out = torch.empty((plan.n_layers, plan.points), dtype=torch.float32, device="cuda:0")
+    tiles = plan.tune(out=out)
+    st = plan.count()
+    got = plan.execute(out=out)
+    torch.cuda.synchronize()
+    got = got.double().cpu().numpy()
+    plan.close()
+    assert st["flops_per_band"] == 10 and st["pairs_band"] > 0
+    o = _oreq(req)
+    for i in range(layers.shape[0]):
+        ref_g = O.grid(lines, layers[i], threads=THREADS, **o)
+        eg = rel_err(got[i], ref_g)
+        print(f"4-point tuned {tiles['wave_nodes']} layer {i}: vs grid {eg:.2e}")
         grid_check(got[i], ref_g, lines, layers[i], req, False)
 
 

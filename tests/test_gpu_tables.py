@@ -7,8 +7,8 @@ layers spread over the table, the direct sum at 65,536 random output nodes,
 plus three whole 10 cm^-1 records (low, middle and high end of the spectrum)
 on three of the layers, and each layer's maximum of the direct sum.  The
 tolerance is relative on nodes whose direct sum is at least 1e-8 of that
-maximum: 1e-4 for the plain line shape (3-point scheme at R = 48 and the
-5-point scheme at R = 24), 1e-3 for the learned line shape.
+maximum: 1e-4 for the plain line shape (3-point scheme at R = 48, the 4- and
+5-point schemes at R = 24), 1e-3 for the learned line shape.
 """
 import os
 
@@ -101,6 +101,12 @@ def test_table_sampled_5pt_r24(refs):
     picks = refs("pt100_2m")
     got = _run_table("pt100_2m", picks, stencil=5, R=24)
     assert _compare(got, picks, "pt100_2m 5-point R=24") < 1e-4
+
+
+def test_table_sampled_4pt_r24(refs):
+    picks = refs("pt100_2m")
+    got = _run_table("pt100_2m", picks, stencil=4, R=24)
+    assert _compare(got, picks, "pt100_2m 4-point R=24") < 1e-4
 
 
 def test_region_edge_rounding_nodes():
