@@ -33,7 +33,7 @@ PEAK_BF16_MFMA_TFLOPS = 2500.0  # MI355X published dense BF16 matrix peak
 # 64->64 layers (2*64*64 each), 64->1 (2*64); the split-BF16 activations run
 # the hidden layers twice on the matrix cores, which is not counted here
 FLOP_MLP = 2 * 3 * 64 + 64 + 3 * 2 * 64 * 64 + 2 * 64
-STENCIL5_R = 24      # 5-point R with the cost of the 3-point R = 48 table and ~40x lower interpolation error
+STENCIL_R = {4: 24, 5: 24}   # R of the 4- and 5-point legs: about the 3-point R = 48 table's cost
 
 
 def profiled_traffic(workload):
@@ -143,11 +143,12 @@ def torch_isfinite_all(t):
     return torch.isfinite(t).all()
 
 
-def stencil5_leg(lines, layers, req, plain, steps):
-    """The same table with the 5-point interpolation stencil at a smaller R."""
+def stencil_leg(lines, layers, req, plain, steps, ns):
+    """The same table with the 4- or 5-point interpolation stencil at a smaller R."""
     import torch
     from paper_2411_03418_amd import marfa
-    plan = marfa.Plan(lines, layers, device=0, stencil=5, R=STENCIL5_R, **req)
+    R = STENCIL_R[ns]
+    plan = marfa.Plan(lines, layers, device=0, stencil=ns, R=R, **req)
     out = torch.empty((plan.n_layers, plan.points), dtype=torch.float32, device="cuda:0")
     tiles = plan.tune(out=out)
     st = plan.count()
@@ -158,13 +159,13 @@ def stencil5_leg(lines, layers, req, plain, steps):
         lv.append(t["level_ms"])
     dev = rel_dev(plain, out)
     points = plan.points * plan.n_layers
-    print(f"[bench] 5-point R={STENCIL5_R}: {ms:.1f} ms/step, level {np.mean(lv):.1f} ms; max dev from 3-point "
+    print(f"[bench] {ns}-point R={R}: {ms:.1f} ms/step, level {np.mean(lv):.1f} ms; max dev from 3-point "
           f"{dev:.2e}", file=sys.stderr, flush=True)
     plan.close()
     del out
     torch.cuda.empty_cache()
     return dict(value=points / (ms * 1e-3), unit="points/s", ms_per_step=ms, level_ms=float(np.mean(lv)),
-                steps=steps, stencil=5, R=STENCIL5_R, pairs=int(sum(st["pairs_level"])),
+                steps=steps, stencil=ns, R=R, pairs=int(sum(st["pairs_level"])),
                 band_pairs=int(st["pairs_band"]), max_rel_dev_from_3point=dev, tiles=tiles)
 
 
@@ -247,6 +248,7 @@ def main():
     ap.add_argument("--no-surrogate-table", action="store_true",
                     help="skip the learned shape on the benchmark's own table (one step)")
     ap.add_argument("--no-stencil5", action="store_true", help="skip the 5-point stencil leg")
+    ap.add_argument("--no-stencil4", action="store_true", help="skip the 4-point stencil leg")
     ap.add_argument("--surrogate-steps", type=int, default=2)
     ap.add_argument("--no-tune", action="store_true", help="keep the density-based tiles")
     ap.add_argument("--tiles", default=None, metavar="JSON",
@@ -308,9 +310,11 @@ def main():
         s_big = surrogate_table_leg(plan, out, lines, layers, chi, req["cutoff"], args.workload)
         s_big["speed_vs_plain"] = ms / s_big["ms_per_step"]
     plan.close()
-    s5 = None
+    s5 = s4 = None
     if not args.no_stencil5:
-        s5 = stencil5_leg(lines, layers, req, out, args.steps)
+        s5 = stencil_leg(lines, layers, req, out, args.steps, 5)
+    if not args.no_stencil4:
+        s4 = stencil_leg(lines, layers, req, out, args.steps, 4)
     del out
     torch.cuda.empty_cache()
 
@@ -350,6 +354,8 @@ def main():
     }
     if s5 is not None:
         line["stencil5"] = s5
+    if s4 is not None:
+        line["stencil4"] = s4
     if not args.no_surrogate:
         line["surrogate"] = surrogate_leg(args)
     if s_big is not None:
