@@ -112,7 +112,7 @@ typedef struct {
                                  tens of times at equal R), or 4, the symmetric rule
                                  on the two coarse nodes on each side ((-1, 9, 9, -1)/16
                                  at a midpoint), between them in error and cost.  The
-                                 learned shape runs with 3 or 5 points. */
+                                 learned shape runs with 3 points. */
   int32_t reserved[3];
 } marfa_request;
 
@@ -335,11 +335,14 @@ void marfa_surrogate_destroy(marfa_surrogate* s);
  * eval is MARFA_EVAL_SURROGATE evaluates its line shapes with it; pairs
  * outside the trained domain (y outside [1e-4, 1e3] or |x| above the
  * report's x_max) take the plain line shape.  Requires a single-precision
- * Voigt plan with the surrogate's chi and cut-off.  The surrogate must
- * outlive its use by the plan.  Waits for the device's queued work before
- * rebuilding the plan's graphs.  Errors: MARFA_E_INVALID (mismatch),
- * MARFA_E_UNSUPPORTED (untrained network, a cut-off under two coarsest
- * steps). */
+ * Voigt plan with the 3-point stencil and the surrogate's chi and cut-off.
+ * The learned-shape kernel runs on work items of its own (128 nodes, 2048
+ * on level 0, allocated here on first attach); marfa_plan_tune always tunes
+ * the plain kernel.  The surrogate must outlive its use by the plan.  Waits
+ * for the device's queued work before rebuilding the plan's graphs.
+ * Errors: MARFA_E_INVALID (mismatch), MARFA_E_UNSUPPORTED (untrained
+ * network, another stencil, a cut-off under two coarsest steps),
+ * MARFA_E_NOMEM. */
 marfa_status marfa_plan_set_surrogate(marfa_plan* plan, const marfa_surrogate* s);
 
 /* Switch the plan's line-shape evaluation (marfa_eval, as the request's

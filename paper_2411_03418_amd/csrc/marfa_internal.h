@@ -174,6 +174,7 @@ struct DeviceBuffers {
   void* A = nullptr;               // [n_layers][a_total] level arrays 1..10
   IntervalSet* ivs = nullptr;      // [11][8]
   Tile* tiles = nullptr;           // [n_tiles] heaviest first
+  Tile* stiles = nullptr;          // the learned shape's work items (smaller, so two workgroups fit a CU's LDS)
   unsigned int* counter = nullptr; // work-queue counter
   double* scale = nullptr;         // [n_layers] output scale
   double* span = nullptr;          // [n_layers] max |(delta_i - delta_j) p| [cm^-1]

@@ -240,8 +240,10 @@ __device__ float g_surr(float d, const LineRec32& L, const float* __restrict__ s
 // |x|, y and |d| in cm; the batch overwrites |x| with Kb(x, y) e^t / y, and
 // the lane scales it by its line's S' sqrt(pi) xs^2 (= A sqrt(pi) xs^2 with
 // A = S' gamma_L / pi).  A session pushes at most kSurrSlots pairs per lane
-// (the band pass's candidate nodes), so the queue never overflows.
-constexpr int kSurrSlots = 15;
+// (with the 3-point stencil, the only one the learned shape runs with: up to
+// three candidate bases times three nodes on the ratio-4 level), so the queue
+// never overflows.
+constexpr int kSurrSlots = 9;
 constexpr int kSurrQueue = 64 * kSurrSlots;   // entries per wavefront: three arrays of this many floats
 
 // Push `want` pairs of the calling lanes; returns the slot of each, `n` the
@@ -1219,22 +1221,34 @@ __device__ __forceinline__ void level_body(const Geometry& G, const LevelArgs& a
         const bool two = G.r[l + 1] == 2 * G.r[l];
         // the stencils this kernel is built with (MARFA_STENCILS: bit 0 the
         // 3-point, bit 1 the 4-point, bit 2 the 5-point rule)
-        if ((MARFA_STENCILS & 4) && G.ns == 5) {
-          if (two)
-            band_lines<R, COUNT, 2, SURR, 5>(G, a, l, layer, first, own_lo, own_hi, iv, lds_acc, cnt, n_used, n_band);
-          else
-            band_lines<R, COUNT, 4, SURR, 5>(G, a, l, layer, first, own_lo, own_hi, iv, lds_acc, cnt, n_used, n_band);
-        } else if ((MARFA_STENCILS & 2) && G.ns == 4) {
-          if (two)
-            band_lines<R, COUNT, 2, SURR, 4>(G, a, l, layer, first, own_lo, own_hi, iv, lds_acc, cnt, n_used, n_band);
-          else
-            band_lines<R, COUNT, 4, SURR, 4>(G, a, l, layer, first, own_lo, own_hi, iv, lds_acc, cnt, n_used, n_band);
-        } else if (MARFA_STENCILS & 1) {
-          if (two)
-            band_lines<R, COUNT, 2, SURR, 3>(G, a, l, layer, first, own_lo, own_hi, iv, lds_acc, cnt, n_used, n_band);
-          else
-            band_lines<R, COUNT, 4, SURR, 3>(G, a, l, layer, first, own_lo, own_hi, iv, lds_acc, cnt, n_used, n_band);
+        bool done = false;
+        if constexpr ((MARFA_STENCILS & 4) != 0) {
+          if (G.ns == 5) {
+            if (two)
+              band_lines<R, COUNT, 2, SURR, 5>(G, a, l, layer, first, own_lo, own_hi, iv, lds_acc, cnt, n_used, n_band);
+            else
+              band_lines<R, COUNT, 4, SURR, 5>(G, a, l, layer, first, own_lo, own_hi, iv, lds_acc, cnt, n_used, n_band);
+            done = true;
+          }
         }
+        if constexpr ((MARFA_STENCILS & 2) != 0) {
+          if (!done && G.ns == 4) {
+            if (two)
+              band_lines<R, COUNT, 2, SURR, 4>(G, a, l, layer, first, own_lo, own_hi, iv, lds_acc, cnt, n_used, n_band);
+            else
+              band_lines<R, COUNT, 4, SURR, 4>(G, a, l, layer, first, own_lo, own_hi, iv, lds_acc, cnt, n_used, n_band);
+            done = true;
+          }
+        }
+        if constexpr ((MARFA_STENCILS & 1) != 0) {
+          if (!done) {
+            if (two)
+              band_lines<R, COUNT, 2, SURR, 3>(G, a, l, layer, first, own_lo, own_hi, iv, lds_acc, cnt, n_used, n_band);
+            else
+              band_lines<R, COUNT, 4, SURR, 3>(G, a, l, layer, first, own_lo, own_hi, iv, lds_acc, cnt, n_used, n_band);
+          }
+        }
+        (void)done;
       } else {
         const int ngroup = (count + 63) >> 6;
         for (int g = wv; g < ngroup; g += 4)

@@ -177,6 +177,7 @@ struct marfa_plan {
   Geometry G{};
   std::vector<IntervalSet> ivs;
   std::vector<Tile> tiles;
+  std::vector<Tile> stiles;   // work items of the learned-shape kernel
   std::vector<double> layers_h;
   std::vector<double> span_h;
   DeviceBuffers d;
@@ -469,6 +470,7 @@ static void choose_tiles(Geometry& G, double lines_per_cm) {
 
 // candidate work-item sizes of the autotuner (ascending)
 static const int kTuneItems[3] = {128, 256, 512};
+static const int kSurrItemNodes = 128;   // work-item size of the learned-shape kernel
 
 // Work items: nodes per item scale inversely with the per-node cost, which
 // grows with the level step (window width in lines); heaviest levels first.
@@ -562,7 +564,8 @@ static void free_plan(marfa_plan* p) {
   }
   void* bufs[] = {p->d.nu0, p->d.S296, p->d.gair, p->d.gself, p->d.El, p->d.nair, p->d.dair, p->d.layers,
                   p->d.smax, p->d.bcount, p->d.scount, p->d.kept, p->d.gcount, p->d.bucket, p->d.coarse, p->d.rec, p->d.cnu, p->d.csp,
-                  p->d.A, p->d.ivs, p->d.tiles, p->d.counter, p->d.scale, p->d.span, p->d.perm, p->d.stats};
+                  p->d.A, p->d.ivs, p->d.tiles, p->d.stiles, p->d.counter, p->d.scale, p->d.span, p->d.perm,
+                  p->d.stats};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   delete p;
@@ -760,9 +763,10 @@ struct TileSet {
   int max_item;
 };
 
-static TileSet plan_tiles(const marfa_plan* p) {
-  TileSet t{p->d.tiles, (int64_t)p->tiles.size(), 0};
-  for (const Tile& x : p->tiles) t.max_item = std::max(t.max_item, x.count);
+static TileSet plan_tiles(const marfa_plan* p, bool surr) {
+  const std::vector<Tile>& v = surr ? p->stiles : p->tiles;
+  TileSet t{surr ? p->d.stiles : p->d.tiles, (int64_t)v.size(), 0};
+  for (const Tile& x : v) t.max_item = std::max(t.max_item, x.count);
   return t;
 }
 
@@ -795,7 +799,8 @@ static void enqueue(marfa_plan* p, int first, int count, void* out, int64_t stri
   pa.fp64 = f64 ? 1 : 0;
   char* A = (char*)p->d.A + F * (size_t)p->G.a_total * realsz;
   if (stages & 1) launch_prep(in, p->d.layers + 4 * F, count, p->G, pa, s);
-  const TileSet tl = ts ? *ts : plan_tiles(p);
+  const bool surr = p->surr && p->req.eval == MARFA_EVAL_SURROGATE && !count_mode;
+  const TileSet tl = ts ? *ts : plan_tiles(p, surr);
   LevelArgs a;
   a.tiles = tl.dev;
   a.n_tiles = tl.n;
@@ -812,7 +817,7 @@ static void enqueue(marfa_plan* p, int first, int count, void* out, int64_t stri
   a.stride = stride;
   a.stats = p->d.stats;
   a.max_item = tl.max_item;
-  a.surr = (p->surr && p->req.eval == MARFA_EVAL_SURROGATE && !count_mode) ? 1 : 0;
+  a.surr = surr ? 1 : 0;
   a.mlp_xmax = p->mlp_xmax;
   a.mlp_inv_c = p->mlp_inv_c;
   a.mlp = p->mlp;
@@ -1068,6 +1073,14 @@ extern "C" marfa_status marfa_plan_tune(marfa_plan* p, void* out, int64_t stride
   hipStream_t s = (hipStream_t)stream;
   const auto t0 = std::chrono::steady_clock::now();
   drop_graphs(p);
+  // the tiles are the plain kernel's: tune it even while the learned shape is selected
+  const int32_t eval = p->req.eval;
+  p->req.eval = MARFA_EVAL_PLAIN;
+  struct Restore {
+    marfa_plan* p;
+    int32_t e;
+    ~Restore() { p->req.eval = e; }
+  } restore{p, eval};
   enqueue(p, 0, p->n_layers, out, stride, s, false, 1);   // line preparation
   HIP_TRY(hipGetLastError());
   // 1. region tile per level, items of the current size
@@ -1156,13 +1169,24 @@ extern "C" marfa_status marfa_plan_set_surrogate(marfa_plan* p, const marfa_surr
   if (dev != p->device) return fail(MARFA_E_INVALID, "surrogate on device %d, plan on %d", dev, p->device);
   if (p->req.fp64 || p->req.shape != MARFA_SHAPE_VOIGT)
     return fail(MARFA_E_INVALID, "the surrogate serves single-precision Voigt plans");
-  if (p->G.ns == 4) return fail(MARFA_E_UNSUPPORTED, "the learned shape runs with 3- or 5-point plans");
+  if (p->G.ns != 3) return fail(MARFA_E_UNSUPPORTED, "the learned shape runs with 3-point plans");
   if (chi != p->req.chi || cutoff != p->req.cutoff)
     return fail(MARFA_E_INVALID, "surrogate trained for chi %d, cut-off %g; plan has chi %d, cut-off %g", chi, cutoff,
                 p->req.chi, p->req.cutoff);
   for (const IntervalSet& iv : p->ivs)
     if (iv.n_jump > 0 && !iv.lc_ok)
       return fail(MARFA_E_UNSUPPORTED, "cut-off too small for the line-major band pass the surrogate needs");
+  // its own work items: 128 nodes (2048 on level 0) keep the accumulators at
+  // 8 KB of LDS, so two workgroups fit a CU beside the staged network
+  if (p->stiles.empty()) {
+    std::vector<Tile> st;
+    make_tiles(p->G, st, kSurrItemNodes);
+    HIP_TRY(hipSetDevice(p->device));
+    marfa_status m = dmalloc(&p->d.stiles, st.size());
+    if (m != MARFA_OK) return m;
+    HIP_TRY(hipMemcpy(p->d.stiles, st.data(), st.size() * sizeof(Tile), hipMemcpyHostToDevice));
+    p->stiles = st;
+  }
   p->surr = s;
   p->mlp = W;
   p->mlp_xmax = (float)x_max;
