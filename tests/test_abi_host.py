@@ -55,6 +55,10 @@ def _plan(**kw):
     dict(layers=[[float("inf"), 296.0, 1.0, 0.0]]),
     dict(level_table=3),
     dict(shape=7),
+    dict(shape=4),
+    dict(chi=3),
+    dict(stencil=2),
+    dict(stencil=6),
 ])
 def test_invalid_requests(kw):
     with pytest.raises(marfa.MarfaError) as e:
@@ -72,6 +76,21 @@ def test_invalid_lines():
     lines.S296[0] = -1.0
     with pytest.raises(marfa.MarfaError):
         marfa.Plan(lines, [[1.0, 296.0, 1.0, 0.0]], nu_begin=1000.0, nu_end=1001.0, cutoff=25.0)
+
+
+def test_line_count_limit():
+    """Records are addressed by 32-bit byte offsets within a layer: 2^26 lines
+    or more are refused before any array is read."""
+    L = marfa.lib()
+    one = np.zeros(1, np.float64)
+    f = np.zeros(1, np.float32)
+    p = lambda a: a.ctypes.data_as(C.c_void_p)
+    lines = marfa.Lines(1 << 26, p(one), p(f), p(f), p(f), p(f), p(f), None, p(f), 44.0)
+    lay = (marfa.Layer * 1)(marfa.Layer(1.0, 296.0, 1.0, 0.0))
+    rq = marfa.Request(1000.0, 1001.0, 25.0, 0, 0, 0, 0, 0.0, 48.0, 0, 0, 3)
+    h = C.c_void_p()
+    assert L.marfa_plan_create(C.byref(h), C.byref(lines), lay, 1, C.byref(rq), 0) == marfa.E_INVALID
+    assert not h.value
 
 
 def test_voigt_eval_rejects_negative_y():
