@@ -177,8 +177,7 @@ def surrogate_table_leg(plan, out, lines, layers, chi, cutoff, workload):
     from paper_2411_03418_amd import marfa
     S = marfa.Surrogate(chi=chi, cutoff=cutoff, seed=1)
     nu = lines.nu0[lines.nu0 > 0]
-    # the 2M-line table's 0-10125 cm^-1 spans more Doppler widths: twice the samples
-    n_train = 20_000_000 if workload == "pt100_2m" else 10_000_000
+    n_train = 20_000_000
     rep = S.fit(nu_lo=float(nu.min()), nu_hi=float(nu.max()), T_lo=float(layers[:, 1].min()),
                 T_hi=float(layers[:, 1].max()), n_train=n_train)
     print(f"[bench] {workload} surrogate trained: {rep}", file=sys.stderr, flush=True)
@@ -234,7 +233,7 @@ def surrogate_leg(args):
                 steps=args.surrogate_steps, level_ms=t["level_ms"], plain_ms_per_step=ms_plain,
                 speed_vs_plain=ms_plain / ms_surr, max_rel_dev_from_plain=dev,
                 train=dict(ms=rep["ms"], steps=rep["steps"], val_max_abs_t=rep["val_max_abs"],
-                           val_mean_abs_t=rep["val_mean_abs"], samples=10_000_000,
+                           val_mean_abs_t=rep["val_mean_abs"], samples=20_000_000,
                            recipe="300 epochs mean-squared + 100 epochs fourth-power, batch 16384"),
                 mfma="v_mfma_f32_16x16x32_bf16, BF16 weights, BF16 hi/lo activations, FP32 accumulate")
 

@@ -383,10 +383,13 @@ class Surrogate:
                            val_mean_abs=r.val_mean_abs, ms=r.ms, steps=r.steps, x_max=r.x_max)
         return self.report
 
-    def fit(self, nu_lo, nu_hi, T_lo, T_hi, molar_mass=44.0, n_train=10_000_000, n_val=1_000_000, epochs=300,
+    def fit(self, nu_lo, nu_hi, T_lo, T_hi, molar_mass=44.0, n_train=20_000_000, n_val=1_000_000, epochs=300,
             fine_epochs=100, batch=16384, lr=3e-3, seed=4):
         """Two-stage training: mean squared error, then a fourth-power stage
-        at a tenth of the learning rate that weights the largest errors."""
+        at a tenth of the learning rate that weights the largest errors.
+        20M samples by default: on the 100-layer tables the worst sampled
+        nodes are 5.7e-4 (200k lines) and 9.1e-4 (2M lines) from the direct
+        sum, against 8.3e-4 and 1.1-1.3e-3 with 10M."""
         rng = dict(nu_lo=nu_lo, nu_hi=nu_hi, T_lo=T_lo, T_hi=T_hi, molar_mass=molar_mass)
         r1 = self.train(n_train=n_train, n_val=n_val, epochs=epochs, batch=batch, lr_max=lr, lr_min=lr * 1e-3,
                         seed=seed, **rng)

@@ -25,10 +25,6 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 THREADS = min(16, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1))
 
 
-# training samples of the learned shape per table
-TRAIN_SAMPLES = {"pt100_200k": 10_000_000, "pt100_2m": 20_000_000}
-
-
 def marfa():
     from paper_2411_03418_amd import marfa as M
     return M
@@ -140,16 +136,14 @@ def test_region_edge_rounding_nodes():
 def test_table_sampled_learned_shape(refs, workload):
     """The learned line shape in the table (cut-off 125 cm^-1, Tonkov chi),
     trained on the device for the table's lines and temperatures, within 1e-3
-    of the direct sum.  The 2M-line table spans 0-10125 cm^-1, a wider range of
-    Doppler widths: its network trains on 20M samples instead of 10M (with
-    10M its worst layers reach 1.1-1.3e-3)."""
+    of the direct sum (the network trains on 20M samples, the default)."""
     M = marfa()
     picks = refs(workload)
     lines, layers, rq = synth.workload(workload)
     S = M.Surrogate(chi="tonkov", cutoff=rq["cutoff"], seed=1)
     nu = lines.nu0[lines.nu0 > 0]
     rep = S.fit(nu_lo=float(nu.min()), nu_hi=float(nu.max()), T_lo=float(layers[:, 1].min()),
-                T_hi=float(layers[:, 1].max()), n_train=TRAIN_SAMPLES[workload])
+                T_hi=float(layers[:, 1].max()))
     print(f"[gpu] {workload} learned shape trained: {rep}", flush=True)
     plan = M.Plan(lines, layers, device=0, eval="surrogate", **_req(rq))
     plan.set_surrogate(S)
