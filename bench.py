@@ -246,7 +246,9 @@ def main():
     ap.add_argument("--workload", default="pt100_2m")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true", help="skip every learned-shape leg")
+    ap.add_argument("--surrogate-200k", action="store_true",
+                    help="also time the learned shape on the 200k-line table (its own plan and training)")
     ap.add_argument("--no-surrogate-table", action="store_true",
                     help="skip the learned shape on the benchmark's own table (one step)")
     ap.add_argument("--no-stencil5", action="store_true", help="skip the 5-point stencil leg")
@@ -358,7 +360,7 @@ def main():
         line["stencil5"] = s5
     if s4 is not None:
         line["stencil4"] = s4
-    if not args.no_surrogate:
+    if args.surrogate_200k and not args.no_surrogate:
         line["surrogate"] = surrogate_leg(args)
     if s_big is not None:
         line["surrogate_table"] = s_big
