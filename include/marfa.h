@@ -296,6 +296,17 @@ marfa_status marfa_surrogate_create(marfa_surrogate** out, int32_t chi, double c
  * weights are in place. */
 marfa_status marfa_surrogate_set_params(marfa_surrogate* s, const float* params, int64_t n);
 marfa_status marfa_surrogate_get_params(const marfa_surrogate* s, float* params, int64_t n);
+/* Save and restore a trained network: its 12801 FP32 parameters and the
+ * largest |x| of its training distribution (x_max of the train report), the
+ * two things a plan reads from it besides the chi and cut-off it was created
+ * with.  load sets the parameters as set_params does (synchronous, optimizer
+ * state reset) and marks the network trained, so plans can attach it; a plan
+ * attached before the call keeps the x_max it read when it attached (attach
+ * it again).  Errors: MARFA_E_INVALID (null, n != 12801, a non-finite
+ * parameter, x_max not finite and > 0); save: MARFA_E_UNSUPPORTED for a
+ * network never trained or loaded. */
+marfa_status marfa_surrogate_load(marfa_surrogate* s, const float* params, int64_t n, double x_max);
+marfa_status marfa_surrogate_save(const marfa_surrogate* s, float* params, int64_t n, double* x_max);
 /* Network output t for n samples: X_dev [n][3] features, out_dev [n], both
  * device memory on the surrogate's device.  Asynchronous on hip_stream. */
 marfa_status marfa_surrogate_forward(marfa_surrogate* s, const float* X_dev, int64_t n, float* out_dev,

@@ -529,6 +529,25 @@ extern "C" marfa_status marfa_surrogate_get_params(const marfa_surrogate* s, flo
   return MARFA_OK;
 }
 
+extern "C" marfa_status marfa_surrogate_load(marfa_surrogate* s, const float* params, int64_t n, double x_max) {
+  if (!s || !params) return sfail(MARFA_E_INVALID, "null argument");
+  if (!(std::isfinite(x_max) && x_max > 0.0)) return sfail(MARFA_E_INVALID, "x_max must be finite and > 0");
+  const marfa_status st = marfa_surrogate_set_params(s, params, n);
+  if (st != MARFA_OK) return st;
+  s->x_max = x_max;
+  s->trained = 1;
+  return MARFA_OK;
+}
+
+extern "C" marfa_status marfa_surrogate_save(const marfa_surrogate* s, float* params, int64_t n, double* x_max) {
+  if (!s || !params || !x_max) return sfail(MARFA_E_INVALID, "null argument");
+  if (!s->trained) return sfail(MARFA_E_UNSUPPORTED, "the surrogate is not trained");
+  const marfa_status st = marfa_surrogate_get_params(s, params, n);
+  if (st != MARFA_OK) return st;
+  *x_max = s->x_max;
+  return MARFA_OK;
+}
+
 extern "C" marfa_status marfa_surrogate_forward(marfa_surrogate* s, const float* X, int64_t n, float* out,
                                                 void* stream) {
   if (!s || (n > 0 && (!X || !out))) return sfail(MARFA_E_INVALID, "null argument");

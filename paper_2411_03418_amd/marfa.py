@@ -120,6 +120,8 @@ def lib():
         L.marfa_surrogate_create.argtypes = [C.POINTER(vp), i32, C.c_double, u64, i32]
         L.marfa_surrogate_set_params.argtypes = [vp, vp, i64]
         L.marfa_surrogate_get_params.argtypes = [vp, vp, i64]
+        L.marfa_surrogate_load.argtypes = [vp, vp, i64, C.c_double]
+        L.marfa_surrogate_save.argtypes = [vp, vp, i64, C.POINTER(C.c_double)]
         L.marfa_surrogate_forward.argtypes = [vp, vp, i64, vp, vp]
         L.marfa_surrogate_loss_grad.argtypes = [vp, vp, vp, i64, f32p, vp]
         L.marfa_surrogate_loss_grad_noalloc.argtypes = [vp, vp, vp, i64, vp, vp]
@@ -134,6 +136,7 @@ def lib():
         L.marfa_linedb_read.argtypes = [C.c_char_p, i64, i64, vp, vp, vp, vp, vp, vp, vp, vp]
         L.marfa_linedb_write.argtypes = [C.c_char_p, C.POINTER(Lines)]
         for f in ("marfa_surrogate_create", "marfa_surrogate_set_params", "marfa_surrogate_get_params",
+                  "marfa_surrogate_load", "marfa_surrogate_save",
                   "marfa_surrogate_forward", "marfa_surrogate_loss_grad", "marfa_surrogate_loss_grad_noalloc",
                   "marfa_surrogate_make_samples",
                   "marfa_surrogate_train", "marfa_plan_set_surrogate", "marfa_plan_set_eval"):
@@ -325,6 +328,24 @@ class Surrogate:
         queued work, so launches already enqueued use the old weights."""
         p = np.ascontiguousarray(params, np.float32)
         _check(lib().marfa_surrogate_set_params(self._h, _ptr(p), p.size))
+
+    def save(self, path):
+        """Write the trained network -- parameters, x_max (the largest |x| of
+        its training distribution), chi and cut-off -- to an .npz file."""
+        p = np.empty(N_PARAMS, np.float32)
+        x_max = C.c_double()
+        _check(lib().marfa_surrogate_save(self._h, _ptr(p), N_PARAMS, C.byref(x_max)))
+        np.savez(path, params=p, x_max=np.float64(x_max.value), chi=np.int32(CHIS.get(self.chi, self.chi)),
+                 cutoff=np.float64(self.cutoff))
+
+    @classmethod
+    def load(cls, path, device=0):
+        """A network written by save(), ready to attach to plans."""
+        with np.load(path) as z:
+            s = cls(chi=int(z["chi"]), cutoff=float(z["cutoff"]), device=device)
+            p = np.ascontiguousarray(z["params"], np.float32)
+            _check(lib().marfa_surrogate_load(s._h, _ptr(p), p.size, float(z["x_max"])))
+        return s
 
     def forward(self, X, stream=None):
         import torch

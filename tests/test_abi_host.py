@@ -145,3 +145,6 @@ def test_null_handles_are_rejected():
     assert L.marfa_surrogate_train(None, None, None, None) == marfa.E_INVALID
     assert L.marfa_plan_tune(None, None, 0, None) == marfa.E_INVALID
     assert L.marfa_surrogate_loss_grad_noalloc(None, None, None, 1, None, None) == marfa.E_INVALID
+    assert L.marfa_surrogate_load(None, None, 0, 1.0) == marfa.E_INVALID
+    x_max = C.c_double()
+    assert L.marfa_surrogate_save(None, None, 0, C.byref(x_max)) == marfa.E_INVALID

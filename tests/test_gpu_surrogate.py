@@ -253,3 +253,41 @@ def test_surrogate_eval_switch_and_set_params_after_execute():
     assert torch.equal(back, ref)
     plan.close()
     S.close()
+
+
+def test_surrogate_save_load_round_trip(tmp_path):
+    """A network saved after training and loaded into a new handle attaches to
+    a plan and gives the same output, bit for bit; an untrained network has
+    nothing to save and a load needs a positive x_max."""
+    from paper_2411_03418_amd import synth
+    mm = M()
+    lines = synth.make_lines(1500, 950.0, 1070.0, 47, shift=True)
+    layers = synth.pt_table(3)
+    req = dict(nu_begin=1000.0, nu_end=1008.0, cutoff=60.0, chi="tonkov", prune=1e-6)
+    S = mm.Surrogate(chi="tonkov", cutoff=60.0, seed=3)
+    with pytest.raises(mm.MarfaError) as e:
+        S.save(str(tmp_path / "untrained.npz"))
+    assert e.value.status == mm.E_UNSUPPORTED
+    rep = S.train(n_train=65536, n_val=4096, epochs=2, batch=4096, lr_max=2e-3, lr_min=1e-4, seed=11,
+                  nu_lo=945.0, nu_hi=1075.0, T_lo=150.0, T_hi=740.0)
+    path = str(tmp_path / "net.npz")
+    S.save(path)
+    plan = mm.Plan(lines, layers, device=0, eval="surrogate", **req)
+    plan.set_surrogate(S)
+    ref = plan.execute().clone()
+    torch.cuda.synchronize()
+    plan.set_surrogate(None)
+    S.close()
+    L = mm.Surrogate.load(path)
+    with np.load(path) as z:
+        assert float(z["x_max"]) == rep["x_max"]
+        assert np.array_equal(L.get_params(), z["params"])
+        params = np.ascontiguousarray(z["params"], np.float32)
+        for bad in (0.0, -1.0, float("inf"), float("nan")):
+            assert mm.lib().marfa_surrogate_load(L._h, mm._ptr(params), mm.N_PARAMS, bad) == mm.E_INVALID
+    plan.set_surrogate(L)
+    got = plan.execute().clone()
+    torch.cuda.synchronize()
+    assert torch.equal(got, ref)
+    plan.close()
+    L.close()
