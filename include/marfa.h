@@ -347,7 +347,7 @@ void marfa_surrogate_destroy(marfa_surrogate* s);
  * outside the trained domain (y outside [1e-4, 1e3] or |x| above the
  * report's x_max) take the plain line shape.  Requires a single-precision
  * Voigt plan with the 3-point stencil and the surrogate's chi and cut-off.
- * The learned-shape kernel runs on work items of its own (128 nodes, 2048
+ * The learned-shape kernel runs on work items of its own (128 nodes, 1024
  * on level 0, allocated here on first attach); marfa_plan_tune always tunes
  * the plain kernel.  The surrogate must outlive its use by the plan.  Waits
  * for the device's queued work before rebuilding the plan's graphs.

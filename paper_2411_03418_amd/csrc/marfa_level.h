@@ -240,10 +240,11 @@ __device__ float g_surr(float d, const LineRec32& L, const float* __restrict__ s
 // |x|, y and |d| in cm; the batch overwrites |x| with Kb(x, y) e^t / y, and
 // the lane scales it by its line's S' sqrt(pi) xs^2 (= A sqrt(pi) xs^2 with
 // A = S' gamma_L / pi).  A session pushes at most kSurrSlots pairs per lane
-// (with the 3-point stencil, the only one the learned shape runs with: up to
-// three candidate bases times three nodes on the ratio-4 level), so the queue
-// never overflows.
-constexpr int kSurrSlots = 9;
+// (with the 3-point stencil, the only one the learned shape runs with: four
+// nodes of the region pass, five stencil values or two candidate centres of
+// three nodes each in the band pass), so the queue never overflows.  Six
+// slots keep the four queues at 18 KB, so three workgroups share a CU.
+constexpr int kSurrSlots = 6;
 constexpr int kSurrQueue = 64 * kSurrSlots;   // entries per wavefront: three arrays of this many floats
 
 // Push `want` pairs of the calling lanes; returns the slot of each, `n` the
@@ -272,7 +273,9 @@ __device__ __forceinline__ void surr_batch(float* q, int n, const LevelArgs& a) 
     const float ad = ok ? q[2 * kSurrQueue + i] : 0.0f;
     float f1, f2, f3;
     mlp_features(x, y, ad, a.mlp_inv_c, f1, f2, f3);
-    const float t = mlp_forward_wave(a.mlp, f1, f2, f3);
+    // a partial last batch runs only the 16-sample groups that hold entries
+    const int ns = n - r >= 64 ? 4 : (n - r + 15) >> 4;
+    const float t = mlp_forward_wave(a.mlp, f1, f2, f3, ns);
     if (ok) q[i] = __builtin_amdgcn_rcpf(y) * mlp_base(x, y) * __expf(t);
   }
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -986,39 +989,45 @@ __device__ __forceinline__ void band_chunk(const typename RecOf<R>::T& L, int32_
   R glv[NC][RHO];
   if constexpr (SURR && !COUNT) {
     // learned shape: the line's own values at the candidate nodes through the
-    // queue (queued slots hold their position, bit c RHO + ji of qmask)
+    // queue (queued slots hold their position, bit c RHO + ji of qmask), in
+    // sessions of CS centres so that a lane never holds more than kSurrSlots
     static_assert(NC * RHO <= 32, "one mask bit per candidate node");
-    static_assert(NC * (SS::kJhi - SS::kJlo) <= kSurrSlots, "one queue session holds the candidate nodes");
-    uint32_t qmask = 0;
-    int n = 0;
+    constexpr int kPer = SS::kJhi - SS::kJlo;   // interpolated nodes per centre
+    constexpr int CS = kSurrSlots / kPer;
+    static_assert(CS >= 1, "one queue session holds a centre's nodes");
     const float amp = L.A * 1.7724538509055160f * L.xs * L.xs;
 #pragma unroll
-    for (int c = 0; c < NC; ++c)
+    for (int cb = 0; cb < NC; cb += CS) {
+      uint32_t qmask = 0;
+      int n = 0;
 #pragma unroll
-      for (int jj = SS::kJlo; jj <= SS::kJhi; ++jj) {
-        const int ji = jj - SS::kJlo;
-        glv[c][ji] = 0.0f;
-        if (jj == 0) continue;
-        R d;
-        bool use, need, in_reg, own;
-        node(c, jj, d, use, need, in_reg, own);
-        float x, y;
-        const bool dom = surr_domain(d, L, a, x, y);
-        const bool queued = need && dom;
-        if (need && !dom) glv[c][ji] = g_any<float, false>(d, L, sp, jl, G, cfine, true, cnt);
-        const int pos = surr_push(a.sq, queued, n, x, y, fabsf(d) * float(kH0));
-        if (queued) {
-          glv[c][ji] = __int_as_float(pos);
-          qmask |= 1u << (c * RHO + ji);
+      for (int c = cb; c < (cb + CS < NC ? cb + CS : NC); ++c)
+#pragma unroll
+        for (int jj = SS::kJlo; jj <= SS::kJhi; ++jj) {
+          const int ji = jj - SS::kJlo;
+          glv[c][ji] = 0.0f;
+          if (jj == 0) continue;
+          R d;
+          bool use, need, in_reg, own;
+          node(c, jj, d, use, need, in_reg, own);
+          float x, y;
+          const bool dom = surr_domain(d, L, a, x, y);
+          const bool queued = need && dom;
+          if (need && !dom) glv[c][ji] = g_any<float, false>(d, L, sp, jl, G, cfine, true, cnt);
+          const int pos = surr_push(a.sq, queued, n, x, y, fabsf(d) * float(kH0));
+          if (queued) {
+            glv[c][ji] = __int_as_float(pos);
+            qmask |= 1u << (c * RHO + ji);
+          }
         }
-      }
-    if (n > 0) surr_batch(a.sq, n, a);
+      if (n > 0) surr_batch(a.sq, n, a);
 #pragma unroll
-    for (int c = 0; c < NC; ++c)
+      for (int c = cb; c < (cb + CS < NC ? cb + CS : NC); ++c)
 #pragma unroll
-      for (int ji = 0; ji < RHO; ++ji)
-        if ((qmask >> (c * RHO + ji)) & 1u) glv[c][ji] = amp * a.sq[__float_as_int(glv[c][ji])];
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        for (int ji = 0; ji < RHO; ++ji)
+          if ((qmask >> (c * RHO + ji)) & 1u) glv[c][ji] = amp * a.sq[__float_as_int(glv[c][ji])];
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    }
   }
 #pragma unroll
   for (int c = 0; c < NC; ++c) {

@@ -3,4 +3,4 @@
 #define MARFA_STENCILS 1
 #include "marfa_level.h"
 
-MARFA_LEVEL_LAUNCHER(f32_surr, float, false, true, 2)
+MARFA_LEVEL_LAUNCHER(f32_surr, float, false, true, 3)

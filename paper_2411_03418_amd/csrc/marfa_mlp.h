@@ -168,13 +168,15 @@ __device__ __forceinline__ float mlp_base(float x, float y) {
 
 // Wave-collective forward pass: every lane brings one sample (f1, f2, f3)
 // and receives its network output t.  All 64 lanes must call it together.
-// Weights may live in global memory or LDS (generic pointers).
-__device__ __forceinline__ float mlp_forward_wave(const MlpDev& W, float f1, float f2, float f3) {
+// Weights may live in global memory or LDS (generic pointers).  Only the
+// first 16 ns lanes' samples are evaluated (ns uniform, 1..4); the other
+// lanes receive 0.
+__device__ __forceinline__ float mlp_forward_wave(const MlpDev& W, float f1, float f2, float f3, int ns = 4) {
   const int lane = threadIdx.x & 63;
   const int q = lane >> 4, col = lane & 15;
   float result = 0.0f;
 #pragma unroll 1
-  for (int s = 0; s < 4; ++s) {
+  for (int s = 0; s < ns; ++s) {
     // keeps the weight loads inside the loop: hoisted to the callers' loops
     // they would hold ~100 registers for the whole kernel
     asm volatile("" ::: "memory");

@@ -471,13 +471,14 @@ static void choose_tiles(Geometry& G, double lines_per_cm) {
 // candidate work-item sizes of the autotuner (ascending)
 static const int kTuneItems[3] = {128, 256, 512};
 static const int kSurrItemNodes = 128;   // work-item size of the learned-shape kernel
+static const int kSurrItemMult = 8;      // at most this many times larger on the finest levels
 
 // Work items: nodes per item scale inversely with the per-node cost, which
 // grows with the level step (window width in lines); heaviest levels first.
-static void make_tiles(const Geometry& G, std::vector<Tile>& tiles, int base_nodes) {
+static void make_tiles(const Geometry& G, std::vector<Tile>& tiles, int base_nodes, int max_mult = 16) {
   tiles.clear();
   for (int l = kLevels - 1; l >= 0; --l) {
-    int64_t per = (int64_t)base_nodes * std::max<int64_t>(1, 16 / G.r[l]);
+    int64_t per = (int64_t)base_nodes * std::max<int64_t>(1, std::min(max_mult, 16 / G.r[l]));
     per = ((per + kWave - 1) / kWave) * kWave;
     for (int64_t f = 0; f < G.n[l]; f += per) {
       Tile t;
@@ -1176,11 +1177,11 @@ extern "C" marfa_status marfa_plan_set_surrogate(marfa_plan* p, const marfa_surr
   for (const IntervalSet& iv : p->ivs)
     if (iv.n_jump > 0 && !iv.lc_ok)
       return fail(MARFA_E_UNSUPPORTED, "cut-off too small for the line-major band pass the surrogate needs");
-  // its own work items: 128 nodes (2048 on level 0) keep the accumulators at
-  // 8 KB of LDS, so two workgroups fit a CU beside the staged network
+  // its own work items: 128 nodes (1024 on level 0) keep the accumulators at
+  // 4 KB of LDS, so three workgroups fit a CU beside the staged network
   if (p->stiles.empty()) {
     std::vector<Tile> st;
-    make_tiles(p->G, st, kSurrItemNodes);
+    make_tiles(p->G, st, kSurrItemNodes, kSurrItemMult);
     HIP_TRY(hipSetDevice(p->device));
     marfa_status m = dmalloc(&p->d.stiles, st.size());
     if (m != MARFA_OK) return m;
