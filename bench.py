@@ -229,7 +229,7 @@ def surrogate_leg(args):
                 roofline={"bound": "mfma", "achieved": mfma_tflops, "peak": PEAK_BF16_MFMA_TFLOPS, "unit": "TFLOP/s",
                           "frac": mfma_tflops / PEAK_BF16_MFMA_TFLOPS, "kernel": "k_level (learned shape)",
                           "evaluations": int(evals), "flop_per_evaluation": FLOP_MLP,
-                          "note": "VALU-bound in practice: SiLU costs two quarter-rate transcendentals per activation"},
+                          "note": "VALU-bound in practice: each SiLU activation costs two transcendentals (3.3x an FP32 add each)"},
                 steps=args.surrogate_steps, level_ms=t["level_ms"], plain_ms_per_step=ms_plain,
                 speed_vs_plain=ms_plain / ms_surr, max_rel_dev_from_plain=dev,
                 train=dict(ms=rep["ms"], steps=rep["steps"], val_max_abs_t=rep["val_max_abs"],
