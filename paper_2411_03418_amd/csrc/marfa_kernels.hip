@@ -21,7 +21,8 @@
 //   k_level           persistent work queue over (layer, level, node tile):
 //                     each lane owns one level node and sums the contributions
 //                     of the lines in its windows (wave-uniform line loads)
-//   k_cascade         3-, 4- or 5-point interpolation from level l+1 into level l;
+//   k_cascade         3-, 4- or 5-point interpolation from level l+1 into level l,
+//                     one thread per coarse cell with compile-time weights;
 //                     the level-0 pass applies the layer scale and writes out.
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -284,42 +285,89 @@ __global__ void k_layer_scale(const double* __restrict__ layers, const unsigned 
 // ------------------------------------------------------------------
 // cascade: A_l += P(A_(l+1)); level 0 also scales into the output
 // ------------------------------------------------------------------
-template <typename R>
-__global__ void k_cascade(Geometry G, int l, R* A, R* out, int64_t stride, const double* scale) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int layer = blockIdx.y;
-  if (i >= G.n[l]) return;
-  int64_t m = G.lo[l] + i;
-  int64_t rho = G.r[l + 1] / G.r[l];
-  int64_t q = floor_div(m, rho);
-  int64_t rem = m - q * rho;
-  const R* Ac = A + (int64_t)layer * G.a_total + G.aoff[l + 1] - G.lo[l + 1];
-  R v;
-  if (rem == 0) {
-    v = Ac[q];
-  } else if (G.ns == 4) {
-    // the two coarse nodes on each side, q - 1 .. q + 2
-    const double f = (double)rem / (double)rho;
-    v = R(0);
-#pragma unroll
-    for (int k = -1; k <= 2; ++k) v += R(lagrange_w4(k, f)) * Ac[q + k];
-  } else {
-    double f = (double)rem / (double)rho, t;
-    int64_t kc;
-    if (f <= 0.5) { kc = q; t = f; } else { kc = q + 1; t = f - 1.0; }
-    if (G.ns == 5) {
-      v = R(0);
-#pragma unroll
-      for (int k = -2; k <= 2; ++k) v += R(lagrange_w<2>(k, t)) * Ac[kc + k];
-    } else {
-      v = R(lagrange_w<1>(-1, t)) * Ac[kc - 1] + R(lagrange_w<1>(0, t)) * Ac[kc] + R(lagrange_w<1>(1, t)) * Ac[kc + 1];
+// Interpolation weights of the cascade, fixed at compile time: fine node j
+// (0 <= j < RHO) of coarse cell q takes sum_e w(j, e) A[q - kCascL + e] over
+// the window e = 0 .. kCascL + kCascR.  Injection at j = 0; the 3- and
+// 5-point rules centre on the nearest coarse node (ties to the left), the
+// 4-point rule uses q - 1 .. q + 2.
+template <int NS>
+constexpr int kCascL = NS == 5 ? 2 : 1;
+template <int NS>
+constexpr int kCascR = NS == 5 ? 3 : 2;
+template <int RHO, int NS>
+struct CascadeStencil {
+  double w[RHO][kCascL<NS> + kCascR<NS> + 1] = {};
+  bool used[RHO][kCascL<NS> + kCascR<NS> + 1] = {};
+  constexpr CascadeStencil() {
+    constexpr int WL = kCascL<NS>;
+    w[0][WL] = 1.0;
+    used[0][WL] = true;
+    for (int j = 1; j < RHO; ++j) {
+      const double f = (double)j / (double)RHO;
+      if (NS == 4) {
+        for (int k = -1; k <= 2; ++k) {
+          w[j][WL + k] = lagrange_w4(k, f);
+          used[j][WL + k] = true;
+        }
+      } else {
+        const int kc = f <= 0.5 ? 0 : 1;
+        const double t = f - kc;
+        constexpr int H = NS == 5 ? 2 : 1;
+        for (int k = -H; k <= H; ++k) {
+          w[j][WL + kc + k] = lagrange_w<H>(k, t);
+          used[j][WL + kc + k] = true;
+        }
+      }
     }
   }
-  if (l > 0) {
-    A[(int64_t)layer * G.a_total + G.aoff[l] + i] += v;
-  } else {
-    R* o = out + (int64_t)layer * stride + i;
-    *o = R(scale[layer]) * (*o + v);
+};
+
+// Level l from level l+1 (ratio RHO = 2 or 4, NS-point stencil): one thread
+// per coarse cell q holds the coarse window once and writes the RHO fine nodes
+// m = RHO q + j that lie in level l's range; level 0 gets the layer's scale.
+template <typename R, int RHO, int NS>
+__global__ void __launch_bounds__(256) k_cascade(Geometry G, int l, R* A, R* out, int64_t stride,
+                                                 const double* scale) {
+  constexpr CascadeStencil<RHO, NS> S{};
+  constexpr int WL = kCascL<NS>, NW = kCascL<NS> + kCascR<NS> + 1;
+  const int layer = blockIdx.y;
+  const int64_t lo = G.lo[l], hi = G.lo[l] + G.n[l];
+  const int64_t q = floor_div(lo, RHO) + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t m0 = q * RHO;
+  if (m0 >= hi) return;
+  const R* Ac = A + (int64_t)layer * G.a_total + G.aoff[l + 1] - G.lo[l + 1];
+  const R sc = l == 0 ? R(scale[layer]) : R(1);
+  bool in[RHO];
+#pragma unroll
+  for (int j = 0; j < RHO; ++j) in[j] = m0 + j >= lo && m0 + j < hi;
+  // the window entries some in-range node reads (all of them inside the range)
+  R c[NW];
+#pragma unroll
+  for (int e = 0; e < NW; ++e) {
+    bool need = false;
+#pragma unroll
+    for (int j = 0; j < RHO; ++j) need = need || (in[j] && S.used[j][e]);
+    c[e] = need ? Ac[q - WL + e] : R(0);
+  }
+#pragma unroll
+  for (int j = 0; j < RHO; ++j) {
+    if (!in[j]) continue;
+    R v;
+    if (j == 0) {
+      v = c[WL];
+    } else {
+      v = R(0);
+#pragma unroll
+      for (int e = 0; e < NW; ++e)
+        if (S.used[j][e]) v += R(S.w[j][e]) * c[e];
+    }
+    const int64_t i = m0 + j - lo;
+    if (l > 0) {
+      A[(int64_t)layer * G.a_total + G.aoff[l] + i] += v;
+    } else {
+      R* o = out + (int64_t)layer * stride + i;
+      *o = sc * (*o + v);
+    }
   }
 }
 
@@ -473,15 +521,33 @@ void launch_rank(const LineIn& in, const double* layers, int nL, const double* s
   k_rank<<<grid, 256, 0, s>>>(in, layers, span, perm);
 }
 
+template <typename R, int RHO>
+static void launch_cascade_level(const Geometry& G, int l, dim3 grid, R* A, R* out, int64_t stride,
+                                 const double* scale, hipStream_t s) {
+  if (G.ns == 5) k_cascade<R, RHO, 5><<<grid, 256, 0, s>>>(G, l, A, out, stride, scale);
+  else if (G.ns == 4) k_cascade<R, RHO, 4><<<grid, 256, 0, s>>>(G, l, A, out, stride, scale);
+  else k_cascade<R, RHO, 3><<<grid, 256, 0, s>>>(G, l, A, out, stride, scale);
+}
+
+template <typename R>
+static void launch_cascade_r(const Geometry& G, int nL, R* A, R* out, int64_t stride, const double* scale,
+                             hipStream_t s) {
+  for (int l = kLevels - 2; l >= 0; --l) {
+    // the level tables have ratios 2 and 4 only (4 between levels 1 and 0 in the default table)
+    const int64_t rho = G.r[l + 1] / G.r[l];
+    const int64_t q_lo = G.lo[l] >= 0 ? G.lo[l] / rho : -((-G.lo[l] + rho - 1) / rho);
+    const int64_t m_hi = G.lo[l] + G.n[l] - 1;
+    const int64_t q_hi = m_hi >= 0 ? m_hi / rho : -((-m_hi + rho - 1) / rho);
+    const dim3 grid((unsigned)((q_hi - q_lo + 1 + 255) / 256), nL);
+    if (rho == 4) launch_cascade_level<R, 4>(G, l, grid, A, out, stride, scale, s);
+    else launch_cascade_level<R, 2>(G, l, grid, A, out, stride, scale, s);
+  }
+}
+
 void launch_cascade(const Geometry& G, int nL, void* A, void* out, int64_t stride, const double* scale, bool fp64,
                     hipStream_t s) {
-  for (int l = kLevels - 2; l >= 0; --l) {
-    dim3 grid((unsigned)((G.n[l] + 255) / 256), nL);
-    if (fp64)
-      k_cascade<double><<<grid, 256, 0, s>>>(G, l, (double*)A, (double*)out, stride, scale);
-    else
-      k_cascade<float><<<grid, 256, 0, s>>>(G, l, (float*)A, (float*)out, stride, scale);
-  }
+  if (fp64) launch_cascade_r<double>(G, nL, (double*)A, (double*)out, stride, scale, s);
+  else launch_cascade_r<float>(G, nL, (float*)A, (float*)out, stride, scale, s);
 }
 
 void launch_mlp_samples(const MlpSampleCfg& c, uint64_t seed, int64_t n, float* X, float* T,
