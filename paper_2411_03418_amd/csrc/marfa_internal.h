@@ -161,6 +161,7 @@ struct DeviceBuffers {
   float* nair = nullptr;
   float* dair = nullptr;
   double* layers = nullptr;        // [n_layers][4] p, T, p_self, q_ratio
+  double* lconst = nullptr;        // [n_layers][8] per-layer constants of the line preparation
   unsigned long long* smax = nullptr;  // [n_layers] bits of max S(T) (FP64)
   int32_t* bcount = nullptr;       // [n_layers][n_blocks] kept lines per block -> offsets
   int32_t* scount = nullptr;       // [n_layers][n_blocks][12] lines per start level (12 = dropped)
@@ -227,6 +228,7 @@ struct PrepArgs {
   double* cnu;
   void* csp;
   double* scale;
+  double* lc;   // [layer][8] per-layer constants, written by the preparation's first kernel
   double prune, R;
   int32_t out_kind, fp64;
 };

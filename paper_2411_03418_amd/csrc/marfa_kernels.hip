@@ -12,6 +12,7 @@
 //
 // Kernels (all launched on the caller's stream, captured into one HIP graph):
 //   k_fill_*          clear counters and maxima (graph-safe, no memset nodes)
+//   k_layer_const     per-layer factors of the FP64 line preparation
 //   k_prep_smax       FP64 S(T) per (line, layer), max per layer
 //   k_prep_count      per-block counts of kept lines by start level
 //   k_prep_scan       exclusive offsets per (layer, start level)
@@ -56,26 +57,44 @@ struct LineState {
 //   (1 - exp(-c2 nu/T))/(1 - exp(-c2 nu/296));
 // gamma_L = (296/T)^n (gamma_air (p - p_self) + gamma_self p_self);
 // alpha_D = nu/c sqrt(2 ln2 k_B T N_A / M);  nu~0 = nu0 + delta_air p.
-__device__ __forceinline__ LineState line_state(const LineIn& in, int64_t j, const double* lay) {
-  double p = lay[0], T = lay[1], ps = lay[2], q = lay[3];
-  double nu = in.nu0[j];
-  double qr = q > 0.0 ? q : kTref / T;
-  double boltz = exp(-kC2 * (double)in.El[j] * (1.0 / T - 1.0 / kTref));
-  double stim = nu > 0.0 ? expm1(-kC2 * nu / T) / expm1(-kC2 * nu / kTref) : kTref / T;
+// The factors that depend on the layer alone are formed once per layer:
+// c = {p, p_self, Q(296)/Q(T), c2 (1/T - 1/296), ln(296/T), c2/T,
+//      sqrt(2 ln2 k_B N_A T / M)/c_light, 296/T}.
+constexpr int kLayerConst = 8;
+__global__ void k_layer_const(const double* __restrict__ layers, int nL, double molar_mass, double* lc) {
+  const int L = blockIdx.x * blockDim.x + threadIdx.x;
+  if (L >= nL) return;
+  const double p = layers[4 * L], T = layers[4 * L + 1], ps = layers[4 * L + 2], q = layers[4 * L + 3];
+  double* c = lc + kLayerConst * L;
+  c[0] = p;
+  c[1] = ps;
+  c[2] = q > 0.0 ? q : kTref / T;
+  c[3] = kC2 * (1.0 / T - 1.0 / kTref);
+  c[4] = log(kTref / T);
+  c[5] = kC2 / T;
+  c[6] = sqrt(2.0 * kLn2d * kBoltzmann * kNA * T / (molar_mass * 1e-3)) / kCLight;
+  c[7] = kTref / T;
+}
+
+__device__ __forceinline__ LineState line_state(const LineIn& in, int64_t j, const double* __restrict__ c) {
+  constexpr double kC2Tref = kC2 / kTref;
+  const double nu = in.nu0[j];
+  const double boltz = exp(-(double)in.El[j] * c[3]);
+  const double stim = nu > 0.0 ? expm1(-nu * c[5]) / expm1(-nu * kC2Tref) : c[7];
   LineState s;
-  s.S = (double)in.S296[j] * qr * boltz * stim;
-  s.gL = pow(kTref / T, (double)in.nair[j]) * ((double)in.gair[j] * (p - ps) + (double)in.gself[j] * ps);
-  s.aD = nu / kCLight * sqrt(2.0 * kLn2d * kBoltzmann * kNA * T / (in.molar_mass * 1e-3));
-  s.nut = nu + (double)in.dair[j] * p;
+  s.S = (double)in.S296[j] * c[2] * boltz * stim;
+  s.gL = exp((double)in.nair[j] * c[4]) * ((double)in.gair[j] * (c[0] - c[1]) + (double)in.gself[j] * c[1]);
+  s.aD = nu * c[6];
+  s.nut = nu + (double)in.dair[j] * c[0];
   return s;
 }
 
-__global__ void k_prep_smax(LineIn in, const double* __restrict__ layers, unsigned long long* smax) {
+__global__ void k_prep_smax(LineIn in, const double* __restrict__ lc, unsigned long long* smax) {
   __shared__ double red[256];
   int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
   int L = blockIdx.y;
   double S = 0.0;
-  if (j < in.n) S = line_state(in, j, layers + 4 * L).S;
+  if (j < in.n) S = line_state(in, j, lc + kLayerConst * L).S;
   red[threadIdx.x] = S;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
@@ -96,15 +115,15 @@ __device__ __forceinline__ int start_level(double w, double R, const Geometry& G
 }
 
 // start level of a kept line, kGroups if pruned
-__device__ __forceinline__ int line_key(const LineIn& in, int64_t j, const double* lay, double smax,
+__device__ __forceinline__ int line_key(const LineIn& in, int64_t j, const double* lc, double smax,
                                         double prune, double R, const Geometry& G, LineState& st) {
-  st = line_state(in, j, lay);
+  st = line_state(in, j, lc);
   bool keep = prune <= 0.0 || st.S >= prune * smax;
   if (!keep) return kGroups;
   return start_level(fmax(st.gL, st.aD), R, G);
 }
 
-__global__ void k_prep_count(LineIn in, const double* __restrict__ layers, Geometry G, PrepArgs pa, int nblk) {
+__global__ void k_prep_count(LineIn in, Geometry G, PrepArgs pa, int nblk) {
   __shared__ int cnt[kGroups + 1];
   if (threadIdx.x <= kGroups) cnt[threadIdx.x] = 0;
   __syncthreads();
@@ -113,7 +132,8 @@ __global__ void k_prep_count(LineIn in, const double* __restrict__ layers, Geome
   if (i < in.n) {
     const int64_t j = pa.perm[(int64_t)L * in.n + i];
     LineState st;
-    int key = line_key(in, j, layers + 4 * L, __longlong_as_double((long long)pa.smax[L]), pa.prune, pa.R, G, st);
+    int key = line_key(in, j, pa.lc + kLayerConst * L, __longlong_as_double((long long)pa.smax[L]), pa.prune, pa.R, G,
+                       st);
     atomicAdd(&cnt[key], 1);
   }
   __syncthreads();
@@ -160,7 +180,7 @@ __global__ void k_prep_scan(PrepArgs pa, int nblk) {
 }
 
 template <typename R>
-__global__ void k_prep_scatter(LineIn in, const double* __restrict__ layers, Geometry G, PrepArgs pa, int nblk) {
+__global__ void k_prep_scatter(LineIn in, Geometry G, PrepArgs pa, int nblk) {
   __shared__ int wcnt[4];
   int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   int L = blockIdx.y;
@@ -171,7 +191,7 @@ __global__ void k_prep_scatter(LineIn in, const double* __restrict__ layers, Geo
   int64_t j = 0;
   if (i < in.n) {
     j = pa.perm[(int64_t)L * in.n + i];
-    key = line_key(in, j, layers + 4 * L, sm, pa.prune, pa.R, G, st);
+    key = line_key(in, j, pa.lc + kLayerConst * L, sm, pa.prune, pa.R, G, st);
   }
   bool keep = key < kGroups;
   unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -466,16 +486,17 @@ void launch_prep(const LineIn& in, const double* layers, int nL, const Geometry&
                  hipStream_t s) {
   int nblk = (int)((in.n + 255) / 256);
   launch_fill_u64(pa.smax, nL, 0ull, s);
+  k_layer_const<<<(nL + 63) / 64, 64, 0, s>>>(layers, nL, in.molar_mass, pa.lc);
   if (nblk > 0) {
     dim3 grid(nblk, nL);
-    k_prep_smax<<<grid, 256, 0, s>>>(in, layers, pa.smax);
-    k_prep_count<<<grid, 256, 0, s>>>(in, layers, G, pa, nblk);
+    k_prep_smax<<<grid, 256, 0, s>>>(in, pa.lc, pa.smax);
+    k_prep_count<<<grid, 256, 0, s>>>(in, G, pa, nblk);
   }
   k_prep_scan<<<nL, 256, 0, s>>>(pa, nblk);
   if (nblk > 0) {
     dim3 grid(nblk, nL);
-    if (pa.fp64) k_prep_scatter<double><<<grid, 256, 0, s>>>(in, layers, G, pa, nblk);
-    else k_prep_scatter<float><<<grid, 256, 0, s>>>(in, layers, G, pa, nblk);
+    if (pa.fp64) k_prep_scatter<double><<<grid, 256, 0, s>>>(in, G, pa, nblk);
+    else k_prep_scatter<float><<<grid, 256, 0, s>>>(in, G, pa, nblk);
   }
   dim3 gc((unsigned)((in.n + 1 + 255) / 256), nL);
   k_prep_coarse<<<gc, 256, 0, s>>>(in.n, G, pa);

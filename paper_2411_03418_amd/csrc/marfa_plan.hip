@@ -563,7 +563,7 @@ static void free_plan(marfa_plan* p) {
     if (p->sexec[i]) (void)hipGraphExecDestroy(p->sexec[i]);
     if (p->sgraph[i]) (void)hipGraphDestroy(p->sgraph[i]);
   }
-  void* bufs[] = {p->d.nu0, p->d.S296, p->d.gair, p->d.gself, p->d.El, p->d.nair, p->d.dair, p->d.layers,
+  void* bufs[] = {p->d.nu0, p->d.S296, p->d.gair, p->d.gself, p->d.El, p->d.nair, p->d.dair, p->d.layers, p->d.lconst,
                   p->d.smax, p->d.bcount, p->d.scount, p->d.kept, p->d.gcount, p->d.bucket, p->d.coarse, p->d.rec, p->d.cnu, p->d.csp,
                   p->d.A, p->d.ivs, p->d.tiles, p->d.stiles, p->d.counter, p->d.scale, p->d.span, p->d.perm,
                   p->d.stats};
@@ -674,6 +674,7 @@ extern "C" marfa_status marfa_plan_create(marfa_plan** out, const marfa_lines* l
   ALLOC(p->d.nair, n);
   ALLOC(p->d.dair, n);
   ALLOC(p->d.layers, 4 * NL);
+  ALLOC(p->d.lconst, 8 * NL);
   ALLOC(p->d.smax, NL);
   ALLOC(p->d.bcount, NL * (size_t)std::max(1, p->nblk));
   ALLOC(p->d.scount, NL * (size_t)std::max(1, p->nblk) * (kGroups + 1));
@@ -794,6 +795,7 @@ static void enqueue(marfa_plan* p, int first, int count, void* out, int64_t stri
   pa.cnu = p->d.cnu + F * (size_t)n;
   pa.csp = (char*)p->d.csp + F * (size_t)n * realsz;
   pa.scale = p->d.scale + F;
+  pa.lc = p->d.lconst + 8 * F;
   pa.prune = p->req.prune_rel;
   pa.R = p->req.R;
   pa.out_kind = p->req.out_kind;
