@@ -72,7 +72,6 @@ struct Geometry {
   int32_t nbucket;           // buckets of the per-layer line index (kBucketPerCm per cm^-1)
   int32_t pad;
   double bucket_origin;      // wavenumber of bucket 0 [cm^-1] (below every shifted centre)
-  int32_t ncoarse;           // 1 cm^-1 buckets of the coarse line index
   int32_t pad2;
   // Tonkov chi pieces as exp2(chi_c0[i] + chi_c1[i] |d|), |d| in cm (host-computed)
   double chi_c0[3], chi_c1[3];
@@ -171,7 +170,6 @@ struct DeviceBuffers {
   double* cnu = nullptr;           // [n_layers][n_lines] shifted centre of the kept lines
   void* csp = nullptr;             // [n_layers][n_lines] S(T)/max S(T) of the kept lines (FP32/FP64)
   int32_t* bucket = nullptr;       // [n_layers][nbucket+1] first kept line with nu~0 >= origin + b/kBucketPerCm
-  int32_t* coarse = nullptr;       // [n_layers][ncoarse+1] first kept line with nu~0 >= origin + b (cm)
   void* A = nullptr;               // [n_layers][a_total] level arrays 1..10
   IntervalSet* ivs = nullptr;      // [11][8]
   Tile* tiles = nullptr;           // [n_tiles] heaviest first
@@ -223,7 +221,7 @@ void launch_fill_u32(unsigned int* p, int64_t n, unsigned int v, hipStream_t s);
 struct PrepArgs {
   const int32_t* perm;   // [layer][line] order of shifted centres
   unsigned long long* smax;
-  int32_t *bcount, *scount, *kept, *gcount, *bucket, *coarse;
+  int32_t *bcount, *scount, *kept, *gcount, *bucket;
   void* rec;
   double* cnu;
   void* csp;

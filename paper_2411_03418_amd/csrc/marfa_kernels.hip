@@ -18,6 +18,8 @@
 //   k_prep_scan       exclusive offsets per (layer, start level)
 //   k_prep_scatter    FP64 placement nu~0*2048 -> (int k0, frac) and the
 //                     compacted per-layer line records, grouped by start level
+//   k_prep_bucket     per-layer index: first kept line at or above each
+//                     1/256 cm^-1 bucket (one thread per line fills its gap)
 //   k_layer_scale     output scale per layer (max S(T), number density)
 //   k_level           persistent work queue over (layer, level, node tile):
 //                     each lane owns one level node and sums the contributions
@@ -228,42 +230,41 @@ __global__ void k_prep_scatter(LineIn in, Geometry G, PrepArgs pa, int nblk) {
   pa.cnu[base + dest] = st.nut;
 }
 
-// coarse[c] = first kept line with nu~0 >= origin + c (1 cm^-1 buckets, per
-// layer): each line fills the buckets between its predecessor's and its own
-__global__ void k_prep_coarse(int64_t n_lines, Geometry G, PrepArgs pa) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int L = blockIdx.y;
-  const int64_t kept = pa.kept[L];
-  const double* cnu = pa.cnu + (int64_t)L * n_lines;
-  int32_t* co = pa.coarse + (int64_t)L * (G.ncoarse + 1);
-  const int64_t nc = G.ncoarse;
-  if (i > kept) return;
-  int64_t prev = (i == 0) ? -1 : (int64_t)floor(cnu[i - 1] - G.bucket_origin);
-  int64_t cur = (i == kept) ? nc : (int64_t)floor(cnu[i] - G.bucket_origin);
-  if (cur > nc) cur = nc;
-  for (int64_t b = prev + 1; b <= cur; ++b) co[b] = (int32_t)i;
+// bucket[b] = first kept line with nu~0 >= v_b = origin + b / kBucketPerCm
+// (per layer; bucket[nbucket] = kept): thread i writes the buckets with
+// nu~0_(i-1) < v_b <= nu~0_i, found from floor((nu - origin) kBucketPerCm)
+// and settled by comparing with v_b itself, so every bucket is written once.
+__device__ __forceinline__ double bucket_value(const Geometry& G, int64_t b) {
+  return G.bucket_origin + (double)b / kBucketPerCm;
 }
-
-// bucket[b] = first kept line with nu~0 >= origin + b / kBucketPerCm: a short
-// binary search inside the bucket's 1 cm^-1 coarse bucket
 __global__ void k_prep_bucket(int64_t n_lines, Geometry G, PrepArgs pa) {
-  int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int L = blockIdx.y;
-  if (b > G.nbucket) return;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int L = blockIdx.y;
   const int64_t kept = pa.kept[L];
+  if (i > kept) return;
   const double* cnu = pa.cnu + (int64_t)L * n_lines;
-  const int32_t* co = pa.coarse + (int64_t)L * (G.ncoarse + 1);
   int32_t* bk = pa.bucket + (int64_t)L * (G.nbucket + 1);
-  if (b == G.nbucket) { bk[b] = (int32_t)kept; return; }
-  const int64_t c = b / kBucketPerCm;
-  int64_t lo = co[c < G.ncoarse ? c : G.ncoarse];
-  int64_t hi = co[c + 1 < G.ncoarse ? c + 1 : G.ncoarse];
-  const double v = G.bucket_origin + (double)b / kBucketPerCm;
-  while (lo < hi) {
-    const int64_t mid = (lo + hi) >> 1;
-    if (cnu[mid] < v) lo = mid + 1; else hi = mid;
+  const int64_t nb = G.nbucket;
+  // first bucket with v_b > nu~0_(i-1)
+  int64_t b0 = 0;
+  if (i > 0) {
+    const double lo = cnu[i - 1];
+    b0 = (int64_t)floor((lo - G.bucket_origin) * kBucketPerCm) + 1;
+    b0 = b0 < 0 ? 0 : (b0 > nb ? nb : b0);
+    while (b0 > 0 && bucket_value(G, b0 - 1) > lo) --b0;
+    while (b0 < nb && !(bucket_value(G, b0) > lo)) ++b0;
   }
-  bk[b] = (int32_t)lo;
+  // last bucket with v_b <= nu~0_i
+  int64_t b1 = nb - 1;
+  if (i < kept) {
+    const double hi = cnu[i];
+    b1 = (int64_t)floor((hi - G.bucket_origin) * kBucketPerCm);
+    b1 = b1 < -1 ? -1 : (b1 > nb - 1 ? nb - 1 : b1);
+    while (b1 + 1 < nb && bucket_value(G, b1 + 1) <= hi) ++b1;
+    while (b1 >= 0 && bucket_value(G, b1) > hi) --b1;
+  }
+  for (int64_t b = b0; b <= b1; ++b) bk[b] = (int32_t)i;
+  if (i == kept) bk[nb] = (int32_t)kept;
 }
 
 // Position of line i in the order of shifted centres nu~0 = nu0 + delta p
@@ -498,9 +499,7 @@ void launch_prep(const LineIn& in, const double* layers, int nL, const Geometry&
     if (pa.fp64) k_prep_scatter<double><<<grid, 256, 0, s>>>(in, G, pa, nblk);
     else k_prep_scatter<float><<<grid, 256, 0, s>>>(in, G, pa, nblk);
   }
-  dim3 gc((unsigned)((in.n + 1 + 255) / 256), nL);
-  k_prep_coarse<<<gc, 256, 0, s>>>(in.n, G, pa);
-  dim3 gb((unsigned)((G.nbucket + 1 + 255) / 256), nL);
+  dim3 gb((unsigned)((in.n + 1 + 255) / 256), nL);
   k_prep_bucket<<<gb, 256, 0, s>>>(in.n, G, pa);
   k_layer_scale<<<(nL + 255) / 256, 256, 0, s>>>(layers, pa.smax, nL, pa.out_kind, pa.scale);
 }

@@ -287,7 +287,6 @@ static void make_geometry(const marfa_request& rq, double nu_max, Geometry& G) {
   G.out_kind = rq.out_kind;
   G.fp64 = rq.fp64;
   G.nbucket = (int32_t)std::ceil((nu_max + 1.0) * kBucketPerCm) + 1;
-  G.ncoarse = (int32_t)std::ceil(nu_max + 1.0) + 1;
   // Eq.(10): 1.084 e^{-0.027|d|}, 0.208 e^{-0.016|d|}, 0.025 e^{-0.009|d|}
   const double l2e = 1.0 / std::log(2.0);
   G.chi_c0[0] = std::log2(1.084); G.chi_c1[0] = -0.027 * l2e;
@@ -564,7 +563,7 @@ static void free_plan(marfa_plan* p) {
     if (p->sgraph[i]) (void)hipGraphDestroy(p->sgraph[i]);
   }
   void* bufs[] = {p->d.nu0, p->d.S296, p->d.gair, p->d.gself, p->d.El, p->d.nair, p->d.dair, p->d.layers, p->d.lconst,
-                  p->d.smax, p->d.bcount, p->d.scount, p->d.kept, p->d.gcount, p->d.bucket, p->d.coarse, p->d.rec, p->d.cnu, p->d.csp,
+                  p->d.smax, p->d.bcount, p->d.scount, p->d.kept, p->d.gcount, p->d.bucket, p->d.rec, p->d.cnu, p->d.csp,
                   p->d.A, p->d.ivs, p->d.tiles, p->d.stiles, p->d.counter, p->d.scale, p->d.span, p->d.perm,
                   p->d.stats};
   for (void* b : bufs)
@@ -681,7 +680,6 @@ extern "C" marfa_status marfa_plan_create(marfa_plan** out, const marfa_lines* l
   ALLOC(p->d.kept, NL);
   ALLOC(p->d.gcount, NL * (kGroups + 1));
   ALLOC(p->d.bucket, NL * ((size_t)p->G.nbucket + 1));
-  ALLOC(p->d.coarse, NL * ((size_t)p->G.ncoarse + 1));
   {
     char* r = nullptr;
     ALLOC(r, NL * (size_t)n * recsz);
@@ -790,7 +788,6 @@ static void enqueue(marfa_plan* p, int first, int count, void* out, int64_t stri
   pa.kept = p->d.kept + F;
   pa.gcount = p->d.gcount + F * G12;
   pa.bucket = p->d.bucket + F * ((size_t)p->G.nbucket + 1);
-  pa.coarse = p->d.coarse + F * ((size_t)p->G.ncoarse + 1);
   pa.rec = (char*)p->d.rec + F * (size_t)n * recsz;
   pa.cnu = p->d.cnu + F * (size_t)n;
   pa.csp = (char*)p->d.csp + F * (size_t)n * realsz;
