@@ -92,18 +92,20 @@ __device__ __forceinline__ LineState line_state(const LineIn& in, int64_t j, con
 }
 
 __global__ void k_prep_smax(LineIn in, const double* __restrict__ lc, unsigned long long* smax) {
-  __shared__ double red[256];
+  __shared__ double wmax[4];
   int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
   int L = blockIdx.y;
   double S = 0.0;
   if (j < in.n) S = line_state(in, j, lc + kLayerConst * L).S;
-  red[threadIdx.x] = S;
+  // wavefront maximum by butterfly shuffles, then the block's four
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) S = fmax(S, __shfl_xor(S, o));
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = S;
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
-    __syncthreads();
+  if (threadIdx.x == 0) {
+    const double m = fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3]));
+    if (m > 0.0) atomicMax(&smax[L], (unsigned long long)__double_as_longlong(m));
   }
-  if (threadIdx.x == 0 && red[0] > 0.0) atomicMax(&smax[L], (unsigned long long)__double_as_longlong(red[0]));
 }
 
 __device__ __forceinline__ int start_level(double w, double R, const Geometry& G) {
@@ -152,13 +154,24 @@ __global__ void k_prep_count(LineIn in, Geometry G, PrepArgs pa, int nblk) {
 // lines per start level of each layer
 __global__ void k_prep_scan(PrepArgs pa, int nblk) {
   __shared__ int part[256];
+  __shared__ int gpart[kGroups + 1][256];
   int L = blockIdx.x;
   int t = threadIdx.x;
   int chunk = (nblk + 255) / 256;
   int b0 = t * chunk, b1 = min(nblk, b0 + chunk);
   int s = 0;
-  for (int b = b0; b < b1; ++b) s += pa.bcount[(int64_t)L * nblk + b];
+  int gs[kGroups + 1];
+#pragma unroll
+  for (int g = 0; g <= kGroups; ++g) gs[g] = 0;
+  for (int b = b0; b < b1; ++b) {
+    const int64_t k = (int64_t)L * nblk + b;
+    s += pa.bcount[k];
+#pragma unroll
+    for (int g = 0; g <= kGroups; ++g) gs[g] += pa.scount[k * (kGroups + 1) + g];
+  }
   part[t] = s;
+#pragma unroll
+  for (int g = 0; g <= kGroups; ++g) gpart[g][t] = gs[g];
   __syncthreads();
   for (int o = 1; o < 256; o <<= 1) {
     int v = (t >= o) ? part[t - o] : 0;
@@ -176,7 +189,7 @@ __global__ void k_prep_scan(PrepArgs pa, int nblk) {
   if (t == 255) pa.kept[L] = part[255];
   if (t <= kGroups) {
     int c = 0;
-    for (int b = 0; b < nblk; ++b) c += pa.scount[((int64_t)L * nblk + b) * (kGroups + 1) + t];
+    for (int k = 0; k < 256; ++k) c += gpart[t][k];
     pa.gcount[L * (kGroups + 1) + t] = c;
   }
 }
