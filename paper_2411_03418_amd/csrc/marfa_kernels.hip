@@ -25,7 +25,9 @@
 //                     each lane owns one level node and sums the contributions
 //                     of the lines in its windows (wave-uniform line loads)
 //   k_cascade         3-, 4- or 5-point interpolation from level l+1 into level l,
-//                     one thread per coarse cell with compile-time weights;
+//                     one thread per coarse cell with compile-time weights
+//                     (k_cascade_out: level 0 in single precision, four
+//                     aligned output nodes per thread);
 //                     the level-0 pass applies the layer scale and writes out.
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -405,6 +407,101 @@ __global__ void __launch_bounds__(256) k_cascade(Geometry G, int l, R* A, R* out
   }
 }
 
+// Value interpolated at fine node rem (0 .. 3) of a ratio-4 cell whose
+// window starts at c (only the entries the node's stencil uses are read).
+template <int NS, int REM>
+__device__ __forceinline__ float cascade_node4(const float* __restrict__ c) {
+  constexpr CascadeStencil<4, NS> S{};
+  constexpr int NW = kCascL<NS> + kCascR<NS> + 1;
+  if constexpr (REM == 0) {
+    return c[kCascL<NS>];
+  } else {
+    float v = 0.0f;
+#pragma unroll
+    for (int e = 0; e < NW; ++e)
+      if (S.used[REM][e]) v += float(S.w[REM][e]) * c[e];
+    return v;
+  }
+}
+
+// The four nodes of one aligned group: node k sits at REM = (PH + k) mod 4 of
+// cell qa + (PH + k) / 4.  Only the window entries some node uses are loaded.
+template <int NS, int PH>
+__device__ __forceinline__ void cascade_group4(const float* __restrict__ Ac, int64_t qa, float (&v)[4]) {
+  constexpr CascadeStencil<4, NS> S{};
+  constexpr int WL = kCascL<NS>, NW = kCascL<NS> + kCascR<NS> + 1;
+  float c[NW + 1];
+#pragma unroll
+  for (int e = 0; e <= NW; ++e) {
+    bool need = false;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int r = (PH + k) & 3, co = (PH + k) >> 2;
+      if (e - co >= 0 && e - co < NW) need = need || S.used[r][e - co];
+    }
+    c[e] = need ? Ac[qa - WL + e] : 0.0f;
+  }
+  v[0] = cascade_node4<NS, (PH + 0) & 3>(c + ((PH + 0) >> 2));
+  v[1] = cascade_node4<NS, (PH + 1) & 3>(c + ((PH + 1) >> 2));
+  v[2] = cascade_node4<NS, (PH + 2) & 3>(c + ((PH + 2) >> 2));
+  v[3] = cascade_node4<NS, (PH + 3) & 3>(c + ((PH + 3) >> 2));
+}
+
+// Level 0 of the single-precision cascade (ratio 4) with 16-byte output
+// accesses: thread t owns output nodes i0 + 4t .. i0 + 4t + 3, where i0 puts
+// the group on a 16-byte boundary of the layer's output row, so the phase
+// PH = (lo + i0) mod 4 of its nodes within their coarse cells is the same for
+// the whole layer and every weight is a constant.  Threads past the groups
+// take the (at most six) nodes before i0 and after the last group one each.
+template <int NS>
+__global__ void __launch_bounds__(256) k_cascade_out(Geometry G, const float* A, float* out, int64_t stride,
+                                                     const double* scale) {
+  const int layer = blockIdx.y;
+  const int64_t lo = G.lo[0], n = G.n[0];
+  float* row = out + (int64_t)layer * stride;
+  const int64_t i0 = (int64_t)((4 - (((uintptr_t)row >> 2) & 3)) & 3);
+  const int64_t ngrp = n > i0 ? (n - i0) / 4 : 0;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const float* Ac = A + (int64_t)layer * G.a_total + G.aoff[1] - G.lo[1];
+  const float sc = float(scale[layer]);
+  if (t < ngrp) {
+    const int64_t i = i0 + 4 * t;
+    const int64_t m = lo + i;   // level-0 nodes are at or above 0
+    float v[4];
+    switch ((int)(m & 3)) {
+      case 0: cascade_group4<NS, 0>(Ac, m >> 2, v); break;
+      case 1: cascade_group4<NS, 1>(Ac, m >> 2, v); break;
+      case 2: cascade_group4<NS, 2>(Ac, m >> 2, v); break;
+      default: cascade_group4<NS, 3>(Ac, m >> 2, v); break;
+    }
+    float4* o = reinterpret_cast<float4*>(row + i);
+    float4 w = *o;
+    w.x = sc * (w.x + v[0]);
+    w.y = sc * (w.y + v[1]);
+    w.z = sc * (w.z + v[2]);
+    w.w = sc * (w.w + v[3]);
+    *o = w;
+    return;
+  }
+  // single nodes: k = 0 .. 5 -> the head (k < i0) or the tail after the groups
+  const int64_t k = t - ngrp;
+  if (k >= 6) return;
+  const int64_t head = i0 < n ? i0 : n;
+  const int64_t i = k < 3 ? k : i0 + 4 * ngrp + (k - 3);
+  if (k < 3 ? i >= head : i >= n) return;
+  const int64_t m = lo + i;
+  constexpr int WL = kCascL<NS>;
+  const float* c = Ac + (m >> 2) - WL;
+  float v;
+  switch ((int)(m & 3)) {
+    case 0: v = cascade_node4<NS, 0>(c); break;
+    case 1: v = cascade_node4<NS, 1>(c); break;
+    case 2: v = cascade_node4<NS, 2>(c); break;
+    default: v = cascade_node4<NS, 3>(c); break;
+  }
+  row[i] = sc * (row[i] + v);
+}
+
 // K(x, y) through the hot-path shape code: a line with alpha_D = sqrt(ln 2)
 // (so x = d and y = gamma_L in cm^-1) and unit intensity has F = K / sqrt(pi)
 template <typename R>
@@ -571,6 +668,16 @@ static void launch_cascade_r(const Geometry& G, int nL, R* A, R* out, int64_t st
     const int64_t q_lo = G.lo[l] >= 0 ? G.lo[l] / rho : -((-G.lo[l] + rho - 1) / rho);
     const int64_t m_hi = G.lo[l] + G.n[l] - 1;
     const int64_t q_hi = m_hi >= 0 ? m_hi / rho : -((-m_hi + rho - 1) / rho);
+    if constexpr (sizeof(R) == 4) {
+      if (l == 0 && rho == 4 && G.lo[0] >= 0) {
+        // groups of four aligned output nodes plus up to six single ones
+        const dim3 g0((unsigned)((G.n[0] / 4 + 6 + 255) / 256), nL);
+        if (G.ns == 5) k_cascade_out<5><<<g0, 256, 0, s>>>(G, A, out, stride, scale);
+        else if (G.ns == 4) k_cascade_out<4><<<g0, 256, 0, s>>>(G, A, out, stride, scale);
+        else k_cascade_out<3><<<g0, 256, 0, s>>>(G, A, out, stride, scale);
+        continue;
+      }
+    }
     const dim3 grid((unsigned)((q_hi - q_lo + 1 + 255) / 256), nL);
     if (rho == 4) launch_cascade_level<R, 4>(G, l, grid, A, out, stride, scale, s);
     else launch_cascade_level<R, 2>(G, l, grid, A, out, stride, scale, s);
