@@ -93,12 +93,14 @@ __device__ __forceinline__ LineState line_state(const LineIn& in, int64_t j, con
   return s;
 }
 
+// Grid-stride over the layer's lines (a few dozen blocks per layer), so that
+// only that many atomics per layer meet on its maximum.
 __global__ void k_prep_smax(LineIn in, const double* __restrict__ lc, unsigned long long* smax) {
   __shared__ double wmax[4];
-  int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  int L = blockIdx.y;
+  const int L = blockIdx.y;
   double S = 0.0;
-  if (j < in.n) S = line_state(in, j, lc + kLayerConst * L).S;
+  for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < in.n; j += (int64_t)gridDim.x * 256)
+    S = fmax(S, line_state(in, j, lc + kLayerConst * L).S);
   // wavefront maximum by butterfly shuffles, then the block's four
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) S = fmax(S, __shfl_xor(S, o));
@@ -600,7 +602,7 @@ void launch_prep(const LineIn& in, const double* layers, int nL, const Geometry&
   k_layer_const<<<(nL + 63) / 64, 64, 0, s>>>(layers, nL, in.molar_mass, pa.lc);
   if (nblk > 0) {
     dim3 grid(nblk, nL);
-    k_prep_smax<<<grid, 256, 0, s>>>(in, pa.lc, pa.smax);
+    k_prep_smax<<<dim3(nblk < 64 ? nblk : 64, nL), 256, 0, s>>>(in, pa.lc, pa.smax);
     k_prep_count<<<grid, 256, 0, s>>>(in, G, pa, nblk);
   }
   k_prep_scan<<<nL, 256, 0, s>>>(pa, nblk);
