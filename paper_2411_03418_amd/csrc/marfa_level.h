@@ -223,7 +223,7 @@ __device__ float g_surr(float d, const LineRec32& L, const float* __restrict__ s
   const bool dom = y >= kMlpYMin && y <= kMlpYMax && fabsf(x) <= a.mlp_xmax;
   float f1, f2, f3;
   mlp_features(x, dom ? y : 1.0f, fabsf(dcm), a.mlp_inv_c, f1, f2, f3);
-  const float t = mlp_forward_wave(a.mlp, f1, f2, f3);
+  const float t = mlp_forward_wave<true>(a.mlp, f1, f2, f3);
   float v = L.A * 1.7724538509055160f * L.xs * L.xs * __builtin_amdgcn_rcpf(dom ? y : 1.0f) * mlp_base(x, y) *
             __expf(t);
   v = dom ? v : 0.0f;
@@ -275,7 +275,7 @@ __device__ __forceinline__ void surr_batch(float* q, int n, const LevelArgs& a) 
     mlp_features(x, y, ad, a.mlp_inv_c, f1, f2, f3);
     // a partial last batch runs only the 16-sample groups that hold entries
     const int ns = n - r >= 64 ? 4 : (n - r + 15) >> 4;
-    const float t = mlp_forward_wave(a.mlp, f1, f2, f3, ns);
+    const float t = mlp_forward_wave<true>(a.mlp, f1, f2, f3, ns);
     if (ok) q[i] = __builtin_amdgcn_rcpf(y) * mlp_base(x, y) * __expf(t);
   }
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -1156,18 +1156,19 @@ __device__ __forceinline__ void level_body(const Geometry& G, const LevelArgs& a
   R* lds_acc = reinterpret_cast<R*>(smem_raw);
   LevelArgs a = a_in;
   if constexpr (SURR) {
-    // the learned line shape's weights, staged once per workgroup
+    // the learned line shape's weights, staged once per workgroup in the
+    // scaled form that mlp_forward_wave<true> takes
     __shared__ float4 s_w0b[kMlpHid];
     __shared__ uint4 s_wp[kMlpHidLayers * 8 * 64];
     __shared__ float s_bh[kMlpHidLayers * kMlpHid];
     __shared__ float s_w4[kMlpHid];
     __shared__ float s_b4[1];
     for (int i = threadIdx.x; i < kMlpHid; i += 256) {
-      s_w0b[i] = a_in.mlp.w0b[i];
-      s_w4[i] = a_in.mlp.w4[i];
+      s_w0b[i] = mlp_scaled_w0b(a_in.mlp.w0b[i]);
+      s_w4[i] = mlp_scaled_w4(a_in.mlp.w4[i]);
     }
     for (int i = threadIdx.x; i < kMlpHidLayers * 8 * 64; i += 256) s_wp[i] = a_in.mlp.wp[i];
-    for (int i = threadIdx.x; i < kMlpHidLayers * kMlpHid; i += 256) s_bh[i] = a_in.mlp.bh[i];
+    for (int i = threadIdx.x; i < kMlpHidLayers * kMlpHid; i += 256) s_bh[i] = mlp_scaled_bh(a_in.mlp.bh[i]);
     if (threadIdx.x == 0) s_b4[0] = a_in.mlp.b4[0];
     __syncthreads();
     a.mlp.w0b = s_w0b;

@@ -171,9 +171,28 @@ __device__ __forceinline__ float mlp_base(float x, float y) {
 // Weights may live in global memory or LDS (generic pointers).  Only the
 // first 16 ns lanes' samples are evaluated (ns uniform, 1..4); the other
 // lanes receive 0.
+//
+// SCALED: the weights are in the scaled form of mlp_scaled_* (layer 0 and the
+// hidden biases times log2 e, the output weights times ln 2).  Every hidden
+// value then carries the factor log2 e, z' = z log2 e, and the activation is
+// h' = z' / (1 + 2^-z') = log2 e SiLU(z): one multiply fewer per value than
+// z / (1 + e^-z), the same network up to single-precision rounding.
+constexpr float kMlpLog2e = 1.44269504088896340736f;
+constexpr float kMlpLn2 = 0.693147180559945309417f;
+__device__ __forceinline__ float mlp_silu_scaled(float zs) {
+  return zs * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-zs));
+}
+__host__ __device__ __forceinline__ float4 mlp_scaled_w0b(float4 w) {
+  return make_float4(w.x * kMlpLog2e, w.y * kMlpLog2e, w.z * kMlpLog2e, w.w * kMlpLog2e);
+}
+__host__ __device__ __forceinline__ float mlp_scaled_bh(float b) { return b * kMlpLog2e; }
+__host__ __device__ __forceinline__ float mlp_scaled_w4(float w) { return w * kMlpLn2; }
+
+template <bool SCALED = false>
 __device__ __forceinline__ float mlp_forward_wave(const MlpDev& W, float f1, float f2, float f3, int ns = 4) {
   const int lane = threadIdx.x & 63;
   const int q = lane >> 4, col = lane & 15;
+  auto act = [](float z) { return SCALED ? mlp_silu_scaled(z) : mlp_silu(z); };
   float result = 0.0f;
 #pragma unroll 1
   for (int s = 0; s < ns; ++s) {
@@ -188,13 +207,13 @@ __device__ __forceinline__ float mlp_forward_wave(const MlpDev& W, float f1, flo
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const float4 w = W.w0b[16 * t + 4 * q + i];
-        h[t * 4 + i] = mlp_silu(fmaf(w.x, g1, fmaf(w.y, g2, fmaf(w.z, g3, w.w))));
+        h[t * 4 + i] = act(fmaf(w.x, g1, fmaf(w.y, g2, fmaf(w.z, g3, w.w))));
       }
 #pragma unroll 1
     for (int k = 0; k < kMlpHidLayers; ++k) {
       mlp_hidden<true>(W.wp + k * 8 * 64, W.bh + k * 64, h, z, lane);
 #pragma unroll
-      for (int v = 0; v < 16; ++v) h[v] = mlp_silu(z[v]);
+      for (int v = 0; v < 16; ++v) h[v] = act(z[v]);
     }
     float part = 0.0f;
 #pragma unroll
